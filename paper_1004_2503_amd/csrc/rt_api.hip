@@ -1,0 +1,456 @@
+// rt_api.hip -- host side of the C ABI declared in include/rt.h.
+//
+// The host only validates, drives and reads back (Appendix A: the host sends
+// the device one signal per step and never computes on the fields).  Every
+// argument check happens before the first HIP call, so invalid input is
+// rejected without touching the device.
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <vector>
+
+#include "rt_internal.h"
+
+using namespace rtk;
+
+namespace {
+
+constexpr double KB = 1.380649e-16;
+constexpr double EV = 1.602176634e-12;
+constexpr double E_ION_EV = 13.6;
+constexpr int MAX_NSUB = 4096;
+constexpr int ZC_DEFAULT = 32;
+
+struct Ev {
+    hipEvent_t a, b;
+};
+
+}  // namespace
+
+struct rt_ctx {
+    rt_params p;
+    rt_fields f;
+    hipStream_t stream = nullptr;
+    int cur = 0;
+    int ntx = 0, nty = 0, nzc = 0, zc = 0, nblocks = 0;
+    uint32_t ncell = 0;
+    int32_t *d_src_ptr = nullptr;
+    int32_t *d_src_key = nullptr;
+    float *d_src_rate = nullptr;
+    int64_t nsrc = 0;
+    double ndot_total = 0.0;
+    double *d_part = nullptr;
+    int npart = 0;
+    double *d_acc = nullptr;
+    double t = 0.0, emitted = 0.0, photons_initial = 0.0;
+    int64_t steps = 0;
+    int64_t hist_host[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    bool prof = false;
+    std::vector<Ev> ev;
+    size_t ev_used = 0;
+};
+
+static int check_params(const rt_params *p)
+{
+    if (!p) return RT_E_ARG;
+    if (p->nx < 1 || p->ny < 1 || p->nz < 1) return RT_E_ARG;
+    const double ncell = double(p->nx) * double(p->ny) * double(p->nz);
+    if (ncell >= 4294967296.0) return RT_E_ARG;
+    for (int f = 0; f < 6; ++f)
+        if (p->bc[f] < RT_BC_PERIODIC || p->bc[f] > RT_BC_REFLECT) return RT_E_ARG;
+    for (int d = 0; d < 3; ++d)
+        if ((p->bc[2 * d] == RT_BC_PERIODIC) != (p->bc[2 * d + 1] == RT_BC_PERIODIC))
+            return RT_E_ARG;
+    if (p->chem < RT_CHEM_FULL || p->chem > RT_CHEM_FROZEN) return RT_E_ARG;
+    if (p->prec != RT_PREC_FP32 && p->prec != RT_PREC_MIXED) return RT_E_ARG;
+    if (p->sub != RT_SUB_FIXED && p->sub != RT_SUB_ADAPTIVE) return RT_E_ARG;
+    if (p->reserved != 0) return RT_E_ARG;
+    if (!(p->dx_cm > 0.0) || !isfinite(p->dx_cm)) return RT_E_ARG;
+    if (!(p->c_cms > 0.0) || !isfinite(p->c_cms)) return RT_E_ARG;
+    if (!(p->sigma_n > 0.0) || !(p->sigma_e > 0.0) || !(p->egamma_eV > 0.0)) return RT_E_ARG;
+    if (!(p->T_floor >= 0.0) || !isfinite(p->T_floor)) return RT_E_ARG;
+    if (p->sub == RT_SUB_ADAPTIVE && !(p->sub_eps > 0.0 && p->sub_eps <= 1.0)) return RT_E_ARG;
+    if (!(p->xhi_fp64_thr >= 0.0 && p->xhi_fp64_thr <= 1.0)) return RT_E_ARG;
+    return RT_OK;
+}
+
+static int check_fields(const rt_fields *f)
+{
+    if (!f) return RT_E_ARG;
+    const void *ptrs[11] = {f->N[0], f->N[1], f->Fx[0], f->Fx[1], f->Fy[0], f->Fy[1],
+                            f->Fz[0], f->Fz[1], f->xHI, f->T, f->nH};
+    for (int i = 0; i < 11; ++i) {
+        if (!ptrs[i]) return RT_E_ARG;
+        for (int j = 0; j < i; ++j)
+            if (ptrs[i] == ptrs[j]) return RT_E_ARG;
+    }
+    return RT_OK;
+}
+
+static void free_ctx(rt_ctx *c)
+{
+    if (!c) return;
+    if (c->d_src_ptr) (void)hipFree(c->d_src_ptr);
+    if (c->d_src_key) (void)hipFree(c->d_src_key);
+    if (c->d_src_rate) (void)hipFree(c->d_src_rate);
+    if (c->d_part) (void)hipFree(c->d_part);
+    if (c->d_acc) (void)hipFree(c->d_acc);
+    for (auto &e : c->ev) {
+        (void)hipEventDestroy(e.a);
+        (void)hipEventDestroy(e.b);
+    }
+    delete c;
+}
+
+extern "C" const char *rt_strerror(int code)
+{
+    switch (code) {
+    case RT_OK: return "ok";
+    case RT_E_ARG: return "invalid argument";
+    case RT_E_CFL: return "time step above the light-crossing bound dx/(3c)";
+    case RT_E_STATE: return "invalid call order or null context";
+    case RT_E_HIP: return "HIP runtime failure";
+    case RT_E_NONFINITE: return "a step produced a non-finite value";
+    case RT_E_NOMEM: return "device allocation failed";
+    default: return "unknown error";
+    }
+}
+
+extern "C" int rt_init(const rt_params *params, const rt_fields *fields, void *hip_stream,
+                       rt_ctx **out)
+{
+    if (!out) return RT_E_ARG;
+    *out = nullptr;
+    int rc = check_params(params);
+    if (rc != RT_OK) return rc;
+    rc = check_fields(fields);
+    if (rc != RT_OK) return rc;
+
+    rt_ctx *c = new (std::nothrow) rt_ctx();
+    if (!c) return RT_E_NOMEM;
+    c->p = *params;
+    c->f = *fields;
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    c->ncell = uint32_t(params->nx) * uint32_t(params->ny) * uint32_t(params->nz);
+    c->zc = std::min(ZC_DEFAULT, params->nz);
+    c->ntx = (params->nx + TX - 1) / TX;
+    c->nty = (params->ny + TY - 1) / TY;
+    c->nzc = (params->nz + c->zc - 1) / c->zc;
+    const int64_t nb = int64_t(c->ntx) * c->nty * c->nzc;
+    if (nb > (int64_t(1) << 30)) {
+        delete c;
+        return RT_E_ARG;
+    }
+    c->nblocks = int(nb);
+    c->npart = std::max(c->nblocks, state_sums_blocks(c->ncell));
+
+    if (hipMalloc(&c->d_part, size_t(c->npart) * NRED * sizeof(double)) != hipSuccess ||
+        hipMalloc(&c->d_acc, ACC_SIZE * sizeof(double)) != hipSuccess ||
+        hipMalloc(&c->d_src_ptr, size_t(c->nblocks + 1) * sizeof(int32_t)) != hipSuccess) {
+        (void)hipGetLastError();
+        free_ctx(c);
+        return RT_E_NOMEM;
+    }
+    if (hipMemsetAsync(c->d_src_ptr, 0, size_t(c->nblocks + 1) * sizeof(int32_t), c->stream) !=
+            hipSuccess ||
+        hipMemsetAsync(c->d_acc, 0, ACC_SIZE * sizeof(double), c->stream) != hipSuccess) {
+        free_ctx(c);
+        return RT_E_HIP;
+    }
+    // sums of the initial state (photons_initial and the averages before
+    // any step)
+    const int nsb = state_sums_blocks(c->ncell);
+    if (launch_state_sums(fields->N[0], fields->xHI, fields->nH, c->ncell, c->d_part, nsb,
+                          c->stream) != hipSuccess ||
+        launch_finalize(c->d_part, nsb, c->d_acc, 1, c->stream) != hipSuccess) {
+        free_ctx(c);
+        return RT_E_HIP;
+    }
+    double acc[ACC_SIZE];
+    if (hipMemcpyAsync(acc, c->d_acc, sizeof(acc), hipMemcpyDeviceToHost, c->stream) !=
+            hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess) {
+        free_ctx(c);
+        return RT_E_HIP;
+    }
+    const double vol = params->dx_cm * params->dx_cm * params->dx_cm;
+    c->photons_initial = acc[ACC_CUR + R_N] * vol;
+    *out = c;
+    return RT_OK;
+}
+
+extern "C" int rt_inject_sources(rt_ctx *c, int64_t n, const int32_t *ijk, const double *ndot)
+{
+    if (!c) return RT_E_STATE;
+    if (n < 0 || n > (int64_t(1) << 31) - 1) return RT_E_ARG;
+    if (n > 0 && (!ijk || !ndot)) return RT_E_ARG;
+    const rt_params &p = c->p;
+    struct Src {
+        int32_t tile, key;
+        double ndot;
+    };
+    std::vector<Src> v;
+    v.reserve(size_t(n));
+    double total = 0.0;
+    for (int64_t s = 0; s < n; ++s) {
+        const int32_t i = ijk[3 * s], j = ijk[3 * s + 1], k = ijk[3 * s + 2];
+        const double q = ndot[s];
+        if (i < 0 || i >= p.nx || j < 0 || j >= p.ny || k < 0 || k >= p.nz) return RT_E_ARG;
+        if (!(q >= 0.0) || !isfinite(q)) return RT_E_ARG;
+        const int itx = i / TX, ity = j / TY, izc = k / c->zc;
+        const int tile = (izc * c->nty + ity) * c->ntx + itx;
+        const int key = (k - izc * c->zc) * NTHREADS + (j - ity * TY) * TX + (i - itx * TX);
+        v.push_back({tile, key, q});
+        total += q;
+    }
+    std::sort(v.begin(), v.end(), [](const Src &a, const Src &b) {
+        return a.tile != b.tile ? a.tile < b.tile : a.key < b.key;
+    });
+    // merge duplicate cells (nearest-grid-point projection sums them)
+    std::vector<int32_t> key, ptr(size_t(c->nblocks) + 1, 0);
+    std::vector<float> rate;
+    std::vector<double> acc;
+    std::vector<int32_t> tiles;
+    for (size_t s = 0; s < v.size(); ++s) {
+        if (!key.empty() && tiles.back() == v[s].tile && key.back() == v[s].key) {
+            acc.back() += v[s].ndot;
+        } else {
+            tiles.push_back(v[s].tile);
+            key.push_back(v[s].key);
+            acc.push_back(v[s].ndot);
+        }
+    }
+    const double vol = p.dx_cm * p.dx_cm * p.dx_cm;
+    rate.resize(acc.size());
+    for (size_t s = 0; s < acc.size(); ++s) rate[s] = float(acc[s] / vol);
+    for (size_t s = 0; s < tiles.size(); ++s) ptr[size_t(tiles[s]) + 1] += 1;
+    for (int b = 0; b < c->nblocks; ++b) ptr[size_t(b) + 1] += ptr[size_t(b)];
+
+    // allocate the new lists first so that a failure leaves the old set intact
+    const size_t m = std::max<size_t>(key.size(), 1);
+    int32_t *nkey = nullptr;
+    float *nrate = nullptr;
+    if (hipMalloc(&nkey, m * sizeof(int32_t)) != hipSuccess ||
+        hipMalloc(&nrate, m * sizeof(float)) != hipSuccess) {
+        (void)hipGetLastError();
+        if (nkey) (void)hipFree(nkey);
+        return RT_E_NOMEM;
+    }
+    if (!key.empty() &&
+        (hipMemcpy(nkey, key.data(), key.size() * sizeof(int32_t), hipMemcpyHostToDevice) !=
+             hipSuccess ||
+         hipMemcpy(nrate, rate.data(), rate.size() * sizeof(float), hipMemcpyHostToDevice) !=
+             hipSuccess)) {
+        (void)hipFree(nkey);
+        (void)hipFree(nrate);
+        return RT_E_HIP;
+    }
+    // the stream may still read the old lists
+    if (hipStreamSynchronize(c->stream) != hipSuccess ||
+        hipMemcpy(c->d_src_ptr, ptr.data(), ptr.size() * sizeof(int32_t),
+                  hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(nkey);
+        (void)hipFree(nrate);
+        return RT_E_HIP;
+    }
+    if (c->d_src_key) (void)hipFree(c->d_src_key);
+    if (c->d_src_rate) (void)hipFree(c->d_src_rate);
+    c->d_src_key = nkey;
+    c->d_src_rate = nrate;
+    c->nsrc = int64_t(key.size());
+    c->ndot_total = total;
+    return RT_OK;
+}
+
+static void fill_args(const rt_ctx *c, double dt, int nsub, StepArgs &a)
+{
+    const rt_params &p = c->p;
+    const int cur = c->cur, nxt = 1 - c->cur;
+    a.N = c->f.N[cur];
+    a.Fx = c->f.Fx[cur];
+    a.Fy = c->f.Fy[cur];
+    a.Fz = c->f.Fz[cur];
+    a.No = c->f.N[nxt];
+    a.Fxo = c->f.Fx[nxt];
+    a.Fyo = c->f.Fy[nxt];
+    a.Fzo = c->f.Fz[nxt];
+    a.xHI = c->f.xHI;
+    a.T = c->f.T;
+    a.nH = c->f.nH;
+    a.src_ptr = c->d_src_ptr;
+    a.src_key = c->d_src_key;
+    a.src_rate = c->d_src_rate;
+    a.partials = c->d_part;
+    a.nx = p.nx;
+    a.ny = p.ny;
+    a.nz = p.nz;
+    a.plane = uint32_t(p.nx) * uint32_t(p.ny);
+    a.ntx = c->ntx;
+    a.nty = c->nty;
+    a.nzc = c->nzc;
+    a.zc = c->zc;
+    a.nblocks = c->nblocks;
+    for (int f = 0; f < 6; ++f) a.bc[f] = p.bc[f];
+    a.chem = p.chem;
+    a.mixed = p.prec == RT_PREC_MIXED;
+    a.adaptive = p.sub == RT_SUB_ADAPTIVE;
+    a.nsub = nsub;
+    const double c_ = p.c_cms;
+    const double eheat = (p.sigma_e * p.egamma_eV / p.sigma_n - E_ION_EV) * EV;
+    const double T_h = eheat / (1.5 * KB);
+    a.c = float(c_);
+    a.inv_c = float(1.0 / c_);
+    a.half_c = float(0.5 * c_);
+    a.half_c2 = float(0.5 * c_ * c_);
+    a.k1 = float(dt / p.dx_cm);
+    a.dt = float(dt);
+    a.csig = float(c_ * p.sigma_n);
+    a.T_h = float(T_h);
+    a.inv15kB = float(1.0 / (1.5 * KB));
+    a.T_floor = float(p.T_floor);
+    a.sub_eps = float(p.sub_eps);
+    a.xhi_thr = float(p.xhi_fp64_thr);
+    a.dt_d = dt;
+    a.csig_d = c_ * p.sigma_n;
+    a.T_h_d = T_h;
+    a.T_floor_d = p.T_floor;
+    a.sub_eps_d = p.sub_eps;
+    a.vol = p.dx_cm * p.dx_cm * p.dx_cm;
+    a.esc_scale = dt * p.dx_cm * p.dx_cm;
+}
+
+extern "C" int rt_step(rt_ctx *c, double dt, int32_t nsub)
+{
+    if (!c) return RT_E_STATE;
+    if (!(dt > 0.0) || !isfinite(dt)) return RT_E_ARG;
+    if (nsub < 1 || nsub > MAX_NSUB) return RT_E_ARG;
+    const double dtmax = c->p.dx_cm / (3.0 * c->p.c_cms);
+    if (dt > dtmax * (1.0 + 1e-12)) return RT_E_CFL;
+
+    StepArgs a;
+    fill_args(c, dt, nsub, a);
+    Ev *e = nullptr;
+    if (c->prof) {
+        if (c->ev_used == c->ev.size()) {
+            Ev n;
+            if (hipEventCreate(&n.a) != hipSuccess) return RT_E_HIP;
+            if (hipEventCreate(&n.b) != hipSuccess) return RT_E_HIP;
+            c->ev.push_back(n);
+        }
+        e = &c->ev[c->ev_used++];
+        if (hipEventRecord(e->a, c->stream) != hipSuccess) return RT_E_HIP;
+    }
+    if (launch_step(a, c->stream) != hipSuccess) return RT_E_HIP;
+    if (e && hipEventRecord(e->b, c->stream) != hipSuccess) return RT_E_HIP;
+    if (launch_finalize(c->d_part, c->nblocks, c->d_acc, 0, c->stream) != hipSuccess)
+        return RT_E_HIP;
+    c->cur = 1 - c->cur;
+    c->t += dt;
+    c->emitted += dt * c->ndot_total;
+    c->steps += 1;
+    if (c->p.sub == RT_SUB_FIXED && c->p.chem != RT_CHEM_OFF) {
+        int b = 0;
+        while (b < 7 && (2 << b) <= nsub) ++b;
+        c->hist_host[b] += int64_t(c->ncell);
+    }
+    return RT_OK;
+}
+
+extern "C" int rt_reduce(rt_ctx *c, rt_reductions *out)
+{
+    if (!c) return RT_E_STATE;
+    if (!out) return RT_E_ARG;
+    double acc[ACC_SIZE];
+    if (hipMemcpyAsync(acc, c->d_acc, sizeof(acc), hipMemcpyDeviceToHost, c->stream) !=
+            hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess)
+        return RT_E_HIP;
+    const rt_params &p = c->p;
+    const double vol = p.dx_cm * p.dx_cm * p.dx_cm;
+    const double ncell = double(c->ncell);
+    memset(out, 0, sizeof(*out));
+    out->t = c->t;
+    out->xhi_vol = acc[ACC_CUR + R_XHI] / ncell;
+    out->xhi_mass = acc[ACC_CUR + R_NHXHI] / acc[ACC_CUR + R_NH];
+    out->gamma_vol = p.c_cms * p.sigma_n * acc[ACC_CUR + R_N] / ncell;
+    out->photons_initial = c->photons_initial;
+    out->photons_emitted = c->emitted;
+    out->photons_stored = acc[ACC_CUR + R_N] * vol;
+    out->photons_absorbed = acc[ACC_CUM + R_ABS];
+    out->photons_escaped = acc[ACC_CUM + R_ESC];
+    out->photons_floor = acc[ACC_CUM + R_FLOOR];
+    out->steps = c->steps;
+    out->n_nonfinite = int64_t(acc[ACC_CUM + R_NONFINITE]);
+    out->n_fp64 = int64_t(acc[ACC_CUM + R_FP64]);
+    out->n_fallback = int64_t(acc[ACC_CUM + R_FALLBACK]);
+    for (int b = 0; b < 8; ++b)
+        out->subcycle_hist[b] = c->hist_host[b] + int64_t(acc[ACC_CUM + R_HIST0 + b]);
+    return out->n_nonfinite > 0 ? RT_E_NONFINITE : RT_OK;
+}
+
+extern "C" int rt_state(rt_ctx *c, int32_t field, void *dst, int32_t dst_on_device)
+{
+    if (!c) return RT_E_STATE;
+    if (!dst) return RT_E_ARG;
+    const void *src = nullptr;
+    switch (field) {
+    case RT_FIELD_N: src = c->f.N[c->cur]; break;
+    case RT_FIELD_FX: src = c->f.Fx[c->cur]; break;
+    case RT_FIELD_FY: src = c->f.Fy[c->cur]; break;
+    case RT_FIELD_FZ: src = c->f.Fz[c->cur]; break;
+    case RT_FIELD_XHI: src = c->f.xHI; break;
+    case RT_FIELD_T: src = c->f.T; break;
+    case RT_FIELD_NH: src = c->f.nH; break;
+    default: return RT_E_ARG;
+    }
+    const size_t bytes = size_t(c->ncell) * sizeof(float);
+    const hipMemcpyKind kind = dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    if (hipMemcpyAsync(dst, src, bytes, kind, c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess)
+        return RT_E_HIP;
+    return RT_OK;
+}
+
+extern "C" int rt_current(rt_ctx *c, int32_t *index)
+{
+    if (!c) return RT_E_STATE;
+    if (!index) return RT_E_ARG;
+    *index = c->cur;
+    return RT_OK;
+}
+
+extern "C" int rt_profile(rt_ctx *c, int32_t enable)
+{
+    if (!c) return RT_E_STATE;
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return RT_E_HIP;
+    c->prof = enable != 0;
+    c->ev_used = 0;
+    return RT_OK;
+}
+
+extern "C" int rt_profile_read(rt_ctx *c, double *ms_total, int64_t *launches)
+{
+    if (!c) return RT_E_STATE;
+    if (!ms_total || !launches) return RT_E_ARG;
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return RT_E_HIP;
+    double tot = 0.0;
+    for (size_t i = 0; i < c->ev_used; ++i) {
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, c->ev[i].a, c->ev[i].b) != hipSuccess) return RT_E_HIP;
+        tot += ms;
+    }
+    *ms_total = tot;
+    *launches = int64_t(c->ev_used);
+    return RT_OK;
+}
+
+extern "C" int rt_destroy(rt_ctx *c)
+{
+    if (!c) return RT_E_STATE;
+    (void)hipStreamSynchronize(c->stream);
+    free_ctx(c);
+    return RT_OK;
+}

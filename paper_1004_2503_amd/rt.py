@@ -1,0 +1,277 @@
+"""ctypes binding of librt_m1.so (include/rt.h).
+
+Argument marshalling only: every step of the method runs in the library's
+HIP kernels.  The functions carry the C names (rt_init, rt_inject_sources,
+rt_step, rt_reduce, rt_state, rt_current, rt_profile, rt_profile_read,
+rt_destroy, rt_strerror); ``RTGrid`` is a convenience owner of the torch
+device tensors that the library borrows.  Loading fails loudly if the library
+has not been built.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librt_m1.so")
+
+RT_OK, RT_E_ARG, RT_E_CFL, RT_E_STATE, RT_E_HIP, RT_E_NONFINITE, RT_E_NOMEM = (
+    0, -1, -2, -3, -4, -5, -6)
+BC_PERIODIC, BC_OUTFLOW, BC_REFLECT = 0, 1, 2
+CHEM_FULL, CHEM_ISOTHERMAL, CHEM_OFF, CHEM_FROZEN = 0, 1, 2, 3
+PREC_FP32, PREC_MIXED = 0, 1
+SUB_FIXED, SUB_ADAPTIVE = 0, 1
+FIELD_N, FIELD_FX, FIELD_FY, FIELD_FZ, FIELD_XHI, FIELD_T, FIELD_NH = range(7)
+
+SIGMA_N = 2.93e-18
+SIGMA_E = 2.49e-18
+EGAMMA_EV = 20.27
+C_LIGHT = 2.99792458e10
+
+_fp = ctypes.c_void_p
+
+
+class rt_fields(ctypes.Structure):
+    _fields_ = [("N", _fp * 2), ("Fx", _fp * 2), ("Fy", _fp * 2), ("Fz", _fp * 2),
+                ("xHI", _fp), ("T", _fp), ("nH", _fp)]
+
+
+class rt_params(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("bc", ctypes.c_int32 * 6), ("chem", ctypes.c_int32),
+                ("prec", ctypes.c_int32), ("sub", ctypes.c_int32),
+                ("reserved", ctypes.c_int32),
+                ("dx_cm", ctypes.c_double), ("c_cms", ctypes.c_double),
+                ("sigma_n", ctypes.c_double), ("sigma_e", ctypes.c_double),
+                ("egamma_eV", ctypes.c_double), ("T_floor", ctypes.c_double),
+                ("sub_eps", ctypes.c_double), ("xhi_fp64_thr", ctypes.c_double)]
+
+
+class rt_reductions(ctypes.Structure):
+    _fields_ = [("t", ctypes.c_double), ("xhi_vol", ctypes.c_double),
+                ("xhi_mass", ctypes.c_double), ("gamma_vol", ctypes.c_double),
+                ("photons_initial", ctypes.c_double), ("photons_emitted", ctypes.c_double),
+                ("photons_stored", ctypes.c_double), ("photons_absorbed", ctypes.c_double),
+                ("photons_escaped", ctypes.c_double), ("photons_floor", ctypes.c_double),
+                ("steps", ctypes.c_int64), ("n_nonfinite", ctypes.c_int64),
+                ("n_fp64", ctypes.c_int64), ("n_fallback", ctypes.c_int64),
+                ("subcycle_hist", ctypes.c_int64 * 8)]
+
+    def as_dict(self) -> dict:
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "subcycle_hist"}
+        d["subcycle_hist"] = list(self.subcycle_hist)
+        return d
+
+
+EXPORTS = ["rt_init", "rt_inject_sources", "rt_step", "rt_reduce", "rt_state",
+           "rt_current", "rt_profile", "rt_profile_read", "rt_destroy", "rt_strerror"]
+
+_lib = None
+
+
+class RTError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        super().__init__(f"{what}: {rt_strerror(code)} ({code})")
+        self.code = code
+
+
+def lib():
+    """Load librt_m1.so; raises if it has not been built (no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_1004_2503_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        P = ctypes.POINTER
+        vp = ctypes.c_void_p
+        L.rt_init.argtypes = [P(rt_params), P(rt_fields), vp, P(vp)]
+        L.rt_inject_sources.argtypes = [vp, ctypes.c_int64, P(ctypes.c_int32),
+                                        P(ctypes.c_double)]
+        L.rt_step.argtypes = [vp, ctypes.c_double, ctypes.c_int32]
+        L.rt_reduce.argtypes = [vp, P(rt_reductions)]
+        L.rt_state.argtypes = [vp, ctypes.c_int32, vp, ctypes.c_int32]
+        L.rt_current.argtypes = [vp, P(ctypes.c_int32)]
+        L.rt_profile.argtypes = [vp, ctypes.c_int32]
+        L.rt_profile_read.argtypes = [vp, P(ctypes.c_double), P(ctypes.c_int64)]
+        L.rt_destroy.argtypes = [vp]
+        L.rt_strerror.argtypes = [ctypes.c_int]
+        L.rt_strerror.restype = ctypes.c_char_p
+        for name in EXPORTS:
+            if name != "rt_strerror":
+                getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+# ------------------------------------------------------------ C names
+def rt_strerror(code: int) -> str:
+    return lib().rt_strerror(int(code)).decode()
+
+
+def rt_init(params: rt_params, fields: rt_fields, stream: int | None):
+    """Returns (code, ctx handle)."""
+    ctx = ctypes.c_void_p()
+    rc = lib().rt_init(ctypes.byref(params), ctypes.byref(fields),
+                       ctypes.c_void_p(stream or 0), ctypes.byref(ctx))
+    return rc, ctx
+
+
+def rt_inject_sources(ctx, ijk, ndot) -> int:
+    ijk = np.ascontiguousarray(np.asarray(ijk, dtype=np.int32).reshape(-1, 3))
+    ndot = np.ascontiguousarray(np.asarray(ndot, dtype=np.float64).reshape(-1))
+    if len(ijk) != len(ndot):
+        return RT_E_ARG
+    return lib().rt_inject_sources(
+        ctx, len(ndot), ijk.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+        ndot.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+
+
+def rt_step(ctx, dt: float, nsub: int) -> int:
+    return lib().rt_step(ctx, float(dt), int(nsub))
+
+
+def rt_reduce(ctx):
+    out = rt_reductions()
+    rc = lib().rt_reduce(ctx, ctypes.byref(out))
+    return rc, out
+
+
+def rt_state(ctx, field: int, dst_ptr: int, on_device: bool) -> int:
+    return lib().rt_state(ctx, int(field), ctypes.c_void_p(dst_ptr), int(bool(on_device)))
+
+
+def rt_current(ctx):
+    idx = ctypes.c_int32()
+    rc = lib().rt_current(ctx, ctypes.byref(idx))
+    return rc, idx.value
+
+
+def rt_profile(ctx, enable: bool) -> int:
+    return lib().rt_profile(ctx, int(bool(enable)))
+
+
+def rt_profile_read(ctx):
+    ms = ctypes.c_double()
+    n = ctypes.c_int64()
+    rc = lib().rt_profile_read(ctx, ctypes.byref(ms), ctypes.byref(n))
+    return rc, ms.value, n.value
+
+
+def rt_destroy(ctx) -> int:
+    return lib().rt_destroy(ctx)
+
+
+def check(rc: int, what: str):
+    if rc != RT_OK:
+        raise RTError(rc, what)
+
+
+def make_params(shape, dx, bc=(BC_PERIODIC,) * 6, chem=CHEM_FULL, prec=PREC_FP32,
+                sub=SUB_FIXED, c=C_LIGHT, T_floor=10.0, sub_eps=0.1,
+                xhi_fp64_thr=1e-3) -> rt_params:
+    """``shape`` is (nz, ny, nx), the torch/numpy order of every field."""
+    nz, ny, nx = shape
+    return rt_params(nx, ny, nz, (ctypes.c_int32 * 6)(*bc), chem, prec, sub, 0,
+                     float(dx), float(c), SIGMA_N, SIGMA_E, EGAMMA_EV, float(T_floor),
+                     float(sub_eps), float(xhi_fp64_thr))
+
+
+class RTGrid:
+    """Torch-owned device fields bound to one library context.
+
+    ``state`` is a dict of (nz, ny, nx) arrays or tensors: N, Fx, Fy, Fz,
+    xHI, T, nH (missing N/F start at zero)."""
+
+    def __init__(self, params: rt_params, state: dict, device="cuda", stream=None):
+        import torch
+
+        self.torch = torch
+        self.params = params
+        shape = (params.nz, params.ny, params.nx)
+        self.shape = shape
+        self.device = torch.device(device)
+
+        def dev(name, fill=0.0):
+            v = state.get(name)
+            if v is None:
+                return torch.full(shape, fill, dtype=torch.float32, device=self.device)
+            t = torch.as_tensor(v)
+            return t.to(device=self.device, dtype=torch.float32).reshape(shape).contiguous().clone()
+
+        self.N = [dev("N"), torch.zeros(shape, dtype=torch.float32, device=self.device)]
+        self.Fx = [dev("Fx"), torch.zeros_like(self.N[1])]
+        self.Fy = [dev("Fy"), torch.zeros_like(self.N[1])]
+        self.Fz = [dev("Fz"), torch.zeros_like(self.N[1])]
+        self.xHI = dev("xHI", 1.0)
+        self.T = dev("T", 1e4)
+        self.nH = dev("nH", 1e-3)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        f = rt_fields()
+        f.N[0], f.N[1] = self.N[0].data_ptr(), self.N[1].data_ptr()
+        f.Fx[0], f.Fx[1] = self.Fx[0].data_ptr(), self.Fx[1].data_ptr()
+        f.Fy[0], f.Fy[1] = self.Fy[0].data_ptr(), self.Fy[1].data_ptr()
+        f.Fz[0], f.Fz[1] = self.Fz[0].data_ptr(), self.Fz[1].data_ptr()
+        f.xHI, f.T, f.nH = self.xHI.data_ptr(), self.T.data_ptr(), self.nH.data_ptr()
+        self.fields = f
+        torch.cuda.synchronize(self.device)
+        rc, self.ctx = rt_init(params, f, self.stream.cuda_stream)
+        check(rc, "rt_init")
+
+    def inject_sources(self, ijk, ndot):
+        check(rt_inject_sources(self.ctx, ijk, ndot), "rt_inject_sources")
+
+    def step(self, dt, nsub=1, nsteps=1):
+        for _ in range(int(nsteps)):
+            check(rt_step(self.ctx, dt, nsub), "rt_step")
+
+    def reduce(self, allow_nonfinite=False) -> dict:
+        rc, out = rt_reduce(self.ctx)
+        if not (rc == RT_OK or (allow_nonfinite and rc == RT_E_NONFINITE)):
+            raise RTError(rc, "rt_reduce")
+        return out.as_dict()
+
+    def current(self) -> int:
+        rc, idx = rt_current(self.ctx)
+        check(rc, "rt_current")
+        return idx
+
+    def tensors(self) -> dict:
+        """Current-state device tensors (views, no copy); waits for the stream."""
+        self.stream.synchronize()
+        c = self.current()
+        return dict(N=self.N[c], Fx=self.Fx[c], Fy=self.Fy[c], Fz=self.Fz[c],
+                    xHI=self.xHI, T=self.T, nH=self.nH)
+
+    def state_numpy(self) -> dict:
+        """Current state copied to host through rt_state."""
+        out = {}
+        for name, fid in (("N", FIELD_N), ("Fx", FIELD_FX), ("Fy", FIELD_FY),
+                          ("Fz", FIELD_FZ), ("xHI", FIELD_XHI), ("T", FIELD_T),
+                          ("nH", FIELD_NH)):
+            a = np.empty(self.shape, np.float32)
+            check(rt_state(self.ctx, fid, a.ctypes.data, False), "rt_state")
+            out[name] = a
+        return out
+
+    def profile(self, enable: bool):
+        check(rt_profile(self.ctx, enable), "rt_profile")
+
+    def profile_read(self):
+        rc, ms, n = rt_profile_read(self.ctx)
+        check(rc, "rt_profile_read")
+        return ms, n
+
+    def close(self):
+        if self.ctx is not None and self.ctx.value:
+            check(rt_destroy(self.ctx), "rt_destroy")
+        self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -165,6 +165,22 @@ int rt_inject_sources(rt_ctx *ctx, int64_t n, const int32_t *ijk,
  * RT_E_CFL otherwise); 1 <= nsub <= 4096.  Asynchronous. */
 int rt_step(rt_ctx *ctx, double dt, int32_t nsub);
 
+/* Switch the learned chemistry on (theta != NULL) or off (theta == NULL).
+ * Not part of the paper's method.  theta: device, RT_MLP_NPARAM FP32 network
+ * parameters (copied into the context's own packed bf16 operands, so the
+ * caller may free it afterwards).  norm: host float[24] = mu_in[5],
+ * sd_in[5], mu_out[2], sd_out[2] (standardisation of the log10 features nH,
+ * xHI, T, N, dt and targets xHI', T') and in_min[5], in_max[5] (the training
+ * range of the raw log10 features).  With it on and chem == RT_CHEM_FULL,
+ * rt_step evaluates the network on the matrix cores for every cell, derives
+ * the absorbed photons from the predicted (xHI', T') (net ionisations +
+ * recombinations - collisional ionisations) so the photon budget stays
+ * exact, and runs the exact Phi instead for any cell whose inputs leave the
+ * training range, whose prediction leaves the physical bounds, or whose
+ * backward-Euler residual over dt exceeds residual_tol (counted in
+ * rt_reductions.n_fallback).  RT_E_ARG for non-positive scales or tol. */
+int rt_set_surrogate(rt_ctx *ctx, const float *theta, const float *norm, double residual_tol);
+
 /* Wait for the stream and report the sums of the last step (or of the
  * initial state before any step) and the cumulative tallies.  Returns
  * RT_E_NONFINITE (with *out filled) if any step produced a non-finite
@@ -189,6 +205,52 @@ int rt_profile_read(rt_ctx *ctx, double *ms_total, int64_t *launches);
 
 /* Release the context and its scratch (never the caller's fields). */
 int rt_destroy(rt_ctx *ctx);
+
+/* ---- exact chemistry on a batch of independent cells ------------------- */
+
+/* Apply the per-cell operator Phi (Appendix A; the sub-cycled hydrogen
+ * chemistry and cooling of Sec. 2.2) to n independent cells, in place, on
+ * `hip_stream`, exactly as rt_step applies it after transport: nH, N, xHI,
+ * T and dt are device arrays of n floats (dt per cell, seconds); N, xHI and
+ * T are updated; ncycles (device int32[n], may be NULL) receives the number
+ * of sub-cycles each cell took.  Only the chemistry fields of `params` are
+ * read (chem, prec, sub, sub_eps, T_floor, xhi_fp64_thr, c_cms, sigma_n,
+ * sigma_e, egamma_eV); grid sizes and boundaries are ignored.  Used to
+ * produce training pairs for the surrogate.  Asynchronous. */
+int rt_chem_apply(const rt_params *params, int64_t n, const float *nH, float *N,
+                  float *xHI, float *T, const float *dt, int32_t nsub, int32_t *ncycles,
+                  void *hip_stream);
+
+/* ---- the chemistry-surrogate network (bf16 matrix cores) --------------- */
+/* Not part of the paper's method: an optional learned replacement for Phi.
+ * Network 5 -> 64 -> 64 -> 64 -> 2, SiLU hidden units.  theta is a device
+ * array of RT_MLP_NPARAM FP32 values in the order W1 (64x5), b1, W2 (64x64),
+ * b2, W3 (64x64), b3, W4 (2x64), b4, each W row-major (out, in).  Products
+ * run on bf16 operands rounded from theta and X with FP32 accumulation. */
+#define RT_MLP_NPARAM 8834
+
+typedef struct rt_mlp rt_mlp;
+
+/* Workspace for forward/gradient calls on `hip_stream`; grad_blocks (1 ..
+ * 65536) sets how many blocks share a gradient evaluation (each keeps an FP32
+ * gradient partial: grad_blocks * 8834 floats). */
+int rt_mlp_create(int32_t grad_blocks, void *hip_stream, rt_mlp **out);
+
+/* Y (device, B x 2) = network(X (device, B x 5, standardised inputs)). */
+int rt_mlp_forward(rt_mlp *m, const float *theta, const float *X, int64_t B, float *Y);
+
+/* Gradient of L = 1/(2B) sum over samples and outputs of (y - Y)^2 with
+ * respect to theta into grad (device, 8834 FP32); loss_dev (device double,
+ * may be NULL) receives L.  Deterministic (fixed-order reduction). */
+int rt_mlp_grad(rt_mlp *m, const float *theta, const float *X, const float *Y, int64_t B,
+                float *grad, double *loss_dev);
+
+/* One Adam step (Kingma & Ba 2015, bias-corrected, step >= 1) on the FP32
+ * master theta with moment buffers mom1, mom2 (device, 8834 each). */
+int rt_mlp_adam(rt_mlp *m, float *theta, float *mom1, float *mom2, const float *grad,
+                int64_t step, double lr, double beta1, double beta2, double eps);
+
+int rt_mlp_destroy(rt_mlp *m);
 
 /* Static string naming a return code. */
 const char *rt_strerror(int code);

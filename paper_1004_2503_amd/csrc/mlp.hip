@@ -1,0 +1,479 @@
+// mlp.hip -- training and batch inference of the chemistry-surrogate network
+// on gfx950 matrix cores, and the batch form of the exact per-cell chemistry
+// operator that produces its training pairs.
+//
+// Training step = pack (FP32 master -> permuted bf16 operands) -> fused
+// forward + backward per 32-sample chunk (one wavefront per block, every
+// product on v_mfma_f32_32x32x16_bf16, the weight gradients accumulated in
+// LDS in FP32) -> deterministic reduction of the per-block gradients -> Adam
+// on the FP32 master.
+#include <math.h>
+
+#include <new>
+
+#include "mlp_device.h"
+
+namespace rtk {
+
+// ------------------------------------------------------------ packing
+__global__ __launch_bounds__(256) void mlp_pack_kernel(const float *__restrict__ th,
+                                                       __bf16 *__restrict__ pk)
+{
+    const int e = blockIdx.x * 256 + threadIdx.x;
+    if (e >= PK_ALL * 8) return;
+    const int unit = e >> 3, s = e & 7;
+    const int lane = unit & 63, half = lane >> 5, row = lane & 31;
+    float v = 0.0f;
+    if (unit < PK_P2) {                       // W1, A[out][in]
+        const int mt = unit >> 6, in = 8 * half + s;
+        if (in < MLP_NIN) v = th[OFF_W1 + (32 * mt + row) * MLP_NIN + in];
+    } else if (unit < PK_P4) {                // W2, W3
+        const bool l3 = unit >= PK_P3;
+        const int g = (unit - (l3 ? PK_P3 : PK_P2)) >> 6, mt = g >> 2, kc = g & 3;
+        const int off = l3 ? OFF_W3 : OFF_W2;
+        v = th[off + (32 * mt + row) * MLP_NH + perm_in(kc, half, s)];
+    } else if (unit < PK_T4) {                // W4 (2 rows)
+        const int kc = (unit - PK_P4) >> 6;
+        if (row < MLP_NOUT) v = th[OFF_W4 + row * MLP_NH + perm_in(kc, half, s)];
+    } else if (unit < PK_T3) {                // W4^T: A[in][out]
+        const int mt = (unit - PK_T4) >> 6, out = 8 * half + s;
+        if (out < MLP_NOUT) v = th[OFF_W4 + out * MLP_NH + 32 * mt + row];
+    } else {                                  // W3^T, W2^T: A[in][out = perm]
+        const bool l2 = unit >= PK_T2;
+        const int g = (unit - (l2 ? PK_T2 : PK_T3)) >> 6, mt = g >> 2, kc = g & 3;
+        const int off = l2 ? OFF_W2 : OFF_W3;
+        v = th[off + perm_in(kc, half, s) * MLP_NH + 32 * mt + row];
+    }
+    pk[e] = (__bf16)v;
+}
+
+__device__ __forceinline__ bf16x8 load_features(const float *__restrict__ X, int64_t smp,
+                                                bool valid, int half)
+{
+    bf16x8 xb;
+#pragma unroll
+    for (int s = 0; s < 8; ++s) xb[s] = (__bf16)0.0f;
+    if (valid && half == 0) {
+#pragma unroll
+        for (int f = 0; f < MLP_NIN; ++f) xb[f] = (__bf16)X[smp * MLP_NIN + f];
+    }
+    return xb;
+}
+
+// ------------------------------------------------------ batch inference
+__global__ __launch_bounds__(256) void mlp_forward_kernel(const bf16x8 *__restrict__ pk,
+                                                          const float *__restrict__ th,
+                                                          const float *__restrict__ X,
+                                                          int64_t B, float *__restrict__ Y)
+{
+    const int lane = threadIdx.x & 63, half = lane >> 5, col = lane & 31;
+    const int64_t wave = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nw = (int64_t(gridDim.x) * blockDim.x) >> 6;
+    const int64_t nchunk = (B + 31) / 32;
+    for (int64_t c = wave; c < nchunk; c += nw) {
+        const int64_t smp = c * 32 + col;
+        const bool valid = smp < B;
+        MlpFwd st;
+        float y0, y1;
+        mlp_forward32<false>(pk, MlpBias{th + OFF_B1, th + OFF_B2, th + OFF_B3, th + OFF_B4},
+                             load_features(X, smp, valid, half), st, y0, y1);
+        if (valid && half == 0) {
+            Y[smp * 2] = y0;
+            Y[smp * 2 + 1] = y1;
+        }
+    }
+}
+
+// ------------------------------------------------ forward + backward
+// One wavefront per block.  Loss L = 1/(2B) sum (y - t)^2; the kernel sums
+// the unscaled gradient of sum (y - t)^2 / 2 per block; the reduction applies
+// 1/B.
+__global__ __launch_bounds__(64) void mlp_grad_kernel(const bf16x8 *__restrict__ pk,
+                                                      const float *__restrict__ th,
+                                                      const float *__restrict__ X,
+                                                      const float *__restrict__ Y, int64_t B,
+                                                      float *__restrict__ part,
+                                                      double *__restrict__ lpart)
+{
+    __shared__ float gacc[MLP_NPARAM];
+    __shared__ __attribute__((aligned(16))) __bf16 Gs[64][32];
+    __shared__ __attribute__((aligned(16))) __bf16 Hs[64][32];
+    __shared__ __attribute__((aligned(16))) __bf16 G4s[2][32];
+    const int lane = threadIdx.x, half = lane >> 5, col = lane & 31;
+    const f32x16 zero = {};
+    bf16x8 zero8, ones;
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+        zero8[s] = (__bf16)0.0f;
+        ones[s] = (__bf16)(col == 0 ? 1.0f : 0.0f);
+    }
+    for (int i = lane; i < MLP_NPARAM; i += 64) gacc[i] = 0.0f;
+    double lsum = 0.0;
+    const int64_t nchunk = (B + 31) / 32;
+
+    for (int64_t c = blockIdx.x; c < nchunk; c += gridDim.x) {
+        const int64_t smp = c * 32 + col;
+        const bool valid = smp < B;
+        const bf16x8 xb = load_features(X, smp, valid, half);
+        MlpFwd st;
+        float y0, y1;
+        mlp_forward32<true>(pk, MlpBias{th + OFF_B1, th + OFF_B2, th + OFF_B3, th + OFF_B4}, xb,
+                            st, y0, y1);
+        float d0 = 0.0f, d1 = 0.0f;
+        if (valid && half == 0) {
+            d0 = y0 - Y[smp * 2];
+            d1 = y1 - Y[smp * 2 + 1];
+            lsum += double(d0) * d0 + double(d1) * d1;
+        }
+
+        // ---- output layer: G4 (2 x cells)
+        bf16x8 g4 = zero8;
+        if (half == 0) {
+            g4[0] = (__bf16)d0;
+            g4[1] = (__bf16)d1;
+        }
+        f32x16 G[2];
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt) {
+            const f32x16 a = mfma32(pk[PK_T4 + mt * 64 + lane], g4, zero);
+#pragma unroll
+            for (int r = 0; r < 16; ++r) G[mt][r] = a[r] * silu_grad(st.z[4 + mt][r]);
+        }
+        __syncthreads();
+        if (half == 0) {
+            G4s[0][col] = (__bf16)d0;
+            G4s[1][col] = (__bf16)d1;
+        }
+#pragma unroll
+        for (int kc = 0; kc < 4; ++kc)
+#pragma unroll
+            for (int s = 0; s < 8; ++s) Hs[perm_in(kc, half, s)][col] = st.h[8 + kc][s];
+        __syncthreads();
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt) {
+            f32x16 a = zero;
+#pragma unroll
+            for (int kk = 0; kk < 2; ++kk) {
+                const bf16x8 A =
+                    col < MLP_NOUT ? *(const bf16x8 *)&G4s[col][16 * kk + 8 * half] : zero8;
+                const bf16x8 Bv = *(const bf16x8 *)&Hs[32 * nt + col][16 * kk + 8 * half];
+                a = mfma32(A, Bv, a);
+            }
+            if (half == 0) {
+                gacc[OFF_W4 + 32 * nt + col] += a[0];
+                gacc[OFF_W4 + MLP_NH + 32 * nt + col] += a[1];
+            }
+        }
+        {
+            float s0 = d0, s1 = d1;
+#pragma unroll
+            for (int off = 16; off > 0; off >>= 1) {
+                s0 += __shfl_xor(s0, off);
+                s1 += __shfl_xor(s1, off);
+            }
+            if (lane == 0) {
+                gacc[OFF_B4] += s0;
+                gacc[OFF_B4 + 1] += s1;
+            }
+        }
+
+        // ---- hidden layers 3, 2, 1: G holds dL/dZ_L in the D layout
+#pragma unroll
+        for (int L = 3; L >= 1; --L) {
+            const int offW = L == 3 ? OFF_W3 : (L == 2 ? OFF_W2 : OFF_W1);
+            const int offB = L == 3 ? OFF_B3 : (L == 2 ? OFF_B2 : OFF_B1);
+            const int nin = L == 1 ? MLP_NIN : MLP_NH;
+            // gradient flowing to the previous layer: W_L^T G_L, times SiLU'
+            f32x16 Gp[2];
+            if (L > 1) {
+                const int PT = L == 3 ? PK_T3 : PK_T2;
+                bf16x8 gb[4];
+#pragma unroll
+                for (int kc = 0; kc < 4; ++kc)
+#pragma unroll
+                    for (int s = 0; s < 8; ++s) gb[kc][s] = (__bf16)G[kc >> 1][8 * (kc & 1) + s];
+#pragma unroll
+                for (int mt = 0; mt < 2; ++mt) {
+                    f32x16 a = zero;
+#pragma unroll
+                    for (int kc = 0; kc < 4; ++kc) a = mfma32(pk[PT + (mt * 4 + kc) * 64 + lane], gb[kc], a);
+#pragma unroll
+                    for (int r = 0; r < 16; ++r)
+                        Gp[mt][r] = a[r] * silu_grad(st.z[2 * (L - 2) + mt][r]);
+                }
+            }
+            // dW_L = G_L H_{L-1}^T and db_L = G_L 1 through LDS transposes
+            __syncthreads();
+#pragma unroll
+            for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+                for (int r = 0; r < 16; ++r)
+                    Gs[32 * mt + 8 * (r >> 2) + 4 * half + (r & 3)][col] = (__bf16)G[mt][r];
+            if (L > 1) {
+#pragma unroll
+                for (int kc = 0; kc < 4; ++kc)
+#pragma unroll
+                    for (int s = 0; s < 8; ++s)
+                        Hs[perm_in(kc, half, s)][col] = st.h[4 * (L - 2) + kc][s];
+            } else {
+                // inputs: rows 0..4 features, rows 5..31 zero
+#pragma unroll
+                for (int f = 0; f < 16; ++f)
+                    Hs[16 * half + f][col] = (__bf16)(half == 0 && f < 8 ? float(xb[f & 7]) : 0.0f);
+            }
+            __syncthreads();
+            const int ntiles = L == 1 ? 1 : 2;
+#pragma unroll
+            for (int mt = 0; mt < 2; ++mt) {
+#pragma unroll
+                for (int nt = 0; nt < 2; ++nt) {
+                    if (nt >= ntiles) break;
+                    f32x16 a = zero;
+#pragma unroll
+                    for (int kk = 0; kk < 2; ++kk) {
+                        const bf16x8 A = *(const bf16x8 *)&Gs[32 * mt + col][16 * kk + 8 * half];
+                        const bf16x8 Bv = *(const bf16x8 *)&Hs[32 * nt + col][16 * kk + 8 * half];
+                        a = mfma32(A, Bv, a);
+                    }
+                    const int n = 32 * nt + col;
+                    if (n < nin) {
+#pragma unroll
+                        for (int r = 0; r < 16; ++r) {
+                            const int row = 32 * mt + 8 * (r >> 2) + 4 * half + (r & 3);
+                            gacc[offW + row * nin + n] += a[r];
+                        }
+                    }
+                }
+                f32x16 a = zero;
+#pragma unroll
+                for (int kk = 0; kk < 2; ++kk) {
+                    const bf16x8 A = *(const bf16x8 *)&Gs[32 * mt + col][16 * kk + 8 * half];
+                    a = mfma32(A, ones, a);
+                }
+                if (col == 0) {
+#pragma unroll
+                    for (int r = 0; r < 16; ++r)
+                        gacc[offB + 32 * mt + 8 * (r >> 2) + 4 * half + (r & 3)] += a[r];
+                }
+            }
+            if (L > 1) {
+                G[0] = Gp[0];
+                G[1] = Gp[1];
+            }
+        }
+    }
+    __syncthreads();
+    for (int i = lane; i < MLP_NPARAM; i += 64) part[size_t(blockIdx.x) * MLP_NPARAM + i] = gacc[i];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) lsum += __shfl_xor(lsum, off);
+    if (lane == 0) lpart[blockIdx.x] = lsum;
+}
+
+// fixed-order reduction of the block gradients; grad = sum / B
+__global__ __launch_bounds__(256) void mlp_reduce_kernel(const float *__restrict__ part,
+                                                         const double *__restrict__ lpart,
+                                                         int nblk, double invB,
+                                                         float *__restrict__ grad,
+                                                         double *__restrict__ loss)
+{
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    if (j < MLP_NPARAM) {
+        double s = 0.0;
+        for (int b = 0; b < nblk; ++b) s += part[size_t(b) * MLP_NPARAM + j];
+        grad[j] = float(s * invB);
+    }
+    if (j == 0 && loss) {
+        double s = 0.0;
+        for (int b = 0; b < nblk; ++b) s += lpart[b];
+        *loss = 0.5 * s * invB;
+    }
+}
+
+// Adam (Kingma & Ba 2015) on the FP32 master; c1, c2 are the bias corrections
+__global__ __launch_bounds__(256) void mlp_adam_kernel(float *__restrict__ th,
+                                                       float *__restrict__ m,
+                                                       float *__restrict__ v,
+                                                       const float *__restrict__ g, float lr,
+                                                       float b1, float b2, float eps, float c1,
+                                                       float c2)
+{
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    if (j >= MLP_NPARAM) return;
+    const float gj = g[j];
+    const float mj = b1 * m[j] + (1.0f - b1) * gj;
+    const float vj = b2 * v[j] + (1.0f - b2) * gj * gj;
+    m[j] = mj;
+    v[j] = vj;
+    th[j] -= lr * (mj / c1) / (sqrtf(vj / c2) + eps);
+}
+
+// ----------------------------------------- exact chemistry on a batch
+__global__ __launch_bounds__(256) void chem_batch_kernel(int64_t n, const float *__restrict__ nH,
+                                                         float *__restrict__ N,
+                                                         float *__restrict__ xHI,
+                                                         float *__restrict__ T,
+                                                         const float *__restrict__ dt,
+                                                         int chem, int mixed, int adaptive,
+                                                         int nsub, float csig, float T_h,
+                                                         float inv15kB, float T_floor,
+                                                         float sub_eps, float xhi_thr,
+                                                         int32_t *__restrict__ ncyc)
+{
+    const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (i >= n) return;
+    const float d = dt[i];
+    int nc = 0;
+    if (mixed && xHI[i] < xhi_thr) {
+        const ChemK<double> K{double(d), double(d) / nsub, double(csig), double(T_h),
+                              double(T_floor), double(sub_eps)};
+        double Nd = N[i], xd = xHI[i], Td = T[i], ad = 0.0;
+        nc = chem_cell<double>(chem, nsub, adaptive, inv15kB, K, double(nH[i]), Nd, xd, Td, ad);
+        N[i] = float(Nd);
+        xHI[i] = float(xd);
+        T[i] = float(Td);
+    } else {
+        const ChemK<float> K{d, d / float(nsub), csig, T_h, T_floor, sub_eps};
+        float Nf = N[i], xf = xHI[i], Tf = T[i], af = 0.0f;
+        nc = chem_cell<float>(chem, nsub, adaptive, inv15kB, K, nH[i], Nf, xf, Tf, af);
+        N[i] = Nf;
+        xHI[i] = xf;
+        T[i] = Tf;
+    }
+    if (ncyc) ncyc[i] = nc;
+}
+
+hipError_t launch_mlp_pack(const float *theta, __bf16 *pk, hipStream_t s)
+{
+    hipLaunchKernelGGL(mlp_pack_kernel, dim3((PK_ALL * 8 + 255) / 256), dim3(256), 0, s, theta,
+                       pk);
+    return hipGetLastError();
+}
+
+}  // namespace rtk
+
+using namespace rtk;
+
+struct rt_mlp {
+    hipStream_t stream = nullptr;
+    int nblk = 0;
+    __bf16 *pk = nullptr;
+    float *part = nullptr;
+    double *lpart = nullptr;
+};
+
+namespace {
+constexpr double KB_ = 1.380649e-16;
+constexpr double EV_ = 1.602176634e-12;
+
+int pack(rt_mlp *m, const float *theta)
+{
+    hipLaunchKernelGGL(mlp_pack_kernel, dim3((PK_ALL * 8 + 255) / 256), dim3(256), 0, m->stream,
+                       theta, m->pk);
+    return hipGetLastError() == hipSuccess ? RT_OK : RT_E_HIP;
+}
+}  // namespace
+
+extern "C" int rt_mlp_create(int32_t grad_blocks, void *hip_stream, rt_mlp **out)
+{
+    if (!out) return RT_E_ARG;
+    *out = nullptr;
+    if (grad_blocks < 1 || grad_blocks > 65536) return RT_E_ARG;
+    rt_mlp *m = new (std::nothrow) rt_mlp();
+    if (!m) return RT_E_NOMEM;
+    m->stream = static_cast<hipStream_t>(hip_stream);
+    m->nblk = grad_blocks;
+    if (hipMalloc(&m->pk, size_t(PK_ALL) * 8 * sizeof(__bf16)) != hipSuccess ||
+        hipMalloc(&m->part, size_t(grad_blocks) * MLP_NPARAM * sizeof(float)) != hipSuccess ||
+        hipMalloc(&m->lpart, size_t(grad_blocks) * sizeof(double)) != hipSuccess) {
+        (void)hipGetLastError();
+        if (m->pk) (void)hipFree(m->pk);
+        if (m->part) (void)hipFree(m->part);
+        delete m;
+        return RT_E_NOMEM;
+    }
+    *out = m;
+    return RT_OK;
+}
+
+extern "C" int rt_mlp_destroy(rt_mlp *m)
+{
+    if (!m) return RT_E_STATE;
+    (void)hipStreamSynchronize(m->stream);
+    (void)hipFree(m->pk);
+    (void)hipFree(m->part);
+    (void)hipFree(m->lpart);
+    delete m;
+    return RT_OK;
+}
+
+extern "C" int rt_mlp_forward(rt_mlp *m, const float *theta, const float *X, int64_t B,
+                              float *Y)
+{
+    if (!m) return RT_E_STATE;
+    if (B < 0 || (B > 0 && (!theta || !X || !Y))) return RT_E_ARG;
+    if (B == 0) return RT_OK;
+    if (pack(m, theta) != RT_OK) return RT_E_HIP;
+    const int64_t nchunk = (B + 31) / 32;
+    const int64_t blocks = (nchunk + 3) / 4 < 16384 ? (nchunk + 3) / 4 : 16384;
+    hipLaunchKernelGGL(mlp_forward_kernel, dim3(unsigned(blocks)), dim3(256), 0, m->stream,
+                       reinterpret_cast<const bf16x8 *>(m->pk), theta, X, B, Y);
+    return hipGetLastError() == hipSuccess ? RT_OK : RT_E_HIP;
+}
+
+extern "C" int rt_mlp_grad(rt_mlp *m, const float *theta, const float *X, const float *Y,
+                           int64_t B, float *grad, double *loss_dev)
+{
+    if (!m) return RT_E_STATE;
+    if (B < 1 || !theta || !X || !Y || !grad) return RT_E_ARG;
+    if (pack(m, theta) != RT_OK) return RT_E_HIP;
+    hipLaunchKernelGGL(mlp_grad_kernel, dim3(m->nblk), dim3(64), 0, m->stream,
+                       reinterpret_cast<const bf16x8 *>(m->pk), theta, X, Y, B, m->part,
+                       m->lpart);
+    if (hipGetLastError() != hipSuccess) return RT_E_HIP;
+    hipLaunchKernelGGL(mlp_reduce_kernel, dim3((MLP_NPARAM + 255) / 256), dim3(256), 0,
+                       m->stream, m->part, m->lpart, m->nblk, 1.0 / double(B), grad, loss_dev);
+    return hipGetLastError() == hipSuccess ? RT_OK : RT_E_HIP;
+}
+
+extern "C" int rt_mlp_adam(rt_mlp *m, float *theta, float *mom1, float *mom2,
+                           const float *grad, int64_t step, double lr, double beta1,
+                           double beta2, double eps)
+{
+    if (!m) return RT_E_STATE;
+    if (!theta || !mom1 || !mom2 || !grad || step < 1 || !(lr > 0.0) || !(beta1 >= 0.0) ||
+        !(beta1 < 1.0) || !(beta2 >= 0.0) || !(beta2 < 1.0) || !(eps >= 0.0))
+        return RT_E_ARG;
+    const double c1 = 1.0 - pow(beta1, double(step));
+    const double c2 = 1.0 - pow(beta2, double(step));
+    hipLaunchKernelGGL(mlp_adam_kernel, dim3((MLP_NPARAM + 255) / 256), dim3(256), 0,
+                       m->stream, theta, mom1, mom2, grad, float(lr), float(beta1),
+                       float(beta2), float(eps), float(c1), float(c2));
+    return hipGetLastError() == hipSuccess ? RT_OK : RT_E_HIP;
+}
+
+extern "C" int rt_chem_apply(const rt_params *p, int64_t n, const float *nH, float *N,
+                             float *xHI, float *T, const float *dt, int32_t nsub,
+                             int32_t *ncycles, void *hip_stream)
+{
+    if (!p) return RT_E_ARG;
+    if (n < 0 || nsub < 1 || nsub > 4096) return RT_E_ARG;
+    if (p->chem < RT_CHEM_FULL || p->chem > RT_CHEM_FROZEN) return RT_E_ARG;
+    if (p->prec != RT_PREC_FP32 && p->prec != RT_PREC_MIXED) return RT_E_ARG;
+    if (p->sub != RT_SUB_FIXED && p->sub != RT_SUB_ADAPTIVE) return RT_E_ARG;
+    if (p->sub == RT_SUB_ADAPTIVE && !(p->sub_eps > 0.0 && p->sub_eps <= 1.0)) return RT_E_ARG;
+    if (!(p->c_cms > 0.0) || !(p->sigma_n > 0.0) || !(p->sigma_e > 0.0) ||
+        !(p->egamma_eV > 0.0) || !(p->T_floor >= 0.0))
+        return RT_E_ARG;
+    if (n == 0) return RT_OK;
+    if (!nH || !N || !xHI || !T || !dt) return RT_E_ARG;
+    const double eheat = (p->sigma_e * p->egamma_eV / p->sigma_n - 13.6) * EV_;
+    const int64_t blocks = (n + 255) / 256;
+    if (blocks > 0x7fffffff) return RT_E_ARG;
+    hipLaunchKernelGGL(chem_batch_kernel, dim3(unsigned(blocks)), dim3(256), 0,
+                       static_cast<hipStream_t>(hip_stream), n, nH, N, xHI, T, dt, p->chem,
+                       p->prec == RT_PREC_MIXED ? 1 : 0, p->sub == RT_SUB_ADAPTIVE ? 1 : 0,
+                       nsub, float(p->c_cms * p->sigma_n), float(eheat / (1.5 * KB_)),
+                       float(1.0 / (1.5 * KB_)), float(p->T_floor), float(p->sub_eps),
+                       float(p->xhi_fp64_thr), ncycles);
+    return hipGetLastError() == hipSuccess ? RT_OK : RT_E_HIP;
+}

@@ -1,0 +1,136 @@
+// mlp_device.h -- the chemistry-surrogate network on gfx950 matrix cores.
+//
+// Network 5 -> 64 -> 64 -> 64 -> 2 with SiLU hidden units, bf16 operands,
+// FP32 accumulation, evaluated with v_mfma_f32_32x32x16_bf16 in the
+// transposed form  Z (neurons x cells) = W (out x in) . H (in x cells),  so
+// that 32 cells form the N dimension of every product.
+//
+// Lane layouts of the 32x32x16 bf16 product (checked on the device):
+//   A (32 x 16): lane l supplies row l%32, k = 8*(l/32) + 0..7;
+//   B (16 x 32): lane l supplies column l%32, k = 8*(l/32) + 0..7;
+//   D (32 x 32): lane l holds column l%32, rows 8*(r/4) + 4*(l/32) + r%4
+//                for r = 0..15.
+// A layer's D tiles therefore hold, in lane l, the cell l%32 and 16 of the
+// neurons per 32-neuron tile.  Those registers are fed unchanged to the next
+// product as its B operand: K-chunk kc (16 inputs) takes registers
+// 8*(kc%2) .. +7 of tile kc/2, i.e. input neuron perm_in(kc, l/32, s); the
+// weight operand is packed with the same permutation of its input index, so
+// no data moves between lanes between layers.
+//
+// Parameters: one FP32 vector of 8834 values in the order W1 (64x5), b1,
+// W2 (64x64), b2, W3 (64x64), b3, W4 (2x64), b4, each W row-major (out, in).
+#pragma once
+
+#include "rt_device.h"
+
+namespace rtk {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+constexpr int MLP_NIN = 5, MLP_NH = 64, MLP_NOUT = 2;
+constexpr int OFF_W1 = 0, OFF_B1 = 320, OFF_W2 = 384, OFF_B2 = 4480, OFF_W3 = 4544,
+              OFF_B3 = 8640, OFF_W4 = 8704, OFF_B4 = 8832, MLP_NPARAM = 8834;
+
+// packed operand array, in units of one lane's bf16x8 (64 units per product)
+constexpr int PK_P1 = 0;     // W1:   [mt 2][lane]
+constexpr int PK_P2 = 128;   // W2:   [mt 2][kc 4][lane]
+constexpr int PK_P3 = 640;   // W3:   [mt 2][kc 4][lane]
+constexpr int PK_P4 = 1152;  // W4:   [kc 4][lane]          (rows >= 2 zero)
+constexpr int PK_FWD = 1408; // end of the forward operands
+constexpr int PK_T4 = 1408;  // W4^T: [mt 2][lane]          (k >= 2 zero)
+constexpr int PK_T3 = 1536;  // W3^T: [mt 2][kc 4][lane]
+constexpr int PK_T2 = 2048;  // W2^T: [mt 2][kc 4][lane]
+constexpr int PK_ALL = 2560;
+
+__host__ __device__ __forceinline__ int perm_in(int kc, int half, int s)
+{
+    const int r = 8 * (kc & 1) + s;
+    return 32 * (kc >> 1) + 8 * (r >> 2) + 4 * half + (r & 3);
+}
+
+__device__ __forceinline__ f32x16 mfma32(bf16x8 a, bf16x8 b, f32x16 c)
+{
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ float silu(float z)
+{
+    return z * frcp(1.0f + fexp2(-1.4426950408889634f * z));
+}
+
+__device__ __forceinline__ float silu_grad(float z)
+{
+    const float s = frcp(1.0f + fexp2(-1.4426950408889634f * z));
+    return s * (1.0f + z * (1.0f - s));
+}
+
+// Saved forward state of 32 cells (training): pre-activations of the three
+// hidden layers (2 tiles each) and the bf16 B operands fed to layers 2, 3, 4.
+struct MlpFwd {
+    f32x16 z[6];
+    bf16x8 h[12];
+};
+
+// Biases of the four layers (FP32), wherever they live (global or LDS).
+struct MlpBias {
+    const float *b1, *b2, *b3, *b4;
+};
+
+// Forward pass of 32 cells.  xb: this lane's B operand of layer 1 (features
+// 0..4 of cell l%32 in lanes 0..31, zeros elsewhere).  pk: packed operands.
+// Returns the two outputs of cell l%32 in lanes 0..31.
+template <bool KEEP, typename PK>
+__device__ __forceinline__ void mlp_forward32(const PK *pk, const MlpBias &bias, bf16x8 xb,
+                                              MlpFwd &st, float &y0, float &y1)
+{
+    const int lane = threadIdx.x & 63, half = lane >> 5;
+    const f32x16 zero = {};
+    bf16x8 h[4];
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt) {
+        const f32x16 acc = mfma32(pk[PK_P1 + mt * 64 + lane], xb, zero);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int n = 32 * mt + 8 * (r >> 2) + 4 * half + (r & 3);
+            const float z = acc[r] + bias.b1[n];
+            if (KEEP) st.z[mt][r] = z;
+            h[2 * mt + (r >> 3)][r & 7] = (__bf16)silu(z);
+        }
+    }
+    if (KEEP) {
+#pragma unroll
+        for (int kc = 0; kc < 4; ++kc) st.h[kc] = h[kc];
+    }
+#pragma unroll
+    for (int L = 0; L < 2; ++L) {
+        const int P = L == 0 ? PK_P2 : PK_P3;
+        const float *bl = L == 0 ? bias.b2 : bias.b3;
+        bf16x8 hn[4];
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt) {
+            f32x16 acc = zero;
+#pragma unroll
+            for (int kc = 0; kc < 4; ++kc) acc = mfma32(pk[P + (mt * 4 + kc) * 64 + lane], h[kc], acc);
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int n = 32 * mt + 8 * (r >> 2) + 4 * half + (r & 3);
+                const float z = acc[r] + bl[n];
+                if (KEEP) st.z[2 + 2 * L + mt][r] = z;
+                hn[2 * mt + (r >> 3)][r & 7] = (__bf16)silu(z);
+            }
+        }
+#pragma unroll
+        for (int kc = 0; kc < 4; ++kc) {
+            h[kc] = hn[kc];
+            if (KEEP) st.h[4 * (L + 1) + kc] = hn[kc];
+        }
+    }
+    f32x16 acc = zero;
+#pragma unroll
+    for (int kc = 0; kc < 4; ++kc) acc = mfma32(pk[PK_P4 + kc * 64 + lane], h[kc], acc);
+    y0 = acc[0] + bias.b4[0];
+    y1 = acc[1] + bias.b4[1];
+}
+
+}  // namespace rtk

@@ -12,7 +12,7 @@
 #include <new>
 #include <vector>
 
-#include "rt_internal.h"
+#include "mlp_device.h"
 
 using namespace rtk;
 
@@ -51,6 +51,12 @@ struct rt_ctx {
     bool prof = false;
     std::vector<Ev> ev;
     size_t ev_used = 0;
+    // learned chemistry
+    bool surr = false;
+    __bf16 *d_surr_pk = nullptr;
+    float *d_surr_bias = nullptr;
+    float surr_norm[SURR_NNORM] = {};
+    float surr_tol = 0.0f;
 };
 
 static int check_params(const rt_params *p)
@@ -98,6 +104,8 @@ static void free_ctx(rt_ctx *c)
     if (c->d_src_rate) (void)hipFree(c->d_src_rate);
     if (c->d_part) (void)hipFree(c->d_part);
     if (c->d_acc) (void)hipFree(c->d_acc);
+    if (c->d_surr_pk) (void)hipFree(c->d_surr_pk);
+    if (c->d_surr_bias) (void)hipFree(c->d_surr_bias);
     for (auto &e : c->ev) {
         (void)hipEventDestroy(e.a);
         (void)hipEventDestroy(e.b);
@@ -320,6 +328,12 @@ static void fill_args(const rt_ctx *c, double dt, int nsub, StepArgs &a)
     a.sub_eps_d = p.sub_eps;
     a.vol = p.dx_cm * p.dx_cm * p.dx_cm;
     a.esc_scale = dt * p.dx_cm * p.dx_cm;
+    a.surr = c->surr ? 1 : 0;
+    a.surr_pk = c->d_surr_pk;
+    a.surr_bias = c->d_surr_bias;
+    for (int k = 0; k < SURR_NNORM; ++k) a.surr_norm[k] = c->surr_norm[k];
+    a.surr_tol = c->surr_tol;
+    a.log10_dt = float(log10(dt));
 }
 
 extern "C" int rt_step(rt_ctx *c, double dt, int32_t nsub)
@@ -351,11 +365,49 @@ extern "C" int rt_step(rt_ctx *c, double dt, int32_t nsub)
     c->t += dt;
     c->emitted += dt * c->ndot_total;
     c->steps += 1;
-    if (c->p.sub == RT_SUB_FIXED && c->p.chem != RT_CHEM_OFF) {
+    if (c->p.sub == RT_SUB_FIXED && c->p.chem != RT_CHEM_OFF && !c->surr) {
         int b = 0;
         while (b < 7 && (2 << b) <= nsub) ++b;
         c->hist_host[b] += int64_t(c->ncell);
     }
+    return RT_OK;
+}
+
+extern "C" int rt_set_surrogate(rt_ctx *c, const float *theta, const float *norm,
+                                double residual_tol)
+{
+    if (!c) return RT_E_STATE;
+    if (!theta) {
+        c->surr = false;
+        return RT_OK;
+    }
+    if (!norm || !(residual_tol > 0.0) || !isfinite(residual_tol)) return RT_E_ARG;
+    for (int k = 0; k < SURR_NNORM; ++k)
+        if (!isfinite(norm[k])) return RT_E_ARG;
+    for (int k = 0; k < 7; ++k)
+        if (!(norm[5 + k < 10 ? 5 + k : 12 + (k - 5)] > 0.0f)) return RT_E_ARG;
+    for (int k = 0; k < 5; ++k)
+        if (!(norm[14 + k] <= norm[19 + k])) return RT_E_ARG;
+    if (!c->d_surr_pk) {
+        if (hipMalloc(&c->d_surr_pk, size_t(PK_ALL) * 8 * sizeof(__bf16)) != hipSuccess ||
+            hipMalloc(&c->d_surr_bias, SURR_NBIAS * sizeof(float)) != hipSuccess) {
+            (void)hipGetLastError();
+            return RT_E_NOMEM;
+        }
+    }
+    const int offs[4] = {OFF_B1, OFF_B2, OFF_B3, OFF_B4};
+    const int lens[4] = {MLP_NH, MLP_NH, MLP_NH, MLP_NOUT};
+    int at = 0;
+    if (launch_mlp_pack(theta, c->d_surr_pk, c->stream) != hipSuccess) return RT_E_HIP;
+    for (int l = 0; l < 4; ++l) {
+        if (hipMemcpyAsync(c->d_surr_bias + at, theta + offs[l], lens[l] * sizeof(float),
+                           hipMemcpyDeviceToDevice, c->stream) != hipSuccess)
+            return RT_E_HIP;
+        at += lens[l];
+    }
+    for (int k = 0; k < SURR_NNORM; ++k) c->surr_norm[k] = norm[k];
+    c->surr_tol = float(residual_tol);
+    c->surr = true;
     return RT_OK;
 }
 

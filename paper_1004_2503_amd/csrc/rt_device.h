@@ -1,0 +1,202 @@
+// rt_device.h -- device-side building blocks shared by the gfx950 kernels of
+// librt_m1.so: fast math helpers, the M1 closure (Sec. 2.2), the hydrogen
+// rate set and the sub-cycled per-cell chemistry operator Phi (Sec. 2.2,
+// Appendix A).  Included by the step kernel, the batch chemistry kernel and
+// the surrogate kernels.
+#pragma once
+
+#include <math.h>
+
+#include "rt_internal.h"
+
+namespace rtk {
+
+// ------------------------------------------------------------ math helpers
+__device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double frcp(double x) { return 1.0 / x; }
+__device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ double fsqrt(double x) { return sqrt(x); }
+__device__ __forceinline__ float fexp2(float x) { return __builtin_amdgcn_exp2f(x); }
+__device__ __forceinline__ float flog2(float x) { return __builtin_amdgcn_logf(x); }
+template <typename R> __device__ __forceinline__ R rmin(R a, R b) { return a < b ? a : b; }
+template <typename R> __device__ __forceinline__ R rmax(R a, R b) { return a > b ? a : b; }
+
+// --------------------------------------------------- M1 closure (Sec. 2.2)
+// P = D N, D = (1-chi)/2 I + (3chi-1)/2 n(x)n, chi(f) of Levermore with
+// f = |F|/(cN) clamped to [0, 1], evaluated on the reduced flux u = F/(cN).
+struct Press {
+    float xx, yy, zz, xy, xz, yz;
+};
+
+// Radiation densities below N_TINY are treated as empty: their reciprocals
+// would leave the normal FP32 range.
+constexpr float N_TINY = 1e-30f;
+
+__device__ __forceinline__ Press closure(float N, float Fx, float Fy, float Fz,
+                                         float inv_c)
+{
+    Press P;
+    if (!(N > N_TINY)) {
+        P.xx = P.yy = P.zz = P.xy = P.xz = P.yz = 0.0f;
+        return P;
+    }
+    // reduced flux u = F/(cN), |u| = f
+    const float s = inv_c * frcp(N);
+    const float ux = Fx * s, uy = Fy * s, uz = Fz * s;
+    const float u2 = ux * ux + uy * uy + uz * uz;
+    const float f2 = rmin(u2, 1.0f);
+    const float chi = (3.0f + 4.0f * f2) * frcp(5.0f + 2.0f * fsqrt(4.0f - 3.0f * f2));
+    const float iso = 0.5f * (1.0f - chi) * N;
+    // (3chi-1)/2 N n_i n_j with n = u/|u|; negligible below f^2 = 1e-30
+    const float w = (u2 > 1e-30f) ? 0.5f * (3.0f * chi - 1.0f) * N * frcp(u2) : 0.0f;
+    P.xx = iso + w * ux * ux;
+    P.yy = iso + w * uy * uy;
+    P.zz = iso + w * uz * uz;
+    P.xy = w * ux * uy;
+    P.xz = w * ux * uz;
+    P.yz = w * uy * uz;
+    return P;
+}
+
+// ------------------------------------------------------- hydrogen rates
+// alpha_B and case-B recombination cooling: Hui & Gnedin (1997);
+// collisional ionisation, its cooling (13.6 eV each), collisional excitation
+// and free-free cooling: Cen (1992).  Cooling rates are returned divided by
+// 3/2 kB so that the energy update works in kelvin.
+struct RateSet {
+    float alpha;  // [cm^3/s]
+    float beta;   // [cm^3/s]
+    float crb;    // (recombination + free-free) cooling / (1.5 kB) [K cm^3/s]
+    float cci;    // (excitation + ionisation) cooling / (1.5 kB) [K cm^3/s]
+};
+
+__device__ __forceinline__ RateSet rates_f32(float T, float inv15kB)
+{
+    RateSet r;
+    const float iT = frcp(T);
+    const float lg = flog2(315614.0f * iT);           // log2(lambda)
+    const float log2T = 18.2678016762f - lg;
+    r.alpha = 2.753e-14f *
+              fexp2(1.5f * lg - 2.242f * flog2(1.0f + fexp2(0.407f * lg - 0.5918495885f)));
+    const float recb = 3.435e-30f * T *
+                       fexp2(1.970f * lg - 3.720f * flog2(1.0f + fexp2(0.376f * lg - 0.4398918005f)));
+    const float sT = fsqrt(T);
+    const float damp = frcp(1.0f + sT * 3.162277660168e-3f);
+    r.beta = 5.85e-11f * sT * fexp2(-227670.405977f * iT) * damp;
+    const float colex = 7.5e-19f * fexp2(-170740.072699f * iT) * damp;
+    const float colion = 2.178960222240e-11f * r.beta;
+    const float lt = 5.5f - 0.301029995664f * log2T;
+    const float brems = 1.42e-27f * sT * (1.1f + 0.34f * fexp2(-0.480898346963f * lt * lt));
+    r.crb = (recb + brems) * inv15kB;
+    r.cci = (colex + colion) * inv15kB;
+    return r;
+}
+
+// ------------------------------------------------ per-cell operator Phi
+template <typename R>
+struct ChemK {
+    R dt, hfix, csig, T_h, T_floor, sub_eps;
+};
+
+// shortest e-folding time of xHI and of the internal energy (adaptive mode)
+template <typename R>
+__device__ __forceinline__ R chem_timescale(int chem, const ChemK<R> &K, const RateSet &rs,
+                                            R nH, R N, R xHI, R T)
+{
+    R x = R(1) - xHI;
+    R g = K.csig * N;
+    R dxh = R(rs.alpha) * nH * x * x - (g + R(rs.beta) * nH * x) * xHI;
+    R t = R(3.0e38f);
+    if (dxh != R(0)) t = xHI * frcp(fabs(dxh));
+    if (chem == RT_CHEM_FULL) {
+        R du = g * xHI * K.T_h - nH * (x * x * R(rs.crb) + x * xHI * R(rs.cci));
+        if (du != R(0)) t = rmin(t, (R(1) + x) * T * frcp(fabs(du)));
+    }
+    return t;
+}
+
+// Sub-cycles of one cell: implicit photon-conserving photoionisation,
+// creation/destruction recombination update, semi-implicit energy update.
+// Returns the number of sub-cycles; N, xHI, T updated; `absorbed` gains the
+// photon density removed.
+template <typename R>
+__device__ __forceinline__ int chem_cell(int chem, int nsub, int adaptive, float inv15kB,
+                                         const ChemK<R> &K, R nH, R &N, R &xHI, R &T,
+                                         R &absorbed)
+{
+    const R inv_nH = frcp(nH);
+    R remaining = K.dt;
+    int it = 0;
+    for (; it < nsub && remaining > R(0); ++it) {
+        RateSet rs;
+        bool have = false;
+        R h;
+        if (it == nsub - 1) {
+            h = remaining;
+        } else if (adaptive) {
+            rs = rates_f32(float(T), inv15kB);
+            have = true;
+            h = rmin(remaining, K.sub_eps * chem_timescale<R>(chem, K, rs, nH, N, xHI, T));
+        } else {
+            h = K.hfix;
+        }
+        remaining -= h;
+        if (it == nsub - 1 || remaining < R(0)) remaining = R(0);
+
+        const R a = K.csig * h;
+        const R nHI = nH * xHI;
+        if (chem == RT_CHEM_FROZEN) {
+            R Nn = N * frcp(R(1) + a * nHI);
+            absorbed += N - Nn;
+            N = Nn;
+            continue;
+        }
+        // photoionisation: remaining photons Nn and neutrals un solve
+        // a un Nn = N - Nn, un - Nn = nHI - N; each root taken in the
+        // cancellation-free form for its sign of aD.
+        const R x0 = R(1) - xHI;
+        const R aN = a * N, aH = a * nHI, aD = aH - aN;
+        const R opd = R(1) + aD;
+        const R s = fsqrt(opd * opd + R(4) * aN);
+        R Nn, un;
+        if (aD >= R(0)) {
+            Nn = R(2) * N * frcp(opd + s);
+            un = Nn + (nHI - N);
+        } else {
+            un = R(2) * nHI * frcp((R(1) - aD) + s);
+            Nn = un - (nHI - N);
+        }
+        Nn = rmin(rmax(Nn, R(0)), N);
+        un = rmin(rmax(un, R(0)), nHI);
+        const R Pd = R(2) * aN * nHI * frcp(R(1) + aN + aH + s);
+        absorbed += N - Nn;
+        N = Nn;
+        const R xh = un * inv_nH;
+
+        // recombination (case B) and collisional ionisation
+        if (!have) rs = rates_f32(float(T), inv15kB);
+        const R x = R(1) - xh;
+        R xn = (xh + R(rs.alpha) * nH * x * x * h) * frcp(R(1) + R(rs.beta) * nH * x * h);
+        xn = rmin(rmax(xn, R(1e-12)), R(1));
+
+        // internal energy 3/2 kB nH (1+x) T: photo-heating, then cooling
+        if (chem == RT_CHEM_FULL) {
+            const R x1 = R(1) - xn;
+            const R lu = h * nH * (x1 * x1 * R(rs.crb) + x1 * xn * R(rs.cci)) *
+                         frcp((R(1) + x0) * T);
+            const R Tn = ((R(1) + x0) * T + Pd * inv_nH * K.T_h) *
+                         frcp((R(1) + lu) * (R(1) + x1));
+            T = rmax(Tn, K.T_floor);
+        }
+        xHI = xn;
+    }
+    return it;
+}
+
+__device__ __forceinline__ int hist_bin(int n)
+{
+    int b = 31 - __builtin_clz(n > 0 ? n : 1);
+    return b > 7 ? 7 : b;
+}
+
+}  // namespace rtk

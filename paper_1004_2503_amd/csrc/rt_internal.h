@@ -55,9 +55,21 @@ struct StepArgs {
         sub_eps, xhi_thr;
     // FP64 constants for the FP64 chemistry path and the tallies
     double dt_d, csig_d, T_h_d, T_floor_d, sub_eps_d, vol, esc_scale;
+    // learned chemistry (surrogate form): packed bf16 forward operands,
+    // biases b1|b2|b3|b4 (194 floats), and mu_in[5] sd_in[5] mu_out[2]
+    // sd_out[2] in_min[5] in_max[5]
+    const __bf16 *surr_pk;
+    const float *surr_bias;
+    float surr_norm[24];
+    float surr_tol, log10_dt;
+    int surr;
 };
 
+constexpr int SURR_NBIAS = 194;
+constexpr int SURR_NNORM = 24;
+
 hipError_t launch_step(const StepArgs &a, hipStream_t s);
+hipError_t launch_mlp_pack(const float *theta, __bf16 *pk, hipStream_t s);
 hipError_t launch_finalize(const double *partials, int nblocks, double *acc,
                            int mode, hipStream_t s);
 hipError_t launch_state_sums(const float *N, const float *xHI, const float *nH,

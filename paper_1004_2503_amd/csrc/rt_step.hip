@@ -19,197 +19,9 @@
 //     own L2.
 #include <math.h>
 
-#include "rt_internal.h"
+#include "mlp_device.h"
 
 namespace rtk {
-
-// ------------------------------------------------------------ math helpers
-__device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
-__device__ __forceinline__ double frcp(double x) { return 1.0 / x; }
-__device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
-__device__ __forceinline__ double fsqrt(double x) { return sqrt(x); }
-__device__ __forceinline__ float fexp2(float x) { return __builtin_amdgcn_exp2f(x); }
-__device__ __forceinline__ float flog2(float x) { return __builtin_amdgcn_logf(x); }
-template <typename R> __device__ __forceinline__ R rmin(R a, R b) { return a < b ? a : b; }
-template <typename R> __device__ __forceinline__ R rmax(R a, R b) { return a > b ? a : b; }
-
-// --------------------------------------------------- M1 closure (Sec. 2.2)
-// P = D N, D = (1-chi)/2 I + (3chi-1)/2 n(x)n, chi(f) of Levermore with
-// f = |F|/(cN) clamped to [0, 1], evaluated on the reduced flux u = F/(cN).
-struct Press {
-    float xx, yy, zz, xy, xz, yz;
-};
-
-// Radiation densities below N_TINY are treated as empty: their reciprocals
-// would leave the normal FP32 range.
-constexpr float N_TINY = 1e-30f;
-
-__device__ __forceinline__ Press closure(float N, float Fx, float Fy, float Fz,
-                                         float inv_c)
-{
-    Press P;
-    if (!(N > N_TINY)) {
-        P.xx = P.yy = P.zz = P.xy = P.xz = P.yz = 0.0f;
-        return P;
-    }
-    // reduced flux u = F/(cN), |u| = f
-    const float s = inv_c * frcp(N);
-    const float ux = Fx * s, uy = Fy * s, uz = Fz * s;
-    const float u2 = ux * ux + uy * uy + uz * uz;
-    const float f2 = rmin(u2, 1.0f);
-    const float chi = (3.0f + 4.0f * f2) * frcp(5.0f + 2.0f * fsqrt(4.0f - 3.0f * f2));
-    const float iso = 0.5f * (1.0f - chi) * N;
-    // (3chi-1)/2 N n_i n_j with n = u/|u|; negligible below f^2 = 1e-30
-    const float w = (u2 > 1e-30f) ? 0.5f * (3.0f * chi - 1.0f) * N * frcp(u2) : 0.0f;
-    P.xx = iso + w * ux * ux;
-    P.yy = iso + w * uy * uy;
-    P.zz = iso + w * uz * uz;
-    P.xy = w * ux * uy;
-    P.xz = w * ux * uz;
-    P.yz = w * uy * uz;
-    return P;
-}
-
-// ------------------------------------------------------- hydrogen rates
-// alpha_B and case-B recombination cooling: Hui & Gnedin (1997);
-// collisional ionisation, its cooling (13.6 eV each), collisional excitation
-// and free-free cooling: Cen (1992).  Cooling rates are returned divided by
-// 3/2 kB so that the energy update works in kelvin.
-struct RateSet {
-    float alpha;  // [cm^3/s]
-    float beta;   // [cm^3/s]
-    float crb;    // (recombination + free-free) cooling / (1.5 kB) [K cm^3/s]
-    float cci;    // (excitation + ionisation) cooling / (1.5 kB) [K cm^3/s]
-};
-
-__device__ __forceinline__ RateSet rates_f32(float T, float inv15kB)
-{
-    RateSet r;
-    const float iT = frcp(T);
-    const float lg = flog2(315614.0f * iT);           // log2(lambda)
-    const float log2T = 18.2678016762f - lg;
-    r.alpha = 2.753e-14f *
-              fexp2(1.5f * lg - 2.242f * flog2(1.0f + fexp2(0.407f * lg - 0.5918495885f)));
-    const float recb = 3.435e-30f * T *
-                       fexp2(1.970f * lg - 3.720f * flog2(1.0f + fexp2(0.376f * lg - 0.4398918005f)));
-    const float sT = fsqrt(T);
-    const float damp = frcp(1.0f + sT * 3.162277660168e-3f);
-    r.beta = 5.85e-11f * sT * fexp2(-227670.405977f * iT) * damp;
-    const float colex = 7.5e-19f * fexp2(-170740.072699f * iT) * damp;
-    const float colion = 2.178960222240e-11f * r.beta;
-    const float lt = 5.5f - 0.301029995664f * log2T;
-    const float brems = 1.42e-27f * sT * (1.1f + 0.34f * fexp2(-0.480898346963f * lt * lt));
-    r.crb = (recb + brems) * inv15kB;
-    r.cci = (colex + colion) * inv15kB;
-    return r;
-}
-
-// ------------------------------------------------ per-cell operator Phi
-template <typename R>
-struct ChemK {
-    R dt, hfix, csig, T_h, T_floor, sub_eps;
-};
-
-// shortest e-folding time of xHI and of the internal energy (adaptive mode)
-template <typename R>
-__device__ __forceinline__ R chem_timescale(int chem, const ChemK<R> &K, const RateSet &rs,
-                                            R nH, R N, R xHI, R T)
-{
-    R x = R(1) - xHI;
-    R g = K.csig * N;
-    R dxh = R(rs.alpha) * nH * x * x - (g + R(rs.beta) * nH * x) * xHI;
-    R t = R(3.0e38f);
-    if (dxh != R(0)) t = xHI * frcp(fabs(dxh));
-    if (chem == RT_CHEM_FULL) {
-        R du = g * xHI * K.T_h - nH * (x * x * R(rs.crb) + x * xHI * R(rs.cci));
-        if (du != R(0)) t = rmin(t, (R(1) + x) * T * frcp(fabs(du)));
-    }
-    return t;
-}
-
-// Sub-cycles of one cell: implicit photon-conserving photoionisation,
-// creation/destruction recombination update, semi-implicit energy update.
-// Returns the number of sub-cycles; N, xHI, T updated; `absorbed` gains the
-// photon density removed.
-template <typename R>
-__device__ __forceinline__ int chem_cell(int chem, int nsub, int adaptive, float inv15kB,
-                                         const ChemK<R> &K, R nH, R &N, R &xHI, R &T,
-                                         R &absorbed)
-{
-    const R inv_nH = frcp(nH);
-    R remaining = K.dt;
-    int it = 0;
-    for (; it < nsub && remaining > R(0); ++it) {
-        RateSet rs;
-        bool have = false;
-        R h;
-        if (it == nsub - 1) {
-            h = remaining;
-        } else if (adaptive) {
-            rs = rates_f32(float(T), inv15kB);
-            have = true;
-            h = rmin(remaining, K.sub_eps * chem_timescale<R>(chem, K, rs, nH, N, xHI, T));
-        } else {
-            h = K.hfix;
-        }
-        remaining -= h;
-        if (it == nsub - 1 || remaining < R(0)) remaining = R(0);
-
-        const R a = K.csig * h;
-        const R nHI = nH * xHI;
-        if (chem == RT_CHEM_FROZEN) {
-            R Nn = N * frcp(R(1) + a * nHI);
-            absorbed += N - Nn;
-            N = Nn;
-            continue;
-        }
-        // photoionisation: remaining photons Nn and neutrals un solve
-        // a un Nn = N - Nn, un - Nn = nHI - N; each root taken in the
-        // cancellation-free form for its sign of aD.
-        const R x0 = R(1) - xHI;
-        const R aN = a * N, aH = a * nHI, aD = aH - aN;
-        const R opd = R(1) + aD;
-        const R s = fsqrt(opd * opd + R(4) * aN);
-        R Nn, un;
-        if (aD >= R(0)) {
-            Nn = R(2) * N * frcp(opd + s);
-            un = Nn + (nHI - N);
-        } else {
-            un = R(2) * nHI * frcp((R(1) - aD) + s);
-            Nn = un - (nHI - N);
-        }
-        Nn = rmin(rmax(Nn, R(0)), N);
-        un = rmin(rmax(un, R(0)), nHI);
-        const R Pd = R(2) * aN * nHI * frcp(R(1) + aN + aH + s);
-        absorbed += N - Nn;
-        N = Nn;
-        const R xh = un * inv_nH;
-
-        // recombination (case B) and collisional ionisation
-        if (!have) rs = rates_f32(float(T), inv15kB);
-        const R x = R(1) - xh;
-        R xn = (xh + R(rs.alpha) * nH * x * x * h) * frcp(R(1) + R(rs.beta) * nH * x * h);
-        xn = rmin(rmax(xn, R(1e-12)), R(1));
-
-        // internal energy 3/2 kB nH (1+x) T: photo-heating, then cooling
-        if (chem == RT_CHEM_FULL) {
-            const R x1 = R(1) - xn;
-            const R lu = h * nH * (x1 * x1 * R(rs.crb) + x1 * xn * R(rs.cci)) *
-                         frcp((R(1) + x0) * T);
-            const R Tn = ((R(1) + x0) * T + Pd * inv_nH * K.T_h) *
-                         frcp((R(1) + lu) * (R(1) + x1));
-            T = rmax(Tn, K.T_floor);
-        }
-        xHI = xn;
-    }
-    return it;
-}
-
-__device__ __forceinline__ int hist_bin(int n)
-{
-    int b = 31 - __builtin_clz(n > 0 ? n : 1);
-    return b > 7 ? 7 : b;
-}
 
 // ------------------------------------------------------ boundary mapping
 struct Map1 {
@@ -255,10 +67,12 @@ __device__ __forceinline__ Cell4 load4(const StepArgs &A, uint32_t i, float sx, 
 }
 
 // ------------------------------------------------------ fused step kernel
-template <bool MIXED>
+template <bool MIXED, bool SURR>
 __global__ __launch_bounds__(NTHREADS) void m1_step_kernel(StepArgs A)
 {
     constexpr int SW = TX + 2;
+    __shared__ __attribute__((aligned(16))) __bf16 s_pk[SURR ? PK_FWD * 8 : 8];
+    __shared__ float s_bias[SURR ? SURR_NBIAS : 1];
     __shared__ float sN[TY + 2][SW], sFx[TY + 2][SW], sFy[TY + 2][SW], sFz[TY + 2][SW];
     __shared__ float sPxx[TY + 2][SW], sPyy[TY + 2][SW], sPxy[TY + 2][SW];
     __shared__ float sPxz[TY + 2][SW], sPyz[TY + 2][SW];
@@ -266,6 +80,13 @@ __global__ __launch_bounds__(NTHREADS) void m1_step_kernel(StepArgs A)
 
     const int tid = threadIdx.x;
     const int lx = tid & (TX - 1), ly = tid / TX;
+    if (SURR) {
+        // network operands to LDS (read by every plane; the first barrier of
+        // the z loop orders these stores before any use)
+        for (int i = tid; i < PK_FWD; i += NTHREADS)
+            reinterpret_cast<uint4 *>(s_pk)[i] = reinterpret_cast<const uint4 *>(A.surr_pk)[i];
+        for (int i = tid; i < SURR_NBIAS; i += NTHREADS) s_bias[i] = A.surr_bias[i];
+    }
 
     // XCD-aware renumbering: blockIdx mod 8 selects the XCD; each XCD takes
     // a contiguous range of tiles (x fastest, then y, then the z chunk).
@@ -315,7 +136,7 @@ __global__ __launch_bounds__(NTHREADS) void m1_step_kernel(StepArgs A)
     // FP64 accumulators
     double acc_xhi = 0.0, acc_nhxhi = 0.0, acc_nh = 0.0, acc_N = 0.0;
     double acc_abs = 0.0, acc_esc = 0.0, acc_floor = 0.0;
-    int n_bad = 0, n_fp64 = 0;
+    int n_bad = 0, n_fp64 = 0, n_fb = 0;
     __shared__ int shist[8];
     if (tid < 8) shist[tid] = 0;
 
@@ -460,7 +281,79 @@ __global__ __launch_bounds__(NTHREADS) void m1_step_kernel(StepArgs A)
         double pabs = 0.0;
         int ncyc = 0;
         bool used64 = false;
-        if (A.chem != RT_CHEM_OFF) {
+        bool fallback = true;
+        if (SURR) {
+            // learned Phi for the 64 cells of this wavefront (uniform control
+            // flow: every lane takes part in the matrix products)
+            const float *nm = A.surr_norm;
+            const float LOG10_2 = 0.301029995664f;
+            float f[5] = {LOG10_2 * flog2(c_nh), LOG10_2 * flog2(rmax(c_xh, 1e-30f)),
+                          LOG10_2 * flog2(c_T), LOG10_2 * flog2(rmax(Nt, 1e-30f)), A.log10_dt};
+            bool ood = !(c_nh > 0.0f && c_T > 0.0f);
+            float sv[5];
+#pragma unroll
+            for (int k = 0; k < 5; ++k) {
+                ood = ood || !(f[k] >= nm[14 + k] && f[k] <= nm[19 + k]);
+                sv[k] = (f[k] - nm[k]) * frcp(nm[5 + k]);
+            }
+            const int lane = tid & 63;
+            bf16x8 xa, xb;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                xa[k] = (__bf16)0.0f;
+                xb[k] = (__bf16)0.0f;
+            }
+#pragma unroll
+            for (int k = 0; k < 5; ++k) {
+                const float up = __shfl(sv[k], (lane + 32) & 63);
+                if (lane < 32) {
+                    xa[k] = (__bf16)sv[k];
+                    xb[k] = (__bf16)up;
+                }
+            }
+            const MlpBias mb{s_bias, s_bias + 64, s_bias + 128, s_bias + 192};
+            const bf16x8 *spk = reinterpret_cast<const bf16x8 *>(s_pk);
+            MlpFwd unused;
+            float ya0, ya1, yb0, yb1;
+            mlp_forward32<false>(spk, mb, xa, unused, ya0, ya1);
+            mlp_forward32<false>(spk, mb, xb, unused, yb0, yb1);
+            const float sb0 = __shfl(yb0, lane & 31), sb1 = __shfl(yb1, lane & 31);
+            const float y0 = lane < 32 ? ya0 : sb0, y1 = lane < 32 ? ya1 : sb1;
+            // decode: log10 xHI', log10 T'
+            const float xs = fexp2((y0 * nm[12] + nm[10]) * 3.321928094887362f);
+            float Ts = fexp2((y1 * nm[13] + nm[11]) * 3.321928094887362f);
+            if (A.chem != RT_CHEM_FULL) Ts = c_T;
+            // photons absorbed over dt: net ionisations + recombinations -
+            // collisional ionisations at the predicted end state
+            const RateSet rs = rates_f32(Ts, A.inv15kB);
+            const float x1 = 1.0f - xs, x0 = 1.0f - c_xh;
+            const float nh2dt = c_nh * c_nh * A.dt;
+            float Ph = c_nh * (c_xh - xs) + rs.alpha * nh2dt * x1 * x1 - rs.beta * nh2dt * x1 * xs;
+            Ph = rmin(rmax(Ph, 0.0f), Nt);
+            const float Ns = Nt - Ph;
+            // backward-Euler residuals of one step dt at the predicted end
+            const float inv_nh = frcp(c_nh);
+            const float rx = fabsf(Ph - A.csig * A.dt * Ns * c_nh * xs) * inv_nh;
+            float rT = 0.0f;
+            if (A.chem == RT_CHEM_FULL) {
+                const float lu = A.dt * c_nh * (x1 * x1 * rs.crb + x1 * xs * rs.cci) *
+                                 frcp((1.0f + x1) * Ts);
+                const float TBE = ((1.0f + x0) * c_T + Ph * inv_nh * A.T_h) *
+                                  frcp((1.0f + lu) * (1.0f + x1));
+                rT = fabsf(Ts - TBE) * frcp(Ts);
+            }
+            const bool ok = A.chem == RT_CHEM_FULL && !ood && xs >= 1e-12f && xs <= 1.0f &&
+                            Ts >= A.T_floor && isfinite(Ts) && rx <= A.surr_tol &&
+                            rT <= A.surr_tol;
+            if (ok) {
+                fallback = false;
+                Nn = Ns;
+                xh = xs;
+                Tc = Ts;
+                pabs = Ph;
+            }
+        }
+        if (A.chem != RT_CHEM_OFF && fallback) {
             if (MIXED && c_xh < A.xhi_thr) {
                 double Nd = Nt, xd = c_xh, Td = c_T, ad = 0.0;
                 ncyc = chem_cell<double>(A.chem, A.nsub, A.adaptive, A.inv15kB, Kd,
@@ -476,6 +369,8 @@ __global__ __launch_bounds__(NTHREADS) void m1_step_kernel(StepArgs A)
                                         xh, Tc, af);
                 pabs = af;
             }
+        }
+        if (A.chem != RT_CHEM_OFF) {
             const float sc = (Nt > N_TINY) ? rmin(Nn * frcp(Nt), 1.0f) : 0.0f;
             Fxt *= sc;
             Fyt *= sc;
@@ -505,12 +400,13 @@ __global__ __launch_bounds__(NTHREADS) void m1_step_kernel(StepArgs A)
                              isfinite(c_nh);
             n_bad += fin ? 0 : 1;
             n_fp64 += used64 ? 1 : 0;
+            n_fb += (SURR && fallback && A.chem != RT_CHEM_OFF) ? 1 : 0;
         }
-        if (A.adaptive && A.chem != RT_CHEM_OFF) {
+        if ((A.adaptive || SURR) && A.chem != RT_CHEM_OFF) {
             const int bin = hist_bin(ncyc);
 #pragma unroll
             for (int hb = 0; hb < 8; ++hb) {
-                const unsigned long long m = __ballot(active && bin == hb);
+                const unsigned long long m = __ballot(active && fallback && bin == hb);
                 if (lx == 0 && m) atomicAdd(&shist[hb], __popcll(m));
             }
         }
@@ -538,7 +434,7 @@ __global__ __launch_bounds__(NTHREADS) void m1_step_kernel(StepArgs A)
     v[R_FLOOR] = acc_floor * A.vol;
     v[R_NONFINITE] = double(n_bad);
     v[R_FP64] = double(n_fp64);
-    v[R_FALLBACK] = 0.0;
+    v[R_FALLBACK] = double(n_fb);
 #pragma unroll
     for (int hb = 0; hb < 8; ++hb) v[R_HIST0 + hb] = 0.0;
 #pragma unroll
@@ -640,10 +536,18 @@ int state_sums_blocks(uint32_t ncell)
 
 hipError_t launch_step(const StepArgs &a, hipStream_t s)
 {
-    if (a.mixed)
-        hipLaunchKernelGGL(m1_step_kernel<true>, dim3(a.nblocks), dim3(NTHREADS), 0, s, a);
-    else
-        hipLaunchKernelGGL(m1_step_kernel<false>, dim3(a.nblocks), dim3(NTHREADS), 0, s, a);
+    const dim3 g(a.nblocks), b(NTHREADS);
+    if (a.surr) {
+        if (a.mixed)
+            hipLaunchKernelGGL((m1_step_kernel<true, true>), g, b, 0, s, a);
+        else
+            hipLaunchKernelGGL((m1_step_kernel<false, true>), g, b, 0, s, a);
+    } else {
+        if (a.mixed)
+            hipLaunchKernelGGL((m1_step_kernel<true, false>), g, b, 0, s, a);
+        else
+            hipLaunchKernelGGL((m1_step_kernel<false, false>), g, b, 0, s, a);
+    }
     return hipGetLastError();
 }
 

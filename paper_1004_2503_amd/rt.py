@@ -275,3 +275,69 @@ class RTGrid:
             self.close()
         except Exception:
             pass
+
+
+# ------------------------------------------------ batch chemistry and MLP
+MLP_NPARAM = 8834
+EXPORTS += ["rt_chem_apply", "rt_mlp_create", "rt_mlp_forward", "rt_mlp_grad", "rt_mlp_adam",
+            "rt_mlp_destroy"]
+
+
+def _bind_extra(L):
+    vp = ctypes.c_void_p
+    if getattr(L, "_extra_bound", False):
+        return L
+    L.rt_chem_apply.argtypes = [ctypes.POINTER(rt_params), ctypes.c_int64, vp, vp, vp, vp, vp,
+                                ctypes.c_int32, vp, vp]
+    L.rt_mlp_create.argtypes = [ctypes.c_int32, vp, ctypes.POINTER(vp)]
+    L.rt_mlp_forward.argtypes = [vp, vp, vp, ctypes.c_int64, vp]
+    L.rt_mlp_grad.argtypes = [vp, vp, vp, vp, ctypes.c_int64, vp, vp]
+    L.rt_mlp_adam.argtypes = [vp, vp, vp, vp, vp, ctypes.c_int64, ctypes.c_double,
+                              ctypes.c_double, ctypes.c_double, ctypes.c_double]
+    L.rt_mlp_destroy.argtypes = [vp]
+    for n in ("rt_chem_apply", "rt_mlp_create", "rt_mlp_forward", "rt_mlp_grad",
+              "rt_mlp_adam", "rt_mlp_destroy"):
+        getattr(L, n).restype = ctypes.c_int
+    L._extra_bound = True
+    return L
+
+
+def _p(t):
+    return ctypes.c_void_p(0 if t is None else t.data_ptr())
+
+
+def rt_chem_apply(params: rt_params, nH, N, xHI, T, dt, nsub: int, ncycles=None,
+                  stream: int | None = None) -> int:
+    """Phi on a batch of cells: torch float32 device tensors, updated in place."""
+    L = _bind_extra(lib())
+    n = int(nH.numel())
+    for t in (N, xHI, T, dt):
+        if t.numel() != n:
+            return RT_E_ARG
+    return L.rt_chem_apply(ctypes.byref(params), n, _p(nH), _p(N), _p(xHI), _p(T), _p(dt),
+                           int(nsub), _p(ncycles), ctypes.c_void_p(stream or 0))
+
+
+def rt_mlp_create(grad_blocks: int, stream: int | None = None):
+    L = _bind_extra(lib())
+    h = ctypes.c_void_p()
+    rc = L.rt_mlp_create(int(grad_blocks), ctypes.c_void_p(stream or 0), ctypes.byref(h))
+    return rc, h
+
+
+def rt_mlp_forward(m, theta, X, Y) -> int:
+    return _bind_extra(lib()).rt_mlp_forward(m, _p(theta), _p(X), int(X.shape[0]), _p(Y))
+
+
+def rt_mlp_grad(m, theta, X, Y, grad, loss_dev=None) -> int:
+    return _bind_extra(lib()).rt_mlp_grad(m, _p(theta), _p(X), _p(Y), int(X.shape[0]),
+                                          _p(grad), _p(loss_dev))
+
+
+def rt_mlp_adam(m, theta, mom1, mom2, grad, step, lr, beta1=0.9, beta2=0.999, eps=1e-8) -> int:
+    return _bind_extra(lib()).rt_mlp_adam(m, _p(theta), _p(mom1), _p(mom2), _p(grad), int(step),
+                                          float(lr), float(beta1), float(beta2), float(eps))
+
+
+def rt_mlp_destroy(m) -> int:
+    return _bind_extra(lib()).rt_mlp_destroy(m)

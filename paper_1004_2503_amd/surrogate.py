@@ -1,0 +1,146 @@
+"""Training of the learned chemistry surrogate (not part of the paper's
+method; an optional replacement for the exact per-cell operator Phi).
+
+Everything numerical runs in the library: training pairs come from the exact
+operator on the GPU (rt_chem_apply), gradients and Adam steps from the
+matrix-core kernels (rt_mlp_grad, rt_mlp_adam), evaluation from
+rt_mlp_forward.  This module only samples cells, builds the log-space
+features, standardises them and loops.
+
+Features (log10, floored at 1e-30 for N and xHI): nH, xHI, T, N, dt.
+Targets: log10 xHI', log10 T' after Phi over dt.
+"""
+
+from __future__ import annotations
+
+import math
+import time
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import rt
+
+FLOOR = 1e-30
+
+
+@dataclass
+class Surrogate:
+    theta: "object"            # torch float32 (8834,) on the device
+    mu_in: np.ndarray
+    sd_in: np.ndarray
+    mu_out: np.ndarray
+    sd_out: np.ndarray
+    in_min: np.ndarray
+    in_max: np.ndarray
+    history: list
+
+    def norm_array(self) -> np.ndarray:
+        return np.concatenate([self.mu_in, self.sd_in, self.mu_out, self.sd_out,
+                               self.in_min, self.in_max]).astype(np.float32)
+
+
+def features(torch, nH, N, xHI, T, dt):
+    return torch.stack([torch.log10(nH), torch.log10(xHI.clamp_min(FLOOR)), torch.log10(T),
+                        torch.log10(N.clamp_min(FLOOR)), torch.log10(dt)], dim=1)
+
+
+def exact_pairs(params, nH, N, xHI, T, dt, nsub):
+    """Apply the exact operator to copies of the given cells (device tensors);
+    returns (X raw features, Y raw targets, N after)."""
+    import torch
+
+    N1, x1, T1 = N.clone(), xHI.clone(), T.clone()
+    rt.check(rt.rt_chem_apply(params, nH, N1, x1, T1, dt, nsub), "rt_chem_apply")
+    X = features(torch, nH, N, xHI, T, dt)
+    Y = torch.stack([torch.log10(x1.clamp_min(FLOOR)), torch.log10(T1)], dim=1)
+    return X, Y, N1
+
+
+def sample_cells(state: dict, n: int, seed: int, lit_fraction: float = 0.8):
+    """Draw n cells from a state dict of device tensors (N, xHI, T, nH),
+    preferring cells that hold photons (the ones whose chemistry evolves)."""
+    import torch
+
+    g = torch.Generator(device=state["N"].device)
+    g.manual_seed(seed)
+    flatN = state["N"].reshape(-1)
+    lit = torch.nonzero(flatN > 0).reshape(-1)
+    n_lit = min(int(n * lit_fraction), lit.numel() * 50) if lit.numel() else 0
+    idx_lit = lit[torch.randint(0, max(lit.numel(), 1), (n_lit,), generator=g,
+                                device=lit.device)] if n_lit else lit[:0]
+    idx_any = torch.randint(0, flatN.numel(), (n - n_lit,), generator=g, device=flatN.device)
+    idx = torch.cat([idx_lit, idx_any])
+    return {k: state[k].reshape(-1)[idx].clone() for k in ("N", "xHI", "T", "nH")}
+
+
+def _init_params(seed: int) -> np.ndarray:
+    """He-style uniform initialisation (fan-in), biases zero."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for o, i in ((64, 5), (64, 64), (64, 64), (2, 64)):
+        lim = math.sqrt(6.0 / i)
+        parts.append(rng.uniform(-lim, lim, size=o * i))
+        parts.append(np.zeros(o))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def fit(X, Y, steps: int = 3000, batch: int = 65536, lr: float = 2e-3, seed: int = 0,
+        grad_blocks: int = 1024, log_every: int = 250, verbose: bool = True) -> Surrogate:
+    """Fit the network to raw features X (n, 5) and targets Y (n, 2), device
+    tensors.  Adam with a cosine-decayed learning rate."""
+    import torch
+
+    dev = X.device
+    mu_in, sd_in = X.mean(0), X.std(0).clamp_min(1e-6)
+    mu_out, sd_out = Y.mean(0), Y.std(0).clamp_min(1e-6)
+    Xs = ((X - mu_in) / sd_in).float().contiguous()
+    Ys = ((Y - mu_out) / sd_out).float().contiguous()
+    n = Xs.shape[0]
+    theta = torch.tensor(_init_params(seed), device=dev)
+    m1 = torch.zeros_like(theta)
+    m2 = torch.zeros_like(theta)
+    grad = torch.zeros_like(theta)
+    loss = torch.zeros(1, dtype=torch.float64, device=dev)
+    rc, h = rt.rt_mlp_create(grad_blocks, torch.cuda.current_stream(dev).cuda_stream)
+    rt.check(rc, "rt_mlp_create")
+    g = torch.Generator(device=dev)
+    g.manual_seed(seed)
+    hist = []
+    t0 = time.time()
+    try:
+        for step in range(1, steps + 1):
+            idx = torch.randint(0, n, (min(batch, n),), generator=g, device=dev)
+            xb, yb = Xs[idx].contiguous(), Ys[idx].contiguous()
+            rt.check(rt.rt_mlp_grad(h, theta, xb, yb, grad, loss), "rt_mlp_grad")
+            lr_t = lr * 0.5 * (1.0 + math.cos(math.pi * step / steps)) + 1e-5
+            rt.check(rt.rt_mlp_adam(h, theta, m1, m2, grad, step, lr_t), "rt_mlp_adam")
+            if step % log_every == 0 or step == steps:
+                lv = float(loss.item())
+                hist.append((step, lv, time.time() - t0))
+                if verbose:
+                    print(f"  surrogate step {step}/{steps}: loss {lv:.3e} "
+                          f"({time.time() - t0:.1f} s)", flush=True)
+    finally:
+        rt.rt_mlp_destroy(h)
+    return Surrogate(theta=theta, mu_in=mu_in.cpu().numpy(), sd_in=sd_in.cpu().numpy(),
+                     mu_out=mu_out.cpu().numpy(), sd_out=sd_out.cpu().numpy(),
+                     in_min=X.min(0).values.cpu().numpy(), in_max=X.max(0).values.cpu().numpy(),
+                     history=hist)
+
+
+def predict(s: Surrogate, X):
+    """Raw features -> raw targets with the trained network (device)."""
+    import torch
+
+    Xs = ((X - torch.tensor(s.mu_in, device=X.device)) /
+          torch.tensor(s.sd_in, device=X.device)).float().contiguous()
+    Y = torch.zeros((X.shape[0], 2), device=X.device)
+    rc, h = rt.rt_mlp_create(1, torch.cuda.current_stream(X.device).cuda_stream)
+    rt.check(rc, "rt_mlp_create")
+    try:
+        rt.check(rt.rt_mlp_forward(h, s.theta, Xs, Y), "rt_mlp_forward")
+    finally:
+        torch.cuda.synchronize()
+        rt.rt_mlp_destroy(h)
+    return Y * torch.tensor(s.sd_out, device=X.device) + torch.tensor(s.mu_out, device=X.device)

@@ -38,7 +38,7 @@ def test_library_exports_every_declared_symbol():
     L = rt.lib()
     for n in declared_functions():
         assert hasattr(L, n)
-    assert sorted(rt.EXPORTS) == declared_functions()
+    assert sorted(set(rt.EXPORTS)) == declared_functions()
 
 
 def _c_layout(tmp_path):

@@ -1,0 +1,172 @@
+"""GPU parity on the configured workloads.
+
+  * Stromgren 32^3 (heated, T0 = 100 K): 500 steps on both sides; the
+    ionisation-front radius agrees within one cell, and the isothermal
+    variant tracks the closed form within one cell.
+  * Cosmological 128^3 / 256^3 grids: the library runs its own trajectory;
+    one step from its state is then checked against the oracle everywhere.
+  * 64^3 cosmological trajectory: per-field error after 200 steps of
+    independent evolution (reported, loosely bounded).
+  * 1024^3 (the benchmark's workload and launch configuration): one step
+    checked on sampled 32^3 sub-blocks (random, the eight corners and around
+    sources), the oracle stepping each from the library's input state."""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1004_2503_amd import rt
+from paper_1004_2503_amd import workloads as W
+
+from parity_util import assert_parity, errors, oracle_grid, oracle_state
+
+pytestmark = pytest.mark.gpu
+
+
+def front_radius_cells(xHI, dx):
+    V = float(np.sum(1.0 - xHI.astype(np.float64))) * dx ** 3
+    return (6.0 * V / np.pi) ** (1.0 / 3.0) / dx
+
+
+@pytest.mark.parametrize("chem", [rt.CHEM_FULL, rt.CHEM_ISOTHERMAL])
+def test_stromgren32_front_after_500_steps(chem):
+    w = W.workload("stromgren32")
+    n = w.n
+    T0 = w.T0 if chem == rt.CHEM_FULL else 1e4
+    st = dict(xHI=np.ones((n,) * 3, np.float32), T=np.full((n,) * 3, T0, np.float32),
+              nH=np.full((n,) * 3, w.nH_mean, np.float32))
+    src = W.stromgren_sources(w)
+    G = rt.RTGrid(rt.make_params((n,) * 3, w.dx, bc=w.bc, chem=chem), st)
+    G.inject_sources(*src)
+    G.step(w.dt, 1, 500)
+    out = G.state_numpy()
+    red = G.reduce()
+    G.close()
+    g = oracle_grid(st, (n,) * 3, w.dx, w.bc, chem, sources=src)
+    g.step(w.dt, 1, 500)
+    r_gpu = front_radius_cells(out["xHI"], w.dx)
+    r_orc = front_radius_cells(g.xHI, w.dx)
+    assert abs(r_gpu - r_orc) < 1.0, (r_gpu, r_orc)
+    assert abs(r_gpu - r_orc) < 0.05 * r_orc
+    if chem == rt.CHEM_ISOTHERMAL:
+        alpha = oracle.rates(1e4)[0]
+        rS = (3 * w.extra["ndot"] / (4 * np.pi * alpha * w.nH_mean ** 2)) ** (1 / 3)
+        t = 500 * w.dt
+        want = rS * (1 - np.exp(-t * alpha * w.nH_mean)) ** (1 / 3) / w.dx
+        assert abs(r_gpu - want) < 1.0
+    # the photon budget of the whole run
+    lhs = red["photons_initial"] + red["photons_emitted"] + red["photons_floor"]
+    rhs = red["photons_stored"] + red["photons_absorbed"] + red["photons_escaped"]
+    assert rhs == pytest.approx(lhs, rel=1e-4)
+
+
+def _cosmo_grid(name, steps, nsub=1, device="cuda"):
+    w = W.workload(name)
+    nH, ijk, ndot = W.cosmo_inputs(w, device=device)
+    prec = w.prec
+    G = rt.RTGrid(rt.make_params((w.n,) * 3, w.dx, prec=prec), dict(nH=nH))
+    G.inject_sources(ijk, ndot)
+    G.step(w.dt, nsub, steps)
+    return w, G, (ijk, ndot)
+
+
+@pytest.mark.parametrize("name,steps", [("cosmo128", 60), ("cosmo256", 40)])
+def test_cosmological_one_step_from_evolved_state(name, steps):
+    w, G, src = _cosmo_grid(name, steps)
+    st = G.state_numpy()
+    G.close()
+    shape = (w.n,) * 3
+    G2 = rt.RTGrid(rt.make_params(shape, w.dx, prec=w.prec), st)
+    G2.inject_sources(*src)
+    G2.step(w.dt, 1)
+    out = G2.state_numpy()
+    red = G2.reduce()
+    G2.close()
+    g = oracle_grid(st, shape, w.dx, (0,) * 6, oracle.CHEM_FULL, sources=src)
+    g.step(w.dt, 1)
+    e = errors(out, oracle_state(g))
+    assert_parity(e, what=name)
+    # the evolved state is non-trivial: photons spread and gas ionised
+    assert np.count_nonzero(st["N"]) > 0.005 * st["N"].size
+    assert st["xHI"].min() < 0.5
+    print(f"{name}: fp64 chemistry cells in the checked step: {red['n_fp64']}", flush=True)
+
+
+def test_cosmological_trajectory_error_64():
+    n, steps = 64, 200
+    dx = W.cosmo_dx(n)
+    dt = W.courant_dt(dx)
+    nH = W.lognormal_density(n).numpy()
+    ijk = W.densest_cells(torch.from_numpy(nH), 32)
+    ndot = W.luminosities(len(ijk))
+    st = dict(nH=nH, xHI=np.ones_like(nH), T=np.full_like(nH, 1e4))
+    G = rt.RTGrid(rt.make_params((n,) * 3, dx, prec=rt.PREC_MIXED), st)
+    G.inject_sources(ijk, ndot)
+    G.step(dt, 1, steps)
+    out = G.state_numpy()
+    G.close()
+    g = oracle_grid(st, (n,) * 3, dx, (0,) * 6, oracle.CHEM_FULL, sources=(ijk, ndot))
+    g.step(dt, 1, steps)
+    e = errors(out, oracle_state(g))
+    print(f"per-field error after {steps} independent steps at 64^3: {e}", flush=True)
+    assert_parity(e, tol=dict(N=1e-3, F=1e-3, xHI=1e-2, T=1e-2), what="trajectory")
+
+
+def _block(t, z0, y0, x0, B, halo, n):
+    idx = [torch.arange(o - halo, o + B + halo, device=t.device) % n for o in (z0, y0, x0)]
+    a = t.index_select(0, idx[0]).index_select(1, idx[1]).index_select(2, idx[2])
+    return a.double().cpu().numpy()
+
+
+@pytest.mark.timeout(900)
+def test_cosmo1024_sampled_subblocks():
+    w = W.workload("cosmo1024")
+    n, B = w.n, 32
+    nH, ijk, ndot = W.cosmo_inputs(w, device="cuda")
+    G = rt.RTGrid(rt.make_params((n,) * 3, w.dx, prec=rt.PREC_MIXED), dict(nH=nH))
+    del nH
+    G.inject_sources(ijk, ndot)
+    G.step(w.dt, 1, 20)
+    # sample origins: random, the eight corners, around a few sources
+    rng = np.random.default_rng(1024)
+    origins = [tuple(int(v) for v in rng.integers(0, n - B + 1, 3)) for _ in range(48)]
+    origins += [(z, y, x) for z in (0, n - B) for y in (0, n - B) for x in (0, n - B)]
+    for s in rng.choice(len(ijk), 8, replace=False):
+        i, j, k = (int(v) for v in ijk[s])
+        origins.append((max(0, min(k - B // 2, n - B)), max(0, min(j - B // 2, n - B)),
+                        max(0, min(i - B // 2, n - B))))
+    pre = G.tensors()
+    before = {}
+    for o in origins:
+        before[o] = dict(xHI=_block(pre["xHI"], *o, B, 0, n), T=_block(pre["T"], *o, B, 0, n))
+    G.step(w.dt, 1)
+    post = G.tensors()
+    cur = G.current()
+    Nin, Fin = G.N[1 - cur], [G.Fx[1 - cur], G.Fy[1 - cur], G.Fz[1 - cur]]
+    p = oracle.make_params((B, B, B), w.dx, chem=oracle.CHEM_FULL)
+    vol = w.dx ** 3
+    worst = dict(N=0.0, F=0.0, xHI=0.0, T=0.0)
+    for o in origins:
+        z0, y0, x0 = o
+        S = np.zeros((B, B, B))
+        inside = ((ijk[:, 0] >= x0) & (ijk[:, 0] < x0 + B) & (ijk[:, 1] >= y0) &
+                  (ijk[:, 1] < y0 + B) & (ijk[:, 2] >= z0) & (ijk[:, 2] < z0 + B))
+        for (i, j, k), q in zip(ijk[inside], ndot[inside]):
+            S[k - z0, j - y0, i - x0] += q / vol
+        res = oracle.step_subblock(p, w.dt, 1, _block(Nin, *o, B, 1, n),
+                                   [_block(f, *o, B, 1, n) for f in Fin],
+                                   before[o]["xHI"], before[o]["T"],
+                                   _block(G.nH, *o, B, 0, n), S)
+        ref = dict(N=res[0], Fx=res[1], Fy=res[2], Fz=res[3], xHI=res[4], T=res[5])
+        got = {k: _block(post[k], *o, B, 0, n) for k in ("N", "Fx", "Fy", "Fz", "xHI", "T")}
+        if np.max(np.abs(ref["N"])) == 0:
+            assert np.all(got["N"] == 0)
+            continue
+        e = errors(got, ref)
+        for k in worst:
+            worst[k] = max(worst[k], e[k])
+        assert_parity(e, what=f"1024^3 block at {o}")
+    print(f"1024^3 sampled blocks ({len(origins)}): worst errors {worst}", flush=True)
+    G.close()
+    torch.cuda.empty_cache()

@@ -341,3 +341,23 @@ def rt_mlp_adam(m, theta, mom1, mom2, grad, step, lr, beta1=0.9, beta2=0.999, ep
 
 def rt_mlp_destroy(m) -> int:
     return _bind_extra(lib()).rt_mlp_destroy(m)
+
+
+EXPORTS += ["rt_set_surrogate"]
+
+
+def rt_set_surrogate(ctx, theta, norm, residual_tol: float) -> int:
+    """theta: torch float32 device tensor (8834) or None (off); norm: 24 host
+    floats (mu_in, sd_in, mu_out, sd_out, in_min, in_max)."""
+    L = lib()
+    L.rt_set_surrogate.argtypes = [ctypes.c_void_p, ctypes.c_void_p,
+                                   ctypes.POINTER(ctypes.c_float), ctypes.c_double]
+    L.rt_set_surrogate.restype = ctypes.c_int
+    if theta is None:
+        return L.rt_set_surrogate(ctx, None, None, 0.0)
+    nv = np.ascontiguousarray(np.asarray(norm, dtype=np.float32).reshape(-1))
+    if nv.size != 24:
+        return RT_E_ARG
+    return L.rt_set_surrogate(ctx, ctypes.c_void_p(theta.data_ptr()),
+                              nv.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                              float(residual_tol))

@@ -92,6 +92,91 @@ def cpu_baseline(G, w, dt, nsub, budget_s: float, seed: int = 20100417):
                       f"step each ({cells} cell-updates in {t_total:.1f} s)"}
 
 
+def surrogate_leg(args, G, w, dt, params):
+    """Train the network on exact pairs sampled from the 256^3 run (several
+    dt), then time the surrogate form from the same state as the plain form
+    and compare the two after the same number of steps."""
+    import torch
+
+    from paper_1004_2503_amd import rt, surrogate
+    from paper_1004_2503_amd import workloads as W
+
+    t0 = time.perf_counter()
+    w256 = W.workload("cosmo256")
+    nH, ijk, ndot = W.cosmo_inputs(w256, device="cuda")
+    G2 = rt.RTGrid(rt.make_params((256,) * 3, w256.dx, prec=rt.PREC_MIXED), dict(nH=nH))
+    del nH
+    G2.inject_sources(ijk, ndot)
+    states = []
+    for _ in range(4):
+        G2.step(w256.dt, 1, 125)
+        t = G2.tensors()
+        states.append({k: t[k].clone() for k in ("N", "xHI", "T", "nH")})
+    G2.close()
+    pexact = rt.make_params((1, 1, 1), 1.0, chem=rt.CHEM_FULL, prec=rt.PREC_MIXED,
+                            sub=rt.SUB_ADAPTIVE, sub_eps=0.1)
+    dts = [W.courant_dt(W.cosmo_dx(n)) for n in (256, 512, 1024)]
+    per = args.surrogate_pairs // (len(states) * len(dts))
+    Xs, Ys = [], []
+    for i, st in enumerate(states):
+        for j, d in enumerate(dts):
+            c = surrogate.sample_cells(st, per, 1000 * i + j)
+            X, Y, _ = surrogate.exact_pairs(pexact, c["nH"], c["N"], c["xHI"], c["T"],
+                                            torch.full_like(c["N"], d), 64)
+            Xs.append(X)
+            Ys.append(Y)
+    n_pairs = int(per * len(states) * len(dts))
+    del states
+    X, Y = torch.cat(Xs), torch.cat(Ys)
+    del Xs, Ys
+    t_pairs = time.perf_counter() - t0
+    s = surrogate.fit(X, Y, steps=args.surrogate_steps, batch=65536, lr=1e-3,
+                      grad_blocks=1024, log_every=max(args.surrogate_steps // 6, 1),
+                      verbose=False)
+    t_train = time.perf_counter() - t0 - t_pairs
+    P = surrogate.predict(s, X[:1_000_000])
+    fit_dx = float((10 ** P[:, 0] - 10 ** Y[:1_000_000, 0]).abs().mean())
+    del X, Y, P
+
+    # both forms from the current state, same steps
+    snap = {k: v.clone() for k, v in G.tensors().items()}
+    n_steps = max(args.steps // 2, 10)
+    out = {}
+    for form in ("plain", "surrogate"):
+        c = G.current()                       # the buffer the next step reads
+        for k in ("xHI", "T"):
+            getattr(G, k).copy_(snap[k])
+        for k in ("N", "Fx", "Fy", "Fz"):
+            getattr(G, k)[c].copy_(snap[k])
+        if form == "surrogate":
+            rt.check(rt.rt_set_surrogate(G.ctx, s.theta, s.norm_array(), 1e-3),
+                     "rt_set_surrogate")
+        r0 = G.reduce()
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        G.step(dt, args.nsub, n_steps)
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        r1 = G.reduce()
+        out[form] = dict(ms_per_step=(tb - ta) / n_steps * 1e3,
+                         value=w.cells * n_steps / (tb - ta),
+                         fallback_frac=(r1["n_fallback"] - r0["n_fallback"]) /
+                         (w.cells * n_steps),
+                         xHI=G.xHI.clone())
+        rt.check(rt.rt_set_surrogate(G.ctx, None, None, 0.0), "rt_set_surrogate off")
+    dxm = float((out["surrogate"]["xHI"] - out["plain"]["xHI"]).abs().double().mean())
+    return {"value": out["surrogate"]["value"], "unit": "cell-updates/s",
+            "ms_per_step": out["surrogate"]["ms_per_step"],
+            "plain_ms_per_step_same_state": out["plain"]["ms_per_step"],
+            "speedup_vs_plain": out["plain"]["ms_per_step"] / out["surrogate"]["ms_per_step"],
+            "fallback_frac": out["surrogate"]["fallback_frac"],
+            "mean_abs_dxHI_vs_plain": dxm, "steps": n_steps,
+            "train": {"pairs": n_pairs, "adam_steps": args.surrogate_steps,
+                      "pair_gen_s": t_pairs, "train_s": t_train,
+                      "loss_first_last": [s.history[0][1], s.history[-1][1]],
+                      "fit_mean_abs_dxHI": fit_dx}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -101,8 +186,17 @@ def main():
                     choices=["cosmo128", "cosmo256", "cosmo512", "cosmo1024"])
     ap.add_argument("--nsub", type=int, default=1)
     ap.add_argument("--prec", default="mixed", choices=["fp32", "mixed"])
+    ap.add_argument("--chem", default="full", choices=["full", "isothermal", "off"])
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="instead of the step, time a plain device copy of MIB MiB "
+                         "(the reference for the HBM byte counters)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--surrogate", action="store_true",
+                    help="also train the learned chemistry on exact pairs from the 256^3 "
+                         "run and time the surrogate form on the same workload")
+    ap.add_argument("--surrogate-pairs", type=int, default=10_000_000)
+    ap.add_argument("--surrogate-steps", type=int, default=3000)
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -118,6 +212,21 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.copy_calibration:
+        n = args.copy_calibration * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(args.warmup):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        dtc = (time.perf_counter() - t0) / args.steps
+        print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n,
+                          "ms": dtc * 1e3, "GBs": 8 * n / dtc / 1e9}), flush=True)
+        return
     w = W.workload(args.workload)
     prec = rt.PREC_MIXED if args.prec == "mixed" else rt.PREC_FP32
     t_gen = time.perf_counter()
@@ -127,7 +236,8 @@ def main():
     print(f"# inputs {w.name}: {w.n}^3, {len(ijk)} sources, generated in {t_gen:.1f} s",
           file=sys.stderr, flush=True)
 
-    params = rt.make_params((w.n,) * 3, w.dx, chem=rt.CHEM_FULL, prec=prec)
+    chem = {"full": rt.CHEM_FULL, "isothermal": rt.CHEM_ISOTHERMAL, "off": rt.CHEM_OFF}[args.chem]
+    params = rt.make_params((w.n,) * 3, w.dx, chem=chem, prec=prec)
     T0 = torch.full((w.n,) * 3, w.T0, dtype=torch.float32, device=dev)
     G = rt.RTGrid(params, dict(nH=nH, T=T0), device=dev)
     del nH, T0
@@ -157,6 +267,10 @@ def main():
             "kernel": "m1_step_kernel", "avg_launch_ms": avg_ms,
             "bytes_per_cell": BYTES_PER_CELL}
 
+    surr = None
+    if args.surrogate:
+        surr = surrogate_leg(args, G, w, dt, params)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(G, w, dt, args.nsub, args.cpu_seconds)
@@ -176,12 +290,14 @@ def main():
         "dtype": "f32+f64" if prec == rt.PREC_MIXED else "f32",
         "data": "synthetic",
         "config": {"workload": f"{w.name}: {w.n}^3 lognormal (sigma_ln 1.5, mean nH 2e-4), "
-                               f"{len(ijk)} sources, plain exact chemistry",
-                   "grid": w.n, "sources": len(ijk), "nsub": args.nsub,
+                               f"{len(ijk)} sources, plain exact chemistry"
+                               + ("" if args.chem == "full" else f" (chemistry {args.chem})"),
+                   "grid": w.n, "sources": len(ijk), "nsub": args.nsub, "chem": args.chem,
                    "precision": args.prec, "dt_s": dt, "dx_cm": w.dx,
                    "parallelism": "single GPU, whole grid"},
         "roofline": roof,
         "cpu_baseline": cpu,
+        "surrogate": surr,
         "hbm_frac_whole_step": BYTES_PER_CELL * value / (HBM_PEAK_GBS * 1e9),
         "state_after": {"xhi_vol": red["xhi_vol"], "xhi_mass": red["xhi_mass"],
                         "gamma_vol": red["gamma_vol"], "n_fp64": red["n_fp64"],

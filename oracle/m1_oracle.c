@@ -118,7 +118,10 @@ static double cooling(const double r[6], double nHII, double nHI)
 }
 
 /* Adaptive sub-cycle time scale: the shorter of the neutral-fraction and
- * internal-energy e-folding times from the rates at the current state. */
+ * internal-energy times, each against the GROSS rate of change (creation
+ * plus destruction, heating plus cooling).  Against the net rate the time
+ * scale would be ill-conditioned near equilibrium, where the net rate is a
+ * small difference of large terms. */
 static double chem_timescale(const orc_params *p, double nH, double N,
                              double xHI, double T)
 {
@@ -126,13 +129,13 @@ static double chem_timescale(const orc_params *p, double nH, double N,
     orc_rates(T, r);
     double x = 1.0 - xHI;
     double gamma = p->c * p->sigma_n * N;
-    double dxHI = r[0] * nH * x * x - (gamma + r[1] * nH * x) * xHI;
+    double gross_x = r[0] * nH * x * x + (gamma + r[1] * nH * x) * xHI;
     double u = 1.5 * KB * nH * (1.0 + x) * T;
-    double du = gamma * nH * xHI * orc_heat_per_ionisation_erg(p) -
-                cooling(r, nH * x, nH * xHI);
+    double gross_u = gamma * nH * xHI * orc_heat_per_ionisation_erg(p) +
+                     cooling(r, nH * x, nH * xHI);
     double t = INFINITY;
-    if (dxHI != 0.0) t = fmin(t, xHI / fabs(dxHI));
-    if (p->chem == ORC_CHEM_FULL && du != 0.0) t = fmin(t, u / fabs(du));
+    if (gross_x > 0.0) t = fmin(t, xHI / gross_x);
+    if (p->chem == ORC_CHEM_FULL && gross_u > 0.0) t = fmin(t, u / gross_u);
     return t;
 }
 

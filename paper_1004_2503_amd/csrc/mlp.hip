@@ -294,14 +294,14 @@ __global__ __launch_bounds__(256) void mlp_adam_kernel(float *__restrict__ th,
                                                        float *__restrict__ m,
                                                        float *__restrict__ v,
                                                        const float *__restrict__ g, float lr,
-                                                       float b1, float b2, float eps, float c1,
-                                                       float c2)
+                                                       float b1, float b2, float omb1,
+                                                       float omb2, float eps, float c1, float c2)
 {
     const int j = blockIdx.x * 256 + threadIdx.x;
     if (j >= MLP_NPARAM) return;
     const float gj = g[j];
-    const float mj = b1 * m[j] + (1.0f - b1) * gj;
-    const float vj = b2 * v[j] + (1.0f - b2) * gj * gj;
+    const float mj = b1 * m[j] + omb1 * gj;
+    const float vj = b2 * v[j] + omb2 * gj * gj;
     m[j] = mj;
     v[j] = vj;
     th[j] -= lr * (mj / c1) / (sqrtf(vj / c2) + eps);
@@ -447,7 +447,8 @@ extern "C" int rt_mlp_adam(rt_mlp *m, float *theta, float *mom1, float *mom2,
     const double c2 = 1.0 - pow(beta2, double(step));
     hipLaunchKernelGGL(mlp_adam_kernel, dim3((MLP_NPARAM + 255) / 256), dim3(256), 0,
                        m->stream, theta, mom1, mom2, grad, float(lr), float(beta1),
-                       float(beta2), float(eps), float(c1), float(c2));
+                       float(beta2), float(1.0 - beta1), float(1.0 - beta2), float(eps),
+                       float(c1), float(c2));
     return hipGetLastError() == hipSuccess ? RT_OK : RT_E_HIP;
 }
 

@@ -22,7 +22,10 @@ constexpr double KB = 1.380649e-16;
 constexpr double EV = 1.602176634e-12;
 constexpr double E_ION_EV = 13.6;
 constexpr int MAX_NSUB = 4096;
-constexpr int ZC_DEFAULT = 32;
+#ifndef RT_M1_ZC
+#define RT_M1_ZC 32
+#endif
+constexpr int ZC_DEFAULT = RT_M1_ZC;  // planes per block along z
 
 struct Ev {
     hipEvent_t a, b;
@@ -45,7 +48,7 @@ struct rt_ctx {
     double *d_part = nullptr;
     int npart = 0;
     double *d_acc = nullptr;
-    double t = 0.0, emitted = 0.0, photons_initial = 0.0;
+    double t = 0.0, emitted = 0.0, photons_initial = 0.0, nh_sum = 0.0;
     int64_t steps = 0;
     int64_t hist_host[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     bool prof = false;
@@ -186,6 +189,7 @@ extern "C" int rt_init(const rt_params *params, const rt_fields *fields, void *h
     }
     const double vol = params->dx_cm * params->dx_cm * params->dx_cm;
     c->photons_initial = acc[ACC_CUR + R_N] * vol;
+    c->nh_sum = acc[ACC_CUR + R_NH];
     *out = c;
     return RT_OK;
 }
@@ -306,6 +310,8 @@ static void fill_args(const rt_ctx *c, double dt, int nsub, StepArgs &a)
     a.mixed = p.prec == RT_PREC_MIXED;
     a.adaptive = p.sub == RT_SUB_ADAPTIVE;
     a.nsub = nsub;
+    a.any_outflow = 0;
+    for (int f = 0; f < 6; ++f) a.any_outflow |= p.bc[f] == RT_BC_OUTFLOW ? 1 : 0;
     const double c_ = p.c_cms;
     const double eheat = (p.sigma_e * p.egamma_eV / p.sigma_n - E_ION_EV) * EV;
     const double T_h = eheat / (1.5 * KB);
@@ -426,7 +432,7 @@ extern "C" int rt_reduce(rt_ctx *c, rt_reductions *out)
     memset(out, 0, sizeof(*out));
     out->t = c->t;
     out->xhi_vol = acc[ACC_CUR + R_XHI] / ncell;
-    out->xhi_mass = acc[ACC_CUR + R_NHXHI] / acc[ACC_CUR + R_NH];
+    out->xhi_mass = acc[ACC_CUR + R_NHXHI] / c->nh_sum;
     out->gamma_vol = p.c_cms * p.sigma_n * acc[ACC_CUR + R_N] / ncell;
     out->photons_initial = c->photons_initial;
     out->photons_emitted = c->emitted;

@@ -98,19 +98,21 @@ struct ChemK {
     R dt, hfix, csig, T_h, T_floor, sub_eps;
 };
 
-// shortest e-folding time of xHI and of the internal energy (adaptive mode)
+// Adaptive sub-cycle time scale: the shorter of xHI / (gross xHI rate) and
+// u / (heating + cooling rate).  Gross rates keep it well conditioned near
+// equilibrium, where the net rate is a small difference of large terms.
 template <typename R>
 __device__ __forceinline__ R chem_timescale(int chem, const ChemK<R> &K, const RateSet &rs,
                                             R nH, R N, R xHI, R T)
 {
     R x = R(1) - xHI;
     R g = K.csig * N;
-    R dxh = R(rs.alpha) * nH * x * x - (g + R(rs.beta) * nH * x) * xHI;
+    R gx = R(rs.alpha) * nH * x * x + (g + R(rs.beta) * nH * x) * xHI;
     R t = R(3.0e38f);
-    if (dxh != R(0)) t = xHI * frcp(fabs(dxh));
+    if (gx > R(0)) t = xHI * frcp(gx);
     if (chem == RT_CHEM_FULL) {
-        R du = g * xHI * K.T_h - nH * (x * x * R(rs.crb) + x * xHI * R(rs.cci));
-        if (du != R(0)) t = rmin(t, (R(1) + x) * T * frcp(fabs(du)));
+        R gu = g * xHI * K.T_h + nH * (x * x * R(rs.crb) + x * xHI * R(rs.cci));
+        if (gu > R(0)) t = rmin(t, (R(1) + x) * T * frcp(gu));
     }
     return t;
 }
@@ -153,25 +155,29 @@ __device__ __forceinline__ int chem_cell(int chem, int nsub, int adaptive, float
         }
         // photoionisation: remaining photons Nn and neutrals un solve
         // a un Nn = N - Nn, un - Nn = nHI - N; each root taken in the
-        // cancellation-free form for its sign of aD.
+        // cancellation-free form for its sign of aD.  Without photons
+        // nothing is absorbed and xHI is left exactly as it is.
         const R x0 = R(1) - xHI;
-        const R aN = a * N, aH = a * nHI, aD = aH - aN;
-        const R opd = R(1) + aD;
-        const R s = fsqrt(opd * opd + R(4) * aN);
-        R Nn, un;
-        if (aD >= R(0)) {
-            Nn = R(2) * N * frcp(opd + s);
-            un = Nn + (nHI - N);
-        } else {
-            un = R(2) * nHI * frcp((R(1) - aD) + s);
-            Nn = un - (nHI - N);
+        R Pd = R(0), xh = xHI;
+        if (N > R(0)) {
+            const R aN = a * N, aH = a * nHI, aD = aH - aN;
+            const R opd = R(1) + aD;
+            const R s = fsqrt(opd * opd + R(4) * aN);
+            R Nn, un;
+            if (aD >= R(0)) {
+                Nn = R(2) * N * frcp(opd + s);
+                un = Nn + (nHI - N);
+            } else {
+                un = R(2) * nHI * frcp((R(1) - aD) + s);
+                Nn = un - (nHI - N);
+            }
+            Nn = rmin(rmax(Nn, R(0)), N);
+            un = rmin(rmax(un, R(0)), nHI);
+            Pd = R(2) * aN * nHI * frcp(R(1) + aN + aH + s);
+            absorbed += N - Nn;
+            N = Nn;
+            xh = un * inv_nH;
         }
-        Nn = rmin(rmax(Nn, R(0)), N);
-        un = rmin(rmax(un, R(0)), nHI);
-        const R Pd = R(2) * aN * nHI * frcp(R(1) + aN + aH + s);
-        absorbed += N - Nn;
-        N = Nn;
-        const R xh = un * inv_nH;
 
         // recombination (case B) and collisional ionisation
         if (!have) rs = rates_f32(float(T), inv15kB);

@@ -49,7 +49,7 @@ struct StepArgs {
     uint32_t plane;                  // nx * ny
     int ntx, nty, nzc, zc, nblocks;
     int bc[6];
-    int chem, mixed, adaptive, nsub;
+    int chem, mixed, adaptive, nsub, any_outflow;
     // FP32 constants
     float c, inv_c, half_c, half_c2, k1, dt, csig, T_h, inv15kB, T_floor,
         sub_eps, xhi_thr;

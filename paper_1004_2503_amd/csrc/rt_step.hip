@@ -21,6 +21,10 @@
 
 #include "mlp_device.h"
 
+#ifndef RT_M1_NT_STORES
+#define RT_M1_NT_STORES 0
+#endif
+
 namespace rtk {
 
 // ------------------------------------------------------ boundary mapping
@@ -51,6 +55,17 @@ __device__ __forceinline__ Map1 map_coord(int g, int n, int bc_lo, int bc_hi)
     return m;
 }
 
+// Results are not re-read by this kernel: stream them past the caches so
+// that L2 keeps the halo rows shared by neighbouring tiles.
+__device__ __forceinline__ void store_out(float *p, float v)
+{
+#if RT_M1_NT_STORES
+    __builtin_nontemporal_store(v, p);
+#else
+    *p = v;
+#endif
+}
+
 struct Cell4 {
     float N, Fx, Fy, Fz;
 };
@@ -67,8 +82,10 @@ __device__ __forceinline__ Cell4 load4(const StepArgs &A, uint32_t i, float sx, 
 }
 
 // ------------------------------------------------------ fused step kernel
+// Exact forms: at most 128 VGPRs so that two 512-thread blocks (4 waves per
+// SIMD) share a CU; the surrogate form needs more and runs one block.
 template <bool MIXED, bool SURR>
-__global__ __launch_bounds__(NTHREADS) void m1_step_kernel(StepArgs A)
+__global__ __launch_bounds__(NTHREADS, SURR ? 2 : 4) void m1_step_kernel(StepArgs A)
 {
     constexpr int SW = TX + 2;
     __shared__ __attribute__((aligned(16))) __bf16 s_pk[SURR ? PK_FWD * 8 : 8];
@@ -134,7 +151,7 @@ __global__ __launch_bounds__(NTHREADS) void m1_step_kernel(StepArgs A)
     const int sp_end = A.src_ptr[tile + 1];
 
     // FP64 accumulators
-    double acc_xhi = 0.0, acc_nhxhi = 0.0, acc_nh = 0.0, acc_N = 0.0;
+    double acc_xhi = 0.0, acc_nhxhi = 0.0, acc_N = 0.0;
     double acc_abs = 0.0, acc_esc = 0.0, acc_floor = 0.0;
     int n_bad = 0, n_fp64 = 0, n_fb = 0;
     __shared__ int shist[8];
@@ -249,12 +266,14 @@ __global__ __launch_bounds__(NTHREADS) void m1_step_kernel(StepArgs A)
         // photons through outflow faces: the face flux against the copied
         // image equals the edge cell's own normal flux
         float esc = 0.0f;
-        if (gx == 0 && A.bc[0] == RT_BC_OUTFLOW) esc -= cur.Fx;
-        if (gx == A.nx - 1 && A.bc[1] == RT_BC_OUTFLOW) esc += cur.Fx;
-        if (gy == 0 && A.bc[2] == RT_BC_OUTFLOW) esc -= cur.Fy;
-        if (gy == A.ny - 1 && A.bc[3] == RT_BC_OUTFLOW) esc += cur.Fy;
-        if (z == 0 && A.bc[4] == RT_BC_OUTFLOW) esc -= cur.Fz;
-        if (z == A.nz - 1 && A.bc[5] == RT_BC_OUTFLOW) esc += cur.Fz;
+        if (A.any_outflow) {
+            if (gx == 0 && A.bc[0] == RT_BC_OUTFLOW) esc -= cur.Fx;
+            if (gx == A.nx - 1 && A.bc[1] == RT_BC_OUTFLOW) esc += cur.Fx;
+            if (gy == 0 && A.bc[2] == RT_BC_OUTFLOW) esc -= cur.Fy;
+            if (gy == A.ny - 1 && A.bc[3] == RT_BC_OUTFLOW) esc += cur.Fy;
+            if (z == 0 && A.bc[4] == RT_BC_OUTFLOW) esc -= cur.Fz;
+            if (z == A.nz - 1 && A.bc[5] == RT_BC_OUTFLOW) esc += cur.Fz;
+        }
 
         // guards: N >= 0, |F| <= c N
         float flo = 0.0f;
@@ -353,7 +372,10 @@ __global__ __launch_bounds__(NTHREADS) void m1_step_kernel(StepArgs A)
                 pabs = Ph;
             }
         }
-        if (A.chem != RT_CHEM_OFF && fallback) {
+        // Phi leaves a dark, fully neutral cell exactly as it is; a
+        // wavefront of such cells branches around the chemistry entirely
+        const bool dark = !(Nt > 0.0f) && c_xh >= 1.0f;
+        if (A.chem != RT_CHEM_OFF && fallback && !dark) {
             if (MIXED && c_xh < A.xhi_thr) {
                 double Nd = Nt, xd = c_xh, Td = c_T, ad = 0.0;
                 ncyc = chem_cell<double>(A.chem, A.nsub, A.adaptive, A.inv15kB, Kd,
@@ -379,25 +401,24 @@ __global__ __launch_bounds__(NTHREADS) void m1_step_kernel(StepArgs A)
 
         if (active) {
             const uint32_t i = uint32_t(gy) * uint32_t(A.nx) + uint32_t(gx) + uint32_t(z) * plane;
-            A.No[i] = Nn;
-            A.Fxo[i] = Fxt;
-            A.Fyo[i] = Fyt;
-            A.Fzo[i] = Fzt;
-            A.xHI[i] = xh;
-            A.T[i] = Tc;
+            store_out(&A.No[i], Nn);
+            store_out(&A.Fxo[i], Fxt);
+            store_out(&A.Fyo[i], Fyt);
+            store_out(&A.Fzo[i], Fzt);
+            store_out(&A.xHI[i], xh);
+            store_out(&A.T[i], Tc);
             acc_xhi += double(xh);
-            acc_nhxhi += double(c_nh) * double(xh);
-            acc_nh += double(c_nh);
+            acc_nhxhi = fma(double(c_nh), double(xh), acc_nhxhi);
             acc_N += double(Nn);
             acc_abs += pabs;
-            acc_esc += double(esc);
-            acc_floor += double(flo);
-            // inputs too: the clamps of Phi would turn a NaN into a bound
-            const bool fin = isfinite(Nn) && isfinite(Fxt) && isfinite(Fyt) &&
-                             isfinite(Fzt) && isfinite(xh) && isfinite(Tc) &&
-                             isfinite(cur.N) && isfinite(cur.Fx) && isfinite(cur.Fy) &&
-                             isfinite(cur.Fz) && isfinite(c_xh) && isfinite(c_T) &&
-                             isfinite(c_nh);
+            if (A.any_outflow) acc_esc += double(esc);
+            if (flo > 0.0f) acc_floor += double(flo);
+            // 0 * v is NaN exactly when v is infinite or NaN; inputs are
+            // checked too, since the clamps of Phi would turn a NaN into a bound
+            float z0 = 0.0f * Nn + 0.0f * Fxt + 0.0f * Fyt + 0.0f * Fzt + 0.0f * xh + 0.0f * Tc;
+            z0 += 0.0f * cur.N + 0.0f * cur.Fx + 0.0f * cur.Fy + 0.0f * cur.Fz + 0.0f * c_xh +
+                  0.0f * c_T + 0.0f * c_nh;
+            const bool fin = z0 == 0.0f;
             n_bad += fin ? 0 : 1;
             n_fp64 += used64 ? 1 : 0;
             n_fb += (SURR && fallback && A.chem != RT_CHEM_OFF) ? 1 : 0;
@@ -427,7 +448,7 @@ __global__ __launch_bounds__(NTHREADS) void m1_step_kernel(StepArgs A)
     double v[NRED];
     v[R_XHI] = acc_xhi;
     v[R_NHXHI] = acc_nhxhi;
-    v[R_NH] = acc_nh;
+    v[R_NH] = 0.0;  // static: summed once at rt_init
     v[R_N] = acc_N;
     v[R_ABS] = acc_abs * A.vol;
     v[R_ESC] = acc_esc * A.esc_scale;

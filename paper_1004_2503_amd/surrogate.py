@@ -115,7 +115,7 @@ def fit(X, Y, steps: int = 3000, batch: int = 65536, lr: float = 2e-3, seed: int
             rt.check(rt.rt_mlp_grad(h, theta, xb, yb, grad, loss), "rt_mlp_grad")
             lr_t = lr * 0.5 * (1.0 + math.cos(math.pi * step / steps)) + 1e-5
             rt.check(rt.rt_mlp_adam(h, theta, m1, m2, grad, step, lr_t), "rt_mlp_adam")
-            if step % log_every == 0 or step == steps:
+            if step == 1 or step % log_every == 0 or step == steps:
                 lv = float(loss.item())
                 hist.append((step, lv, time.time() - t0))
                 if verbose:

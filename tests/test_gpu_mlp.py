@@ -49,12 +49,25 @@ def test_chem_apply_matches_oracle(chem, prec, sub, nsub):
     op = oracle.make_params((1, 1, 1), 1e21, chem=getattr(oracle, "CHEM_" + chem),
                             sub=getattr(oracle, "SUB_" + sub))
     worst = np.zeros(3)
+    errs = np.zeros((n, 3))
     for i in range(n):
         oN, _, ox, oT, _, onc = oracle.chem_cell(op, float(dt[i]), nsub, float(nH[i]),
                                                  float(N[i]), [0, 0, 0], float(xHI[i]),
                                                  float(T[i]))
         eN = abs(gN[i] - oN) / max(float(N[i]), 1e-30)
-        worst = np.maximum(worst, [eN, abs(gx[i] - ox), abs(gT[i] - oT) / oT])
+        errs[i] = [eN, abs(gx[i] - ox), abs(gT[i] - oT) / oT]
+        worst = np.maximum(worst, errs[i])
+    if not (worst[0] <= 1e-4 and worst[1] <= 1e-3 and worst[2] <= 1e-3):
+        # name the worst cell of each field before failing
+        for f in range(3):
+            i = int(np.argmax(errs[:, f]))
+            oN, _, ox, oT, _, onc = oracle.chem_cell(op, float(dt[i]), nsub, float(nH[i]),
+                                                     float(N[i]), [0, 0, 0], float(xHI[i]),
+                                                     float(T[i]))
+            print(f"field {f}: cell {i} in nH={nH[i]:.6e} N={N[i]:.6e} xHI={xHI[i]:.6e} "
+                  f"T={T[i]:.6e} dt={dt[i]:.6e} | gpu N={gN[i]:.6e} x={gx[i]:.6e} "
+                  f"T={gT[i]:.6e} | orc N={oN:.6e} x={ox:.6e} T={oT:.6e} nc={onc}",
+                  flush=True)
     assert worst[0] <= 1e-4 and worst[1] <= 1e-3 and worst[2] <= 1e-3, worst
     if sub == "FIXED":
         assert np.all(nc.cpu().numpy() == nsub)
@@ -132,5 +145,7 @@ def test_mlp_adam_matches_reference():
     ref, rm, rv = mlp.adam_step(theta.astype(np.float64), m1.astype(np.float64),
                                 m2.astype(np.float64), g.astype(np.float64), 7, 1e-3)
     assert np.allclose(tt.cpu().numpy(), ref, rtol=1e-5, atol=1e-7)
-    assert np.allclose(tm1.cpu().numpy(), rm, rtol=1e-5, atol=1e-12)
+    # the moments mix terms of opposite sign: FP32 rounding of each term (~6e-8
+    # of 1e-3) bounds the absolute error where they cancel
+    assert np.allclose(tm1.cpu().numpy(), rm, rtol=1e-5, atol=1e-9)
     assert np.allclose(tm2.cpu().numpy(), rv, rtol=1e-5, atol=1e-14)

@@ -46,10 +46,13 @@ class Params(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
                 ("nz", ctypes.c_int32), ("bc", ctypes.c_int32 * 6),
                 ("chem", ctypes.c_int32), ("sub", ctypes.c_int32),
+                ("clump", ctypes.c_int32),
                 ("dx", ctypes.c_double), ("c", ctypes.c_double),
                 ("sigma_n", ctypes.c_double), ("sigma_e", ctypes.c_double),
                 ("egamma_eV", ctypes.c_double), ("T_floor", ctypes.c_double),
-                ("sub_eps", ctypes.c_double)]
+                ("sub_eps", ctypes.c_double),
+                ("cr_norm", ctypes.c_double), ("cr_exp", ctypes.c_double),
+                ("ci_norm", ctypes.c_double), ("ci_exp", ctypes.c_double)]
 
 
 _lib = None
@@ -68,6 +71,8 @@ def lib():
         L.orc_eddington.argtypes = [ctypes.c_double] * 5 + [dp]
         L.orc_rates.restype = None
         L.orc_rates.argtypes = [ctypes.c_double, dp]
+        L.orc_clumping.restype = None
+        L.orc_clumping.argtypes = [ctypes.POINTER(Params), ctypes.c_double, dp, dp]
         L.orc_heat_per_ionisation_erg.restype = ctypes.c_double
         L.orc_heat_per_ionisation_erg.argtypes = [ctypes.POINTER(Params)]
         L.orc_chem_cell.restype = None
@@ -98,11 +103,15 @@ def _ptr(a):
 
 def make_params(shape, dx, bc=(0,) * 6, chem=CHEM_FULL, sub=SUB_FIXED,
                 c=C_LIGHT, sigma_n=SIGMA_N, sigma_e=SIGMA_E, egamma_eV=EGAMMA_EV,
-                T_floor=10.0, sub_eps=0.1) -> Params:
-    """``shape`` is (nz, ny, nx), the numpy order of every field."""
+                T_floor=10.0, sub_eps=0.1, clump=None) -> Params:
+    """``shape`` is (nz, ny, nx), the numpy order of every field.  ``clump``
+    is None (no subgrid clumping) or (cr_norm, cr_exp, ci_norm, ci_exp):
+    C_R = max(1, cr_norm nH^cr_exp), C_I = ci_norm nH^ci_exp."""
     nz, ny, nx = shape
-    return Params(nx, ny, nz, (ctypes.c_int32 * 6)(*bc), chem, sub, dx, c,
-                  sigma_n, sigma_e, egamma_eV, T_floor, sub_eps)
+    cl = (0.0, 0.0, 1.0, 0.0) if clump is None else tuple(float(v) for v in clump)
+    return Params(nx, ny, nz, (ctypes.c_int32 * 6)(*bc), chem, sub,
+                  0 if clump is None else 1, dx, c,
+                  sigma_n, sigma_e, egamma_eV, T_floor, sub_eps, *cl)
 
 
 # ---------------------------------------------------------------- closure
@@ -118,6 +127,13 @@ def eddington(N, F, c=C_LIGHT) -> np.ndarray:
                         _ptr(out))
     xx, yy, zz, xy, xz, yz = out
     return np.array([[xx, xy, xz], [xy, yy, yz], [xz, yz, zz]])
+
+
+def clumping(params: Params, nH: float):
+    """(C_R, C_I) of a cell of density nH (Sec. 4.1 clumping factors)."""
+    cr, ci = ctypes.c_double(), ctypes.c_double()
+    lib().orc_clumping(ctypes.byref(params), float(nH), ctypes.byref(cr), ctypes.byref(ci))
+    return cr.value, ci.value
 
 
 def rates(T: float) -> np.ndarray:

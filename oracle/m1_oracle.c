@@ -109,12 +109,25 @@ double orc_heat_per_ionisation_erg(const orc_params *p)
     return (p->sigma_e * p->egamma_eV / p->sigma_n - E_ION_EV) * EV;
 }
 
+/* Clumping factors of a cell of density nH (see orc_params). */
+void orc_clumping(const orc_params *p, double nH, double *C_R, double *C_I)
+{
+    if (!p->clump) {
+        *C_R = 1.0;
+        *C_I = 1.0;
+        return;
+    }
+    *C_R = fmax(1.0, p->cr_norm * pow(nH, p->cr_exp));
+    *C_I = p->ci_norm * pow(nH, p->ci_exp);
+}
+
 /* Net cooling rate Lambda [erg cm^-3 s^-1] for electron density ne = nHII
- * (pure hydrogen) and neutral density nHI. */
-static double cooling(const double r[6], double nHII, double nHI)
+ * (pure hydrogen) and neutral density nHI; the ne * nHII terms carry the
+ * recombination clumping factor C_R. */
+static double cooling(const double r[6], double nHII, double nHI, double C_R)
 {
     double ne = nHII;
-    return ne * nHII * r[2] + ne * nHI * (r[3] + r[4]) + ne * nHII * r[5];
+    return C_R * ne * nHII * (r[2] + r[5]) + ne * nHI * (r[3] + r[4]);
 }
 
 /* Adaptive sub-cycle time scale: the shorter of the neutral-fraction and
@@ -125,14 +138,15 @@ static double cooling(const double r[6], double nHII, double nHI)
 static double chem_timescale(const orc_params *p, double nH, double N,
                              double xHI, double T)
 {
-    double r[6];
+    double r[6], C_R, C_I;
     orc_rates(T, r);
+    orc_clumping(p, nH, &C_R, &C_I);
     double x = 1.0 - xHI;
-    double gamma = p->c * p->sigma_n * N;
-    double gross_x = r[0] * nH * x * x + (gamma + r[1] * nH * x) * xHI;
+    double gamma = C_I * p->c * p->sigma_n * N;
+    double gross_x = C_R * r[0] * nH * x * x + (gamma + r[1] * nH * x) * xHI;
     double u = 1.5 * KB * nH * (1.0 + x) * T;
     double gross_u = gamma * nH * xHI * orc_heat_per_ionisation_erg(p) +
-                     cooling(r, nH * x, nH * xHI);
+                     cooling(r, nH * x, nH * xHI, C_R);
     double t = INFINITY;
     if (gross_x > 0.0) t = fmin(t, xHI / gross_x);
     if (p->chem == ORC_CHEM_FULL && gross_u > 0.0) t = fmin(t, u / gross_u);
@@ -154,12 +168,16 @@ static double chem_timescale(const orc_params *p, double nH, double N,
  *   3. internal energy u = 3/2 kB nH (1 + x) T gains P * e_heat and is
  *      cooled semi-implicitly, u <- (u + H)/(1 + h Lambda/u), with the rates
  *      at the sub-cycle's starting temperature.
+ * With subgrid clumping (Sec. 4.1) a becomes C_I a and the ne nHII terms
+ * (alpha_B, recombination cooling, bremsstrahlung) are multiplied by C_R.
  * --------------------------------------------------------------------- */
 void orc_chem_cell(const orc_params *p, double dt, int32_t nsub, double nH,
                    double *N, double *Fx, double *Fy, double *Fz, double *xHI,
                    double *T, double *absorbed, int32_t *ncycles)
 {
     double eheat = orc_heat_per_ionisation_erg(p);
+    double C_R, C_I;
+    orc_clumping(p, nH, &C_R, &C_I);
     double remaining = dt;
     int32_t it = 0;
     *absorbed = 0.0;
@@ -176,7 +194,7 @@ void orc_chem_cell(const orc_params *p, double dt, int32_t nsub, double nH,
         remaining -= h;
         if (it == nsub - 1 || remaining < 0.0) remaining = 0.0;
 
-        double a = p->c * p->sigma_n * h;
+        double a = C_I * p->c * p->sigma_n * h;
         double x0 = 1.0 - *xHI;
         double nHI = nH * (*xHI);
 
@@ -204,7 +222,7 @@ void orc_chem_cell(const orc_params *p, double dt, int32_t nsub, double nH,
         double r[6];
         orc_rates(*T, r);
         double x = 1.0 - *xHI;
-        double xn = (*xHI + r[0] * nH * x * x * h) / (1.0 + r[1] * nH * x * h);
+        double xn = (*xHI + C_R * r[0] * nH * x * x * h) / (1.0 + r[1] * nH * x * h);
         if (xn < XHI_MIN) xn = XHI_MIN;
         if (xn > 1.0) xn = 1.0;
         *xHI = xn;
@@ -214,7 +232,7 @@ void orc_chem_cell(const orc_params *p, double dt, int32_t nsub, double nH,
             double x1 = 1.0 - xn;
             double u = 1.5 * KB * nH * (1.0 + x0) * (*T);
             double H = Pabs * eheat;
-            double lam = cooling(r, nH * x1, nH * xn);
+            double lam = cooling(r, nH * x1, nH * xn, C_R);
             u = (u + H) / (1.0 + h * lam / u);
             double Tn = u / (1.5 * KB * nH * (1.0 + x1));
             *T = (Tn > p->T_floor) ? Tn : p->T_floor;

@@ -58,11 +58,21 @@ extern "C" {
 #define ORC_SUB_FIXED 0
 #define ORC_SUB_ADAPTIVE 1
 
+/* Subgrid clumping (Sec. 4.1, "Clumping factors"): the cell-averaged
+ * chemistry equation carries a recombination clumping factor C_R and a
+ * photon/neutral cross clumping factor C_I, fitted in the paper as power
+ * laws of the cell density.  Here
+ *   C_R(nH) = max(1, cr_norm * nH^cr_exp)   (a ratio <y^2>/<y>^2 >= 1),
+ *   C_I(nH) = ci_norm * nH^ci_exp,          nH in cm^-3.
+ * C_I multiplies the photoionisation (and so the photon absorption) rate;
+ * C_R multiplies every term in ne * nHII: case-B recombination, its
+ * cooling and bremsstrahlung.  clump = 0 means C_R = C_I = 1.          */
 typedef struct {
     int32_t nx, ny, nz;
     int32_t bc[6];
     int32_t chem;
     int32_t sub;
+    int32_t clump;    /* 0 off, 1 power-law clumping factors    */
     double dx;        /* cell size [cm]                         */
     double c;         /* speed of light [cm/s]                  */
     double sigma_n;   /* number-averaged cross-section [cm^2]   */
@@ -70,6 +80,7 @@ typedef struct {
     double egamma_eV; /* mean ionising photon energy [eV]       */
     double T_floor;   /* temperature floor [K]                  */
     double sub_eps;   /* adaptive sub-cycle fraction            */
+    double cr_norm, cr_exp, ci_norm, ci_exp; /* clumping laws   */
 } orc_params;
 
 /* tallies of one step, in photons (dt and cell volume folded in):
@@ -82,6 +93,7 @@ void orc_eddington(double N, double Fx, double Fy, double Fz, double c,
                    double P[6]); /* xx, yy, zz, xy, xz, yz */
 void orc_rates(double T, double r[6]);
 double orc_heat_per_ionisation_erg(const orc_params *p);
+void orc_clumping(const orc_params *p, double nH, double *C_R, double *C_I);
 
 void orc_chem_cell(const orc_params *p, double dt, int32_t nsub, double nH,
                    double *N, double *Fx, double *Fy, double *Fz, double *xHI,

@@ -130,7 +130,7 @@ def eddington(N, F, c=C_LIGHT) -> np.ndarray:
 
 
 def clumping(params: Params, nH: float):
-    """(C_R, C_I) of a cell of density nH (Sec. 4.1 clumping factors)."""
+    """(C_R, C_I) of a cell of density nH (Sec. 3.2.1 clumping factors)."""
     cr, ci = ctypes.c_double(), ctypes.c_double()
     lib().orc_clumping(ctypes.byref(params), float(nH), ctypes.byref(cr), ctypes.byref(ci))
     return cr.value, ci.value
@@ -244,8 +244,8 @@ class Grid:
 
     # ------------------------------------------------- global averages
     def reductions(self) -> dict:
-        """Volume- and mass-weighted neutral fraction (Sec. 3.1 and 3.2), the
-        volume-averaged photoionisation rate c sigma_n N (Sec. 3.1) and the
+        """Volume- and mass-weighted neutral fraction (Sec. 3.1.1-3.1.2), the
+        volume-averaged photoionisation rate c sigma_n N (Sec. 3.1.3) and the
         photon budget, all as plain FP64 sums."""
         vol = self.p.dx ** 3
         ncell = self.N.size

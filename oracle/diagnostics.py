@@ -1,9 +1,9 @@
 """FP64 reference of the run diagnostics (TEST INFRASTRUCTURE ONLY: loaded by
 the tests and nothing else; shares no code with the HIP path).
 
-Sec. 3.4 studies the distribution of cells over density and neutral
+Sec. 3.1.5 studies the distribution of cells over density and neutral
 fraction, (1 - x)(nH), and over density and ionising intensity, J21(nH),
-together with the mean of each quantity per density bin.  Sec. 3.3 measures
+together with the mean of each quantity per density bin.  Sec. 3.1.4 measures
 the Thomson optical depth tau = c sigma_T int n_e dt.
 
 Binning (the definition both sides implement): nb bins between 10^lo and
@@ -59,7 +59,7 @@ def photoionisation_rate(N, c, sigma_n):
 
 def thomson_increment(nH, xHI, dt, c):
     """c sigma_T <n_e> dt with n_e = nH (1 - xHI), the volume mean over
-    cells (Sec. 3.3, one step of the time integral)."""
+    cells (Sec. 3.1.4, one step of the time integral)."""
     nH = np.asarray(nH, dtype=np.float64)
     ne = nH * (1.0 - np.asarray(xHI, dtype=np.float64))
     return c * SIGMA_T * float(ne.mean()) * dt

@@ -168,7 +168,7 @@ static double chem_timescale(const orc_params *p, double nH, double N,
  *   3. internal energy u = 3/2 kB nH (1 + x) T gains P * e_heat and is
  *      cooled semi-implicitly, u <- (u + H)/(1 + h Lambda/u), with the rates
  *      at the sub-cycle's starting temperature.
- * With subgrid clumping (Sec. 4.1) a becomes C_I a and the ne nHII terms
+ * With subgrid clumping (Sec. 3.2.1) a becomes C_I a and the ne nHII terms
  * (alpha_B, recombination cooling, bremsstrahlung) are multiplied by C_R.
  * --------------------------------------------------------------------- */
 void orc_chem_cell(const orc_params *p, double dt, int32_t nsub, double nH,

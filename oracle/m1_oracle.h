@@ -58,7 +58,7 @@ extern "C" {
 #define ORC_SUB_FIXED 0
 #define ORC_SUB_ADAPTIVE 1
 
-/* Subgrid clumping (Sec. 4.1, "Clumping factors"): the cell-averaged
+/* Subgrid clumping (Sec. 3.2.1, "Clumping factors"): the cell-averaged
  * chemistry equation carries a recombination clumping factor C_R and a
  * photon/neutral cross clumping factor C_I, fitted in the paper as power
  * laws of the cell density.  Here

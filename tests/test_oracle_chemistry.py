@@ -6,7 +6,7 @@ the sub-cycled hydrogen chemistry, the cooling and the gray constants).
   * the photoionisation step: its absorbed density solves the defining
     backward-Euler relation, lies in [0, min(N, nHI)] and N - nHI is
     conserved by it;
-  * photoionisation equilibrium (Sec. 3.1 compares its runs with it): under a
+  * photoionisation equilibrium (Sec. 3.1.5 compares its runs with it): under a
     constant photon bath the fixed point tends to the closed-form equilibrium
     at first order in the sub-cycle length;
   * pure recombination: x(t) = x0 / (1 + alpha nH x0 t), first-order

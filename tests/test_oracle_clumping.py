@@ -1,4 +1,4 @@
-"""Pins of the oracle's subgrid clumping (Sec. 4.1, "Clumping factors"): the
+"""Pins of the oracle's subgrid clumping (Sec. 3.2.1, "Clumping factors"): the
 cell-averaged chemistry equation with a recombination clumping factor C_R
 on the recombination term and a cross clumping factor C_I on the
 photoionisation term, both power laws of the cell density.

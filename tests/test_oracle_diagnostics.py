@@ -1,5 +1,5 @@
-"""Pins of the oracle's run diagnostics (Sec. 3.4 distributions over density,
-Sec. 3.3 Thomson optical depth):
+"""Pins of the oracle's run diagnostics (Sec. 3.1.5 distributions over density,
+Sec. 3.1.4 Thomson optical depth):
 
   * the log-uniform edges start at 10^lo, end at 10^hi and grow by the
     constant factor 10^w;

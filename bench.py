@@ -18,6 +18,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -29,12 +30,22 @@ sys.path.insert(0, ROOT)
 BYTES_PER_CELL = 52          # read N,F,xHI,T,nH (28 B) + write N,F,xHI,T (24 B)
 HBM_PEAK_GBS = 8000.0        # MI355X HBM3E
 METRIC = "cell-updates/s (transport+chem) and % HBM peak, plain vs surrogate at 1024^3"
-KERNEL_SRC = os.path.join(ROOT, "paper_1004_2503_amd", "csrc", "rt_step.hip")
+KERNEL_SRC = [os.path.join(ROOT, "paper_1004_2503_amd", "csrc", f)
+              for f in ("rt_step.hip", "rt_device.h", "rt_internal.h", "mlp_device.h")]
 
 
 def kernel_hash() -> str:
-    with open(KERNEL_SRC, "rb") as fh:
-        return hashlib.sha256(fh.read()).hexdigest()[:16]
+    """Hash of the sources the step kernel is compiled from, with comments
+    and whitespace removed (an edit of a comment leaves the kernel as it
+    was)."""
+    h = hashlib.sha256()
+    for f in KERNEL_SRC:
+        with open(f) as fh:
+            src = fh.read()
+        src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+        src = re.sub(r"//[^\n]*", " ", src)
+        h.update(" ".join(src.split()).encode())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic(workload: str, nsub: int, prec: str):
@@ -50,9 +61,11 @@ def measured_traffic(workload: str, nsub: int, prec: str):
     return d.get("bytes_per_launch")
 
 
-def cpu_baseline(G, w, dt, nsub, budget_s: float, seed: int = 20100417):
-    """Time the FP64 oracle on sampled 32^3 sub-blocks (one step each, halo
-    taken from the same device state)."""
+def cpu_baseline(G, w, dt, nsub, budget_s: float, chem: str = "full", clump=None,
+                 seed: int = 20100417):
+    """Time the FP64 oracle on random 64^3 sub-blocks of the state (one step
+    each, halo taken from the same device state) until budget_s of oracle
+    time has been spent."""
     import torch
 
     import oracle
@@ -60,13 +73,15 @@ def cpu_baseline(G, w, dt, nsub, budget_s: float, seed: int = 20100417):
     oracle.lib()
     st = G.tensors()
     n = w.n
-    B = 32
+    B = 64
     rng = np.random.default_rng(seed)
-    p = oracle.make_params((B, B, B), w.dx, chem=oracle.CHEM_FULL)
+    ochem = {"full": oracle.CHEM_FULL, "isothermal": oracle.CHEM_ISOTHERMAL,
+             "off": oracle.CHEM_OFF}[chem]
+    p = oracle.make_params((B, B, B), w.dx, chem=ochem, clump=clump)
     cells = 0
     blocks = 0
     t_total = 0.0
-    while t_total < budget_s and blocks < 512:
+    while t_total < budget_s and blocks < 4096:
         z0, y0, x0 = (int(v) for v in rng.integers(0, n, 3))
         idx = [torch.arange(o - 1, o + B + 1, device=st["N"].device) % n for o in (z0, y0, x0)]
 
@@ -92,10 +107,11 @@ def cpu_baseline(G, w, dt, nsub, budget_s: float, seed: int = 20100417):
                       f"step each ({cells} cell-updates in {t_total:.1f} s)"}
 
 
-def surrogate_leg(args, G, w, dt, params):
+def surrogate_leg(args, G, w, dt, params, src):
     """Train the network on exact pairs sampled from the 256^3 run (several
-    dt), then time the surrogate form from the same state as the plain form
-    and compare the two after the same number of steps."""
+    dt), then time, from the same state and for the same number of steps,
+    the exact and the surrogate forms with fixed sub-cycling (nsub) and with
+    adaptive sub-cycling (10% rule, capped at --adaptive-cap)."""
     import torch
 
     from paper_1004_2503_amd import rt, surrogate
@@ -116,65 +132,114 @@ def surrogate_leg(args, G, w, dt, params):
     pexact = rt.make_params((1, 1, 1), 1.0, chem=rt.CHEM_FULL, prec=rt.PREC_MIXED,
                             sub=rt.SUB_ADAPTIVE, sub_eps=0.1)
     dts = [W.courant_dt(W.cosmo_dx(n)) for n in (256, 512, 1024)]
-    per = args.surrogate_pairs // (len(states) * len(dts))
-    Xs, Ys = [], []
-    for i, st in enumerate(states):
-        for j, d in enumerate(dts):
-            c = surrogate.sample_cells(st, per, 1000 * i + j)
-            X, Y, _ = surrogate.exact_pairs(pexact, c["nH"], c["N"], c["xHI"], c["T"],
-                                            torch.full_like(c["N"], d), 64)
-            Xs.append(X)
-            Ys.append(Y)
-    n_pairs = int(per * len(states) * len(dts))
+
+    def make_pairs(total, seed):
+        per = total // (len(states) * len(dts))
+        Xs, Ys = [], []
+        for i, st in enumerate(states):
+            for j, d in enumerate(dts):
+                c = surrogate.sample_cells(st, per, seed + 1000 * i + j)
+                X, Y, _ = surrogate.exact_pairs(pexact, c["nH"], c["N"], c["xHI"], c["T"],
+                                                torch.full_like(c["N"], d), 64)
+                Xs.append(X)
+                Ys.append(Y)
+        return torch.cat(Xs), torch.cat(Ys)
+
+    X, Y = make_pairs(args.surrogate_pairs, 0)
+    Xv, Yv = make_pairs(1_000_000, 777_000)      # held out
+    n_pairs = int(X.shape[0])
     del states
-    X, Y = torch.cat(Xs), torch.cat(Ys)
-    del Xs, Ys
     t_pairs = time.perf_counter() - t0
     s = surrogate.fit(X, Y, steps=args.surrogate_steps, batch=65536, lr=1e-3,
                       grad_blocks=1024, log_every=max(args.surrogate_steps // 6, 1),
                       verbose=False)
     t_train = time.perf_counter() - t0 - t_pairs
-    P = surrogate.predict(s, X[:1_000_000])
-    fit_dx = float((10 ** P[:, 0] - 10 ** Y[:1_000_000, 0]).abs().mean())
-    del X, Y, P
+    del X, Y
+    P = surrogate.predict(s, Xv)
+    dxv = (10 ** P[:, 0] - 10 ** Yv[:, 0]).abs()
+    held = {"pairs": int(Xv.shape[0]), "mean_abs_dxHI": float(dxv.mean()),
+            "p99_abs_dxHI": float(torch.quantile(dxv[:200_000].float(), 0.99))}
+    del Xv, Yv, P, dxv
 
-    # both forms from the current state, same steps
+    # the adaptive context starts from a copy of the same state
     snap = {k: v.clone() for k, v in G.tensors().items()}
+    pad = rt.make_params((w.n,) * 3, w.dx, chem=params.chem, prec=params.prec,
+                         sub=rt.SUB_ADAPTIVE, sub_eps=0.1)
+    Ga = rt.RTGrid(pad, snap)
+    Ga.inject_sources(*src)
     n_steps = max(args.steps // 2, 10)
     out = {}
-    for form in ("plain", "surrogate"):
-        c = G.current()                       # the buffer the next step reads
+    for form, GG, nsub, use in (("exact_fixed", G, args.nsub, False),
+                                ("surrogate_fixed", G, args.nsub, True),
+                                ("exact_adaptive", Ga, args.adaptive_cap, False),
+                                ("surrogate_adaptive", Ga, args.adaptive_cap, True)):
+        c = GG.current()                      # the buffer the next step reads
         for k in ("xHI", "T"):
-            getattr(G, k).copy_(snap[k])
+            getattr(GG, k).copy_(snap[k])
         for k in ("N", "Fx", "Fy", "Fz"):
-            getattr(G, k)[c].copy_(snap[k])
-        if form == "surrogate":
-            rt.check(rt.rt_set_surrogate(G.ctx, s.theta, s.norm_array(), 1e-3),
+            getattr(GG, k)[c].copy_(snap[k])
+        if use:
+            rt.check(rt.rt_set_surrogate(GG.ctx, s.theta, s.norm_array(), 1e-3),
                      "rt_set_surrogate")
-        r0 = G.reduce()
+        r0 = GG.reduce()
         torch.cuda.synchronize()
         ta = time.perf_counter()
-        G.step(dt, args.nsub, n_steps)
+        GG.step(dt, nsub, n_steps)
         torch.cuda.synchronize()
         tb = time.perf_counter()
-        r1 = G.reduce()
+        r1 = GG.reduce()
+        hist = [b - a for a, b in zip(r0["subcycle_hist"], r1["subcycle_hist"])]
         out[form] = dict(ms_per_step=(tb - ta) / n_steps * 1e3,
                          value=w.cells * n_steps / (tb - ta),
                          fallback_frac=(r1["n_fallback"] - r0["n_fallback"]) /
                          (w.cells * n_steps),
-                         xHI=G.xHI.clone())
-        rt.check(rt.rt_set_surrogate(G.ctx, None, None, 0.0), "rt_set_surrogate off")
-    dxm = float((out["surrogate"]["xHI"] - out["plain"]["xHI"]).abs().double().mean())
-    return {"value": out["surrogate"]["value"], "unit": "cell-updates/s",
-            "ms_per_step": out["surrogate"]["ms_per_step"],
-            "plain_ms_per_step_same_state": out["plain"]["ms_per_step"],
-            "speedup_vs_plain": out["plain"]["ms_per_step"] / out["surrogate"]["ms_per_step"],
-            "fallback_frac": out["surrogate"]["fallback_frac"],
-            "mean_abs_dxHI_vs_plain": dxm, "steps": n_steps,
+                         subcycle_hist=hist, xHI=GG.xHI.clone())
+        rt.check(rt.rt_set_surrogate(GG.ctx, None, None, 0.0), "rt_set_surrogate off")
+    Ga.close()
+    del snap
+
+    def dx(a, b):
+        return float((out[a]["xHI"] - out[b]["xHI"]).abs().double().mean())
+
+    forms = {k: {kk: vv for kk, vv in v.items() if kk != "xHI"} for k, v in out.items()}
+    ms = {k: v["ms_per_step"] for k, v in out.items()}
+    return {"value": out["surrogate_fixed"]["value"], "unit": "cell-updates/s",
+            "ms_per_step": ms["surrogate_fixed"],
+            "plain_ms_per_step_same_state": ms["exact_fixed"],
+            "speedup_vs_plain": ms["exact_fixed"] / ms["surrogate_fixed"],
+            "speedup_vs_adaptive_exact": ms["exact_adaptive"] / ms["surrogate_adaptive"],
+            "adaptive_cap": args.adaptive_cap, "forms": forms, "steps": n_steps,
+            "mean_abs_dxHI_vs_exact_after_steps": {"fixed": dx("surrogate_fixed", "exact_fixed"),
+                                                   "adaptive": dx("surrogate_adaptive",
+                                                                  "exact_adaptive")},
+            "held_out": held,
             "train": {"pairs": n_pairs, "adam_steps": args.surrogate_steps,
                       "pair_gen_s": t_pairs, "train_s": t_train,
-                      "loss_first_last": [s.history[0][1], s.history[-1][1]],
-                      "fit_mean_abs_dxHI": fit_dx}}
+                      "loss_first_last": [s.history[0][1], s.history[-1][1]]}}
+
+
+def diagnostics_leg(G, w, reps: int = 5):
+    """Time rt_histogram (Sec. 3.1.5 distributions, 64 x 64 bins) over the
+    whole grid for both quantities: one pass reading nH and xHI or N, 8
+    bytes per cell; the call includes its small host copies and a stream
+    wait.  Also reports the Thomson depth accumulated by the run."""
+    import torch
+
+    from paper_1004_2503_amd import rt
+
+    out = {}
+    for name, q, yr in (("xHI", rt.HQ_XHI, (-7.0, 0.5, 64)),
+                        ("gamma", rt.HQ_GAMMA, (-18.0, -8.0, 64))):
+        G.histogram(q, (-6.0, 1.0, 64), yr)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            counts, _ = G.histogram(q, (-6.0, 1.0, 64), yr)
+        dt = (time.perf_counter() - t0) / reps
+        out[name] = {"ms": dt * 1e3, "GBs": 8.0 * w.cells / dt / 1e9,
+                     "nonzero_bins": int(np.count_nonzero(counts))}
+    out["tau_e"] = G.reduce()["tau_e"]
+    return out
 
 
 def main():
@@ -187,6 +252,8 @@ def main():
     ap.add_argument("--nsub", type=int, default=1)
     ap.add_argument("--prec", default="mixed", choices=["fp32", "mixed"])
     ap.add_argument("--chem", default="full", choices=["full", "isothermal", "off"])
+    ap.add_argument("--clump", default=None, choices=["A", "B"],
+                    help="subgrid clumping laws in the chemistry (default: none)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="instead of the step, time a plain device copy of MIB MiB "
@@ -196,7 +263,9 @@ def main():
                     help="also train the learned chemistry on exact pairs from the 256^3 "
                          "run and time the surrogate form on the same workload")
     ap.add_argument("--surrogate-pairs", type=int, default=10_000_000)
-    ap.add_argument("--surrogate-steps", type=int, default=3000)
+    ap.add_argument("--surrogate-steps", type=int, default=20000)
+    ap.add_argument("--adaptive-cap", type=int, default=32,
+                    help="sub-cycle cap of the adaptive forms in the surrogate comparison")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -237,7 +306,8 @@ def main():
           file=sys.stderr, flush=True)
 
     chem = {"full": rt.CHEM_FULL, "isothermal": rt.CHEM_ISOTHERMAL, "off": rt.CHEM_OFF}[args.chem]
-    params = rt.make_params((w.n,) * 3, w.dx, chem=chem, prec=prec)
+    clump = None if args.clump is None else W.CLUMP_LAWS[args.clump]
+    params = rt.make_params((w.n,) * 3, w.dx, chem=chem, prec=prec, clump=clump)
     T0 = torch.full((w.n,) * 3, w.T0, dtype=torch.float32, device=dev)
     G = rt.RTGrid(params, dict(nH=nH, T=T0), device=dev)
     del nH, T0
@@ -267,13 +337,15 @@ def main():
             "kernel": "m1_step_kernel", "avg_launch_ms": avg_ms,
             "bytes_per_cell": BYTES_PER_CELL}
 
+    diag = diagnostics_leg(G, w)
+
     surr = None
     if args.surrogate:
-        surr = surrogate_leg(args, G, w, dt, params)
+        surr = surrogate_leg(args, G, w, dt, params, (ijk, ndot))
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(G, w, dt, args.nsub, args.cpu_seconds)
+        cpu = cpu_baseline(G, w, dt, args.nsub, args.cpu_seconds, args.chem, clump)
     G.close()
 
     out = {
@@ -291,12 +363,16 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{w.name}: {w.n}^3 lognormal (sigma_ln 1.5, mean nH 2e-4), "
                                f"{len(ijk)} sources, plain exact chemistry"
-                               + ("" if args.chem == "full" else f" (chemistry {args.chem})"),
+                               + ("" if args.chem == "full" else f" (chemistry {args.chem})")
+                               + ("" if clump is None else
+                                  f", subgrid clumping {args.clump} laws {clump}"),
                    "grid": w.n, "sources": len(ijk), "nsub": args.nsub, "chem": args.chem,
+                   "clump": args.clump,
                    "precision": args.prec, "dt_s": dt, "dx_cm": w.dx,
                    "parallelism": "single GPU, whole grid"},
         "roofline": roof,
         "cpu_baseline": cpu,
+        "diagnostics": diag,
         "surrogate": surr,
         "hbm_frac_whole_step": BYTES_PER_CELL * value / (HBM_PEAK_GBS * 1e9),
         "state_after": {"xhi_vol": red["xhi_vol"], "xhi_mass": red["xhi_mass"],

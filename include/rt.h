@@ -94,14 +94,24 @@ typedef struct {
  * 20.27 eV); c_cms the speed of light used by the transport; T_floor [K]
  * bounds T from below; sub_eps the adaptive sub-cycle fraction;
  * xhi_fp64_thr the neutral fraction below which RT_PREC_MIXED switches a
- * cell's chemistry to FP64. */
+ * cell's chemistry to FP64.
+ *
+ * Subgrid clumping (Sec. 3.2.1, clumping factors of the cell-averaged
+ * chemistry equation), active when clump = 1, with nH in cm^-3:
+ *   C_R(nH) = max(1, clump_cr_norm * nH^clump_cr_exp)  recombination factor,
+ *   C_I(nH) = clump_ci_norm * nH^clump_ci_exp           photoionisation factor.
+ * C_I multiplies the photoionisation rate (and so the photons absorbed);
+ * C_R multiplies the terms in ne*nHII (case-B recombination, its cooling,
+ * bremsstrahlung).  clump = 0 leaves the operator unclumped and the four
+ * doubles unused.  The paper fits C_R ~ nH^0.7 and C_I ~ nH^0.1-0.2 (or
+ * C_I = 1 with C_R ~ nH^2.5); it shows the normalisations only in figures. */
 typedef struct {
     int32_t nx, ny, nz;
     int32_t bc[6];
     int32_t chem;
     int32_t prec;
     int32_t sub;
-    int32_t reserved; /* must be 0 */
+    int32_t clump;    /* 0 off, 1 power-law clumping factors */
     double dx_cm;
     double c_cms;
     double sigma_n;
@@ -110,9 +120,11 @@ typedef struct {
     double T_floor;
     double sub_eps;
     double xhi_fp64_thr;
+    double clump_cr_norm, clump_cr_exp; /* C_R law (clump = 1) */
+    double clump_ci_norm, clump_ci_exp; /* C_I law (clump = 1) */
 } rt_params;
 
-/* Global averages (Sec. 3.1 and 3.2 use the volume- and mass-weighted
+/* Global averages (Sec. 3.1.1-3.1.3 use the volume- and mass-weighted
  * neutral fractions and the volume-averaged photoionisation rate) and the
  * photon budget.  Sums are accumulated in FP64.  Photon counts are absolute
  * numbers of photons: photons_initial + photons_emitted + photons_floor =
@@ -134,6 +146,8 @@ typedef struct {
     int64_t n_fallback;      /* surrogate cell-steps sent to the exact path */
     int64_t subcycle_hist[8]; /* cell-steps by sub-cycle count: 1, 2-3,
                                  4-7, 8-15, 16-31, 32-63, 64-127, >=128     */
+    double tau_e;            /* Thomson depth c sigma_T sum_steps <nH (1 - xHI)> dt,
+                                with the state at the end of each step (Sec. 3.1.4) */
 } rt_reductions;
 
 /* Create a context for the grid described by `params` over the caller's
@@ -186,6 +200,26 @@ int rt_set_surrogate(rt_ctx *ctx, const float *theta, const float *norm, double 
  * RT_E_NONFINITE (with *out filled) if any step produced a non-finite
  * value. */
 int rt_reduce(rt_ctx *ctx, rt_reductions *out);
+
+/* Quantities binned by rt_histogram against the cell density. */
+#define RT_HQ_XHI 0   /* neutral fraction xHI                     */
+#define RT_HQ_GAMMA 1 /* photoionisation rate c sigma_n N [1/s]   */
+#define RT_HIST_MAX_BINS 8192 /* nbx * nby                         */
+
+/* Distribution of the current cells over density and a quantity (Sec. 3.1.5
+ * studies xHI(nH) and J21(nH) this way, with the mean per density bin).
+ * Bins: nbx bins in nH between 10^lox and 10^hix and nby bins in q between
+ * 10^loy and 10^hiy, uniform in log10, with FP64 edges e_k = pow(10, lo +
+ * k w), w = (hi - lo) / nb; a value falls in the largest k < nb with
+ * e_k <= value, values below e_0 (zero included) in bin 0.  q = xHI, or
+ * (c_cms * sigma_n) * N evaluated in FP64 for RT_HQ_GAMMA.
+ * counts (host, nbx * nby int64, row ix: counts[ix * nby + iy]) receives
+ * the exact cell counts; sum_q (host, nbx doubles) the FP64 sum of q over
+ * the cells of each density bin (summation order unspecified).  Both are
+ * overwritten.  1 <= nbx, nby <= 256, nbx * nby <= RT_HIST_MAX_BINS,
+ * lo < hi, |lo|, |hi| <= 300, else RT_E_ARG.  Waits for the stream. */
+int rt_histogram(rt_ctx *ctx, int32_t quantity, int32_t nbx, double lox, double hix,
+                 int32_t nby, double loy, double hiy, int64_t *counts, double *sum_q);
 
 /* Copy field `field` (RT_FIELD_*) of the current state into dst (nx*ny*nz
  * floats; device memory if dst_on_device != 0, else host memory) and wait

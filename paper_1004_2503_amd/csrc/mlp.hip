@@ -317,6 +317,7 @@ __global__ __launch_bounds__(256) void chem_batch_kernel(int64_t n, const float 
                                                          int nsub, float csig, float T_h,
                                                          float inv15kB, float T_floor,
                                                          float sub_eps, float xhi_thr,
+                                                         ClumpLaw cl,
                                                          int32_t *__restrict__ ncyc)
 {
     const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
@@ -327,14 +328,18 @@ __global__ __launch_bounds__(256) void chem_batch_kernel(int64_t n, const float 
         const ChemK<double> K{double(d), double(d) / nsub, double(csig), double(T_h),
                               double(T_floor), double(sub_eps)};
         double Nd = N[i], xd = xHI[i], Td = T[i], ad = 0.0;
-        nc = chem_cell<double>(chem, nsub, adaptive, inv15kB, K, double(nH[i]), Nd, xd, Td, ad);
+        float cR, cI;
+        clump_f32(cl, nH[i], cR, cI);
+        nc = chem_cell<double>(chem, nsub, adaptive, inv15kB, K, double(cR), double(cI),
+                               double(nH[i]), Nd, xd, Td, ad);
         N[i] = float(Nd);
         xHI[i] = float(xd);
         T[i] = float(Td);
     } else {
         const ChemK<float> K{d, d / float(nsub), csig, T_h, T_floor, sub_eps};
-        float Nf = N[i], xf = xHI[i], Tf = T[i], af = 0.0f;
-        nc = chem_cell<float>(chem, nsub, adaptive, inv15kB, K, nH[i], Nf, xf, Tf, af);
+        float Nf = N[i], xf = xHI[i], Tf = T[i], af = 0.0f, cR, cI;
+        clump_f32(cl, nH[i], cR, cI);
+        nc = chem_cell<float>(chem, nsub, adaptive, inv15kB, K, cR, cI, nH[i], Nf, xf, Tf, af);
         N[i] = Nf;
         xHI[i] = xf;
         T[i] = Tf;
@@ -465,6 +470,7 @@ extern "C" int rt_chem_apply(const rt_params *p, int64_t n, const float *nH, flo
     if (!(p->c_cms > 0.0) || !(p->sigma_n > 0.0) || !(p->sigma_e > 0.0) ||
         !(p->egamma_eV > 0.0) || !(p->T_floor >= 0.0))
         return RT_E_ARG;
+    if (check_clump(*p) != RT_OK) return RT_E_ARG;
     if (n == 0) return RT_OK;
     if (!nH || !N || !xHI || !T || !dt) return RT_E_ARG;
     const double eheat = (p->sigma_e * p->egamma_eV / p->sigma_n - 13.6) * EV_;
@@ -475,6 +481,6 @@ extern "C" int rt_chem_apply(const rt_params *p, int64_t n, const float *nH, flo
                        p->prec == RT_PREC_MIXED ? 1 : 0, p->sub == RT_SUB_ADAPTIVE ? 1 : 0,
                        nsub, float(p->c_cms * p->sigma_n), float(eheat / (1.5 * KB_)),
                        float(1.0 / (1.5 * KB_)), float(p->T_floor), float(p->sub_eps),
-                       float(p->xhi_fp64_thr), ncycles);
+                       float(p->xhi_fp64_thr), make_clump_law(*p), ncycles);
     return hipGetLastError() == hipSuccess ? RT_OK : RT_E_HIP;
 }

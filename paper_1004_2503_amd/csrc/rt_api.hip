@@ -23,9 +23,11 @@ constexpr double EV = 1.602176634e-12;
 constexpr double E_ION_EV = 13.6;
 constexpr int MAX_NSUB = 4096;
 #ifndef RT_M1_ZC
-#define RT_M1_ZC 32
+#define RT_M1_ZC 64
 #endif
 constexpr int ZC_DEFAULT = RT_M1_ZC;  // planes per block along z
+constexpr double SIGMA_T = 6.6524587321e-25;  // Thomson cross-section [cm^2]
+constexpr int HSUM_DOUBLES = 256 + 2 * 257;   // histogram sums + edges
 
 struct Ev {
     hipEvent_t a, b;
@@ -48,6 +50,9 @@ struct rt_ctx {
     double *d_part = nullptr;
     int npart = 0;
     double *d_acc = nullptr;
+    float *d_sink = nullptr;
+    unsigned long long *d_hcount = nullptr;  // RT_HIST_MAX_BINS
+    double *d_hsum = nullptr;                // 256 + edges 2 * 257
     double t = 0.0, emitted = 0.0, photons_initial = 0.0, nh_sum = 0.0;
     int64_t steps = 0;
     int64_t hist_host[8] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -76,7 +81,7 @@ static int check_params(const rt_params *p)
     if (p->chem < RT_CHEM_FULL || p->chem > RT_CHEM_FROZEN) return RT_E_ARG;
     if (p->prec != RT_PREC_FP32 && p->prec != RT_PREC_MIXED) return RT_E_ARG;
     if (p->sub != RT_SUB_FIXED && p->sub != RT_SUB_ADAPTIVE) return RT_E_ARG;
-    if (p->reserved != 0) return RT_E_ARG;
+    if (check_clump(*p) != RT_OK) return RT_E_ARG;
     if (!(p->dx_cm > 0.0) || !isfinite(p->dx_cm)) return RT_E_ARG;
     if (!(p->c_cms > 0.0) || !isfinite(p->c_cms)) return RT_E_ARG;
     if (!(p->sigma_n > 0.0) || !(p->sigma_e > 0.0) || !(p->egamma_eV > 0.0)) return RT_E_ARG;
@@ -107,6 +112,9 @@ static void free_ctx(rt_ctx *c)
     if (c->d_src_rate) (void)hipFree(c->d_src_rate);
     if (c->d_part) (void)hipFree(c->d_part);
     if (c->d_acc) (void)hipFree(c->d_acc);
+    if (c->d_sink) (void)hipFree(c->d_sink);
+    if (c->d_hcount) (void)hipFree(c->d_hcount);
+    if (c->d_hsum) (void)hipFree(c->d_hsum);
     if (c->d_surr_pk) (void)hipFree(c->d_surr_pk);
     if (c->d_surr_bias) (void)hipFree(c->d_surr_bias);
     for (auto &e : c->ev) {
@@ -160,7 +168,10 @@ extern "C" int rt_init(const rt_params *params, const rt_fields *fields, void *h
 
     if (hipMalloc(&c->d_part, size_t(c->npart) * NRED * sizeof(double)) != hipSuccess ||
         hipMalloc(&c->d_acc, ACC_SIZE * sizeof(double)) != hipSuccess ||
-        hipMalloc(&c->d_src_ptr, size_t(c->nblocks + 1) * sizeof(int32_t)) != hipSuccess) {
+        hipMalloc(&c->d_src_ptr, size_t(c->nblocks + 1) * sizeof(int32_t)) != hipSuccess ||
+        hipMalloc(&c->d_sink, NTHREADS * sizeof(float)) != hipSuccess ||
+        hipMalloc(&c->d_hcount, RT_HIST_MAX_BINS * sizeof(unsigned long long)) != hipSuccess ||
+        hipMalloc(&c->d_hsum, HSUM_DOUBLES * sizeof(double)) != hipSuccess) {
         (void)hipGetLastError();
         free_ctx(c);
         return RT_E_NOMEM;
@@ -176,7 +187,7 @@ extern "C" int rt_init(const rt_params *params, const rt_fields *fields, void *h
     const int nsb = state_sums_blocks(c->ncell);
     if (launch_state_sums(fields->N[0], fields->xHI, fields->nH, c->ncell, c->d_part, nsb,
                           c->stream) != hipSuccess ||
-        launch_finalize(c->d_part, nsb, c->d_acc, 1, c->stream) != hipSuccess) {
+        launch_finalize(c->d_part, nsb, c->d_acc, 1, 0.0, 0.0, c->stream) != hipSuccess) {
         free_ctx(c);
         return RT_E_HIP;
     }
@@ -277,6 +288,30 @@ extern "C" int rt_inject_sources(rt_ctx *c, int64_t n, const int32_t *ijk, const
     return RT_OK;
 }
 
+int rtk::check_clump(const rt_params &p)
+{
+    if (p.clump != 0 && p.clump != 1) return RT_E_ARG;
+    if (p.clump == 1) {
+        if (!(p.clump_cr_norm > 0.0) || !isfinite(p.clump_cr_norm)) return RT_E_ARG;
+        if (!(p.clump_ci_norm > 0.0) || !isfinite(p.clump_ci_norm)) return RT_E_ARG;
+        if (!(fabs(p.clump_cr_exp) <= 10.0) || !(fabs(p.clump_ci_exp) <= 10.0)) return RT_E_ARG;
+    }
+    return RT_OK;
+}
+
+ClumpLaw rtk::make_clump_law(const rt_params &p)
+{
+    ClumpLaw l{};
+    l.on = p.clump;
+    if (p.clump) {
+        l.cr_exp = float(p.clump_cr_exp);
+        l.cr_l2n = float(log2(p.clump_cr_norm));
+        l.ci_exp = float(p.clump_ci_exp);
+        l.ci_l2n = float(log2(p.clump_ci_norm));
+    }
+    return l;
+}
+
 static void fill_args(const rt_ctx *c, double dt, int nsub, StepArgs &a)
 {
     const rt_params &p = c->p;
@@ -296,6 +331,7 @@ static void fill_args(const rt_ctx *c, double dt, int nsub, StepArgs &a)
     a.src_key = c->d_src_key;
     a.src_rate = c->d_src_rate;
     a.partials = c->d_part;
+    a.sink = c->d_sink;
     a.nx = p.nx;
     a.ny = p.ny;
     a.nz = p.nz;
@@ -310,6 +346,7 @@ static void fill_args(const rt_ctx *c, double dt, int nsub, StepArgs &a)
     a.mixed = p.prec == RT_PREC_MIXED;
     a.adaptive = p.sub == RT_SUB_ADAPTIVE;
     a.nsub = nsub;
+    a.cl = make_clump_law(p);
     a.any_outflow = 0;
     for (int f = 0; f < 6; ++f) a.any_outflow |= p.bc[f] == RT_BC_OUTFLOW ? 1 : 0;
     const double c_ = p.c_cms;
@@ -365,7 +402,9 @@ extern "C" int rt_step(rt_ctx *c, double dt, int32_t nsub)
     }
     if (launch_step(a, c->stream) != hipSuccess) return RT_E_HIP;
     if (e && hipEventRecord(e->b, c->stream) != hipSuccess) return RT_E_HIP;
-    if (launch_finalize(c->d_part, c->nblocks, c->d_acc, 0, c->stream) != hipSuccess)
+    const double tau_coef = c->p.c_cms * SIGMA_T * dt / double(c->ncell);
+    if (launch_finalize(c->d_part, c->nblocks, c->d_acc, 0, tau_coef, c->nh_sum, c->stream) !=
+        hipSuccess)
         return RT_E_HIP;
     c->cur = 1 - c->cur;
     c->t += dt;
@@ -446,7 +485,46 @@ extern "C" int rt_reduce(rt_ctx *c, rt_reductions *out)
     out->n_fallback = int64_t(acc[ACC_CUM + R_FALLBACK]);
     for (int b = 0; b < 8; ++b)
         out->subcycle_hist[b] = c->hist_host[b] + int64_t(acc[ACC_CUM + R_HIST0 + b]);
+    out->tau_e = acc[ACC_CUM + ACC_TAU];
     return out->n_nonfinite > 0 ? RT_E_NONFINITE : RT_OK;
+}
+
+extern "C" int rt_histogram(rt_ctx *c, int32_t quantity, int32_t nbx, double lox, double hix,
+                            int32_t nby, double loy, double hiy, int64_t *counts,
+                            double *sum_q)
+{
+    if (!c) return RT_E_STATE;
+    if (quantity != RT_HQ_XHI && quantity != RT_HQ_GAMMA) return RT_E_ARG;
+    if (nbx < 1 || nbx > 256 || nby < 1 || nby > 256 || nbx * nby > RT_HIST_MAX_BINS)
+        return RT_E_ARG;
+    for (double v : {lox, hix, loy, hiy})
+        if (!(fabs(v) <= 300.0)) return RT_E_ARG;
+    if (!(lox < hix) || !(loy < hiy)) return RT_E_ARG;
+    if (!counts || !sum_q) return RT_E_ARG;
+    // edges e_k = 10^(lo + k w), w = (hi - lo) / nb, in FP64
+    double h_edges[2 * 257];
+    const double wx = (hix - lox) / nbx, wy = (hiy - loy) / nby;
+    for (int k = 0; k <= nbx; ++k) h_edges[k] = pow(10.0, lox + k * wx);
+    for (int k = 0; k <= nby; ++k) h_edges[nbx + 1 + k] = pow(10.0, loy + k * wy);
+    double *d_sum = c->d_hsum, *d_edges = c->d_hsum + 256;
+    const float *q = quantity == RT_HQ_XHI ? c->f.xHI : c->f.N[c->cur];
+    std::vector<unsigned long long> hc(size_t(nbx) * nby);
+    if (hipMemcpyAsync(d_edges, h_edges, size_t(nbx + nby + 2) * sizeof(double),
+                       hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+        hipMemsetAsync(c->d_hcount, 0, hc.size() * sizeof(unsigned long long), c->stream) !=
+            hipSuccess ||
+        hipMemsetAsync(d_sum, 0, size_t(nbx) * sizeof(double), c->stream) != hipSuccess ||
+        launch_hist(c->f.nH, q, quantity == RT_HQ_GAMMA, c->p.c_cms * c->p.sigma_n, c->ncell,
+                    nbx, nby, d_edges, float(lox), float(1.0 / wx), float(loy),
+                    float(1.0 / wy), c->d_hcount, d_sum, c->stream) != hipSuccess ||
+        hipMemcpyAsync(hc.data(), c->d_hcount, hc.size() * sizeof(unsigned long long),
+                       hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+        hipMemcpyAsync(sum_q, d_sum, size_t(nbx) * sizeof(double), hipMemcpyDeviceToHost,
+                       c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess)
+        return RT_E_HIP;
+    for (size_t i = 0; i < hc.size(); ++i) counts[i] = int64_t(hc[i]);
+    return RT_OK;
 }
 
 extern "C" int rt_state(rt_ctx *c, int32_t field, void *dst, int32_t dst_on_device)

@@ -103,30 +103,50 @@ struct ChemK {
 // equilibrium, where the net rate is a small difference of large terms.
 template <typename R>
 __device__ __forceinline__ R chem_timescale(int chem, const ChemK<R> &K, const RateSet &rs,
-                                            R nH, R N, R xHI, R T)
+                                            R cR, R cI, R nH, R N, R xHI, R x, R T)
 {
-    R x = R(1) - xHI;
-    R g = K.csig * N;
-    R gx = R(rs.alpha) * nH * x * x + (g + R(rs.beta) * nH * x) * xHI;
+    R g = cI * K.csig * N;
+    R gx = cR * R(rs.alpha) * nH * x * x + (g + R(rs.beta) * nH * x) * xHI;
     R t = R(3.0e38f);
     if (gx > R(0)) t = xHI * frcp(gx);
     if (chem == RT_CHEM_FULL) {
-        R gu = g * xHI * K.T_h + nH * (x * x * R(rs.crb) + x * xHI * R(rs.cci));
+        R gu = g * xHI * K.T_h + nH * (x * x * cR * R(rs.crb) + x * xHI * R(rs.cci));
         if (gu > R(0)) t = rmin(t, (R(1) + x) * T * frcp(gu));
     }
     return t;
 }
 
+// Subgrid clumping factors (Sec. 3.2.1) of a cell: C_R = max(1, norm_R
+// nH^exp_R) and C_I = norm_I nH^exp_I, evaluated as 2^(exp log2 nH + l2n)
+// with l2n = log2 norm.  Exactly 1 when clumping is off.  The FP64
+// chemistry takes the same FP32 factors (relative error ~1e-6).
+__device__ __forceinline__ void clump_f32(const ClumpLaw &L, float nH, float &cR, float &cI)
+{
+    cR = 1.0f;
+    cI = 1.0f;
+    if (L.on) {
+        const float l = flog2(nH);
+        cR = rmax(1.0f, fexp2(L.cr_exp * l + L.cr_l2n));
+        cI = fexp2(L.ci_exp * l + L.ci_l2n);
+    }
+}
+
 // Sub-cycles of one cell: implicit photon-conserving photoionisation,
 // creation/destruction recombination update, semi-implicit energy update.
-// Returns the number of sub-cycles; N, xHI, T updated; `absorbed` gains the
-// photon density removed.
+// cR multiplies the terms in ne nHII (recombination and its cooling,
+// bremsstrahlung), cI the photoionisation rate.  Returns the number of
+// sub-cycles; N, xHI, T updated; `absorbed` gains the photon density
+// removed.
 template <typename R>
 __device__ __forceinline__ int chem_cell(int chem, int nsub, int adaptive, float inv15kB,
-                                         const ChemK<R> &K, R nH, R &N, R &xHI, R &T,
-                                         R &absorbed)
+                                         const ChemK<R> &K, R cR, R cI, R nH, R &N, R &xHI,
+                                         R &T, R &absorbed)
 {
     const R inv_nH = frcp(nH);
+    // The ionised fraction is carried beside xHI with updates free of
+    // cancellation: 1 - xHI would lose its relative precision in nearly
+    // neutral gas, where cooling goes as its square.
+    R xi = R(1) - xHI;
     R remaining = K.dt;
     int it = 0;
     for (; it < nsub && remaining > R(0); ++it) {
@@ -138,14 +158,15 @@ __device__ __forceinline__ int chem_cell(int chem, int nsub, int adaptive, float
         } else if (adaptive) {
             rs = rates_f32(float(T), inv15kB);
             have = true;
-            h = rmin(remaining, K.sub_eps * chem_timescale<R>(chem, K, rs, nH, N, xHI, T));
+            h = rmin(remaining,
+                     K.sub_eps * chem_timescale<R>(chem, K, rs, cR, cI, nH, N, xHI, xi, T));
         } else {
             h = K.hfix;
         }
         remaining -= h;
         if (it == nsub - 1 || remaining < R(0)) remaining = R(0);
 
-        const R a = K.csig * h;
+        const R a = cI * K.csig * h;
         const R nHI = nH * xHI;
         if (chem == RT_CHEM_FROZEN) {
             R Nn = N * frcp(R(1) + a * nHI);
@@ -157,7 +178,7 @@ __device__ __forceinline__ int chem_cell(int chem, int nsub, int adaptive, float
         // a un Nn = N - Nn, un - Nn = nHI - N; each root taken in the
         // cancellation-free form for its sign of aD.  Without photons
         // nothing is absorbed and xHI is left exactly as it is.
-        const R x0 = R(1) - xHI;
+        const R x0 = xi;
         R Pd = R(0), xh = xHI;
         if (N > R(0)) {
             const R aN = a * N, aH = a * nHI, aD = aH - aN;
@@ -179,22 +200,35 @@ __device__ __forceinline__ int chem_cell(int chem, int nsub, int adaptive, float
             xh = un * inv_nH;
         }
 
-        // recombination (case B) and collisional ionisation
+        // recombination (case B) and collisional ionisation:
+        // xn = (xh + A x^2) / (1 + B x); with xh + x = 1 the ionised
+        // fraction after it is x (1 + B - A x) / (1 + B x), taken in that
+        // form when it is the smaller of the two
         if (!have) rs = rates_f32(float(T), inv15kB);
-        const R x = R(1) - xh;
-        R xn = (xh + R(rs.alpha) * nH * x * x * h) * frcp(R(1) + R(rs.beta) * nH * x * h);
+        const R x = rmin(x0 + Pd * inv_nH, R(1));
+        const R A = cR * R(rs.alpha) * nH * h, B = R(rs.beta) * nH * h;
+        const R den = frcp(R(1) + B * x);
+        R xn = (xh + A * x * x) * den;
+        R xin;
+        if (xn >= R(0.5)) {
+            xin = rmax(x * (R(1) + B - A * x) * den, R(0));
+            xn = R(1) - xin;
+        } else {
+            xin = R(1) - xn;
+        }
         xn = rmin(rmax(xn, R(1e-12)), R(1));
 
         // internal energy 3/2 kB nH (1+x) T: photo-heating, then cooling
         if (chem == RT_CHEM_FULL) {
-            const R x1 = R(1) - xn;
-            const R lu = h * nH * (x1 * x1 * R(rs.crb) + x1 * xn * R(rs.cci)) *
+            const R x1 = xin;
+            const R lu = h * nH * (x1 * x1 * cR * R(rs.crb) + x1 * xn * R(rs.cci)) *
                          frcp((R(1) + x0) * T);
             const R Tn = ((R(1) + x0) * T + Pd * inv_nH * K.T_h) *
                          frcp((R(1) + lu) * (R(1) + x1));
             T = rmax(Tn, K.T_floor);
         }
         xHI = xn;
+        xi = rmin(xin, R(1));
     }
     return it;
 }

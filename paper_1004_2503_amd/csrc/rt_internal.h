@@ -10,10 +10,14 @@
 namespace rtk {
 
 // Tile of the fused step kernel: one wavefront per x-row of 64 cells, TY
-// rows per block (512 threads), the block marching ZC planes along z.
+// rows per block (64 TY threads), the block marching ZC planes along z.
+#ifndef RT_M1_TY
+#define RT_M1_TY 8
+#endif
 constexpr int TX = 64;
-constexpr int TY = 8;
+constexpr int TY = RT_M1_TY;
 constexpr int NTHREADS = TX * TY;
+constexpr int SRC_LDS = 256;   // sources staged in LDS per refill
 
 // Per-block partial sums written by the step kernel (all FP64).
 enum Red : int {
@@ -35,6 +39,14 @@ enum Red : int {
 constexpr int ACC_CUR = 0;    // NRED sums of the last step (or initial state)
 constexpr int ACC_CUM = 32;   // NRED cumulative sums over steps
 constexpr int ACC_SIZE = 64;
+constexpr int ACC_TAU = 31;   // ACC_CUM + ACC_TAU: Thomson depth (cumulative)
+
+// Subgrid clumping laws: C = 2^(exp log2 nH + l2n), l2n = log2 norm; C_R is
+// bounded below by 1.  on = 0: C_R = C_I = 1.
+struct ClumpLaw {
+    int on;
+    float cr_exp, cr_l2n, ci_exp, ci_l2n;
+};
 
 struct StepArgs {
     const float *N, *Fx, *Fy, *Fz;   // current buffer
@@ -45,11 +57,13 @@ struct StepArgs {
     const int32_t *src_key;          // (z - z0) * NTHREADS + thread index
     const float *src_rate;           // S = ndot / dx^3 [cm^-3 s^-1]
     double *partials;                // nblocks * NRED
+    float *sink;                     // NTHREADS floats: stores of lanes off the grid
     int nx, ny, nz;
     uint32_t plane;                  // nx * ny
     int ntx, nty, nzc, zc, nblocks;
     int bc[6];
     int chem, mixed, adaptive, nsub, any_outflow;
+    ClumpLaw cl;
     // FP32 constants
     float c, inv_c, half_c, half_c2, k1, dt, csig, T_h, inv15kB, T_floor,
         sub_eps, xhi_thr;
@@ -69,9 +83,17 @@ constexpr int SURR_NBIAS = 194;
 constexpr int SURR_NNORM = 24;
 
 hipError_t launch_step(const StepArgs &a, hipStream_t s);
+ClumpLaw make_clump_law(const rt_params &p);
+int check_clump(const rt_params &p);
 hipError_t launch_mlp_pack(const float *theta, __bf16 *pk, hipStream_t s);
+// mode 0 also adds tau_coef * (nh_sum - sum nH xHI) to acc[ACC_CUM + ACC_TAU]
 hipError_t launch_finalize(const double *partials, int nblocks, double *acc,
-                           int mode, hipStream_t s);
+                           int mode, double tau_coef, double nh_sum, hipStream_t s);
+size_t hist_lds_bytes(int nbx, int nby);
+hipError_t launch_hist(const float *nH, const float *q, int gamma, double csig, uint32_t ncell,
+                       int nbx, int nby, const double *edges, float lox, float inv_wx,
+                       float loy, float inv_wy, unsigned long long *counts, double *sums,
+                       hipStream_t s);
 hipError_t launch_state_sums(const float *N, const float *xHI, const float *nH,
                              uint32_t ncell, double *partials, int nblocks,
                              hipStream_t s);

@@ -22,7 +22,7 @@
 #include "mlp_device.h"
 
 #ifndef RT_M1_NT_STORES
-#define RT_M1_NT_STORES 0
+#define RT_M1_NT_STORES 1
 #endif
 
 namespace rtk {
@@ -70,6 +70,23 @@ struct Cell4 {
     float N, Fx, Fy, Fz;
 };
 
+// Prefetches stay raw: applying a reflection sign at load time would make
+// the kernel wait for the load right where it is issued.
+__device__ __forceinline__ Cell4 load_raw(const StepArgs &A, uint32_t i)
+{
+    Cell4 c;
+    c.N = A.N[i];
+    c.Fx = A.Fx[i];
+    c.Fy = A.Fy[i];
+    c.Fz = A.Fz[i];
+    return c;
+}
+
+__device__ __forceinline__ Cell4 signed4(const Cell4 &r, float sx, float sy, float sz)
+{
+    return Cell4{r.N, sx * r.Fx, sy * r.Fy, sz * r.Fz};
+}
+
 __device__ __forceinline__ Cell4 load4(const StepArgs &A, uint32_t i, float sx, float sy,
                                        float sz)
 {
@@ -82,10 +99,15 @@ __device__ __forceinline__ Cell4 load4(const StepArgs &A, uint32_t i, float sx, 
 }
 
 // ------------------------------------------------------ fused step kernel
-// Exact forms: at most 128 VGPRs so that two 512-thread blocks (4 waves per
-// SIMD) share a CU; the surrogate form needs more and runs one block.
+// One 512-thread block per CU (up to 256 VGPRs): measured faster at 1024^3
+// than two blocks at 128 VGPRs, where the FP64 chemistry of the mixed form
+// spills.
+#ifndef RT_M1_MINW
+#define RT_M1_MINW 2
+#endif
+
 template <bool MIXED, bool SURR>
-__global__ __launch_bounds__(NTHREADS, SURR ? 2 : 4) void m1_step_kernel(StepArgs A)
+__global__ __launch_bounds__(NTHREADS, SURR ? 2 : RT_M1_MINW) void m1_step_kernel(StepArgs A)
 {
     constexpr int SW = TX + 2;
     __shared__ __attribute__((aligned(16))) __bf16 s_pk[SURR ? PK_FWD * 8 : 8];
@@ -106,7 +128,12 @@ __global__ __launch_bounds__(NTHREADS, SURR ? 2 : 4) void m1_step_kernel(StepArg
     }
 
     // XCD-aware renumbering: blockIdx mod 8 selects the XCD; each XCD takes
-    // a contiguous range of tiles (x fastest, then y, then the z chunk).
+    // a contiguous range of tiles ordered x fastest, so the blocks resident
+    // on one XCD at a time cover whole rows of tiles marching z together and
+    // read each other's halo cells from that XCD's L2.  (A y-fastest order
+    // was measured to fetch 30% more from HBM: a single-float x-halo read
+    // pulls a whole 128-byte line, which is only reused if the x-neighbour
+    // tile is resident at the same time.)
     const int b = blockIdx.x, nb = A.nblocks;
     const int q = nb >> 3, r8 = nb & 7, xcd = b & 7;
     const int tile = xcd * q + (xcd < r8 ? xcd : r8) + (b >> 3);
@@ -114,6 +141,7 @@ __global__ __launch_bounds__(NTHREADS, SURR ? 2 : 4) void m1_step_kernel(StepArg
     const int rest = tile / A.ntx;
     const int ity = rest % A.nty;
     const int izc = rest / A.nty;
+    const int tile_id = tile;   // source-list index
     const int x0 = itx * TX, y0 = ity * TY;
     const int z0 = izc * A.zc;
     const int z1 = min(z0 + A.zc, A.nz);
@@ -146,13 +174,29 @@ __global__ __launch_bounds__(NTHREADS, SURR ? 2 : 4) void m1_step_kernel(StepArg
     const Map1 hy = map_coord(y0 + hsy - 1, A.ny, A.bc[2], A.bc[3]);
     const uint32_t hcol = uint32_t(hy.idx) * uint32_t(A.nx) + uint32_t(hx.idx);
 
-    // sources of this tile, sorted by plane
-    int sp = A.src_ptr[tile];
-    const int sp_end = A.src_ptr[tile + 1];
+    // Sources of this tile, sorted by plane, staged in LDS (refilled when
+    // exhausted): the walk then waits on LDS only and never drains the
+    // prefetched global loads in flight.
+    __shared__ int s_skey[SRC_LDS];
+    __shared__ float s_srate[SRC_LDS];
+    int sp = A.src_ptr[tile_id];
+    const int sp_end = A.src_ptr[tile_id + 1];
+    int buf_base = sp;
+    int buf_n = min(SRC_LDS, sp_end - sp);
+    for (int i = tid; i < buf_n; i += NTHREADS) {
+        s_skey[i] = A.src_key[buf_base + i];
+        s_srate[i] = A.src_rate[buf_base + i];
+    }
 
-    // FP64 accumulators
-    double acc_xhi = 0.0, acc_nhxhi = 0.0, acc_N = 0.0;
-    double acc_abs = 0.0, acc_esc = 0.0, acc_floor = 0.0;
+    // FP64 sums.  The four that change every plane are accumulated per
+    // thread (a per-plane wavefront reduction was measured to cost ~25% of
+    // the step); escaped and floor photons, which are zero almost
+    // everywhere, are reduced across the wavefront only on planes where
+    // they occur and kept per wavefront in LDS.
+    __shared__ double s_acc[NTHREADS / 64][8];
+    const int wave = tid >> 6;
+    if (lx < 8) s_acc[wave][lx] = 0.0;
+    double acc_xhi = 0.0, acc_nhxhi = 0.0, acc_N = 0.0, acc_abs = 0.0;
     int n_bad = 0, n_fp64 = 0, n_fb = 0;
     __shared__ int shist[8];
     if (tid < 8) shist[tid] = 0;
@@ -167,27 +211,52 @@ __global__ __launch_bounds__(NTHREADS, SURR ? 2 : 4) void m1_step_kernel(StepArg
     Press pprv = closure(prv.N, prv.Fx, prv.Fy, prv.Fz, A.inv_c);
     Cell4 cur = load4(A, col + uint32_t(z0) * plane, mx.sign, my.sign, 1.0f);
     Press pcur = closure(cur.N, cur.Fx, cur.Fy, cur.Fz, A.inv_c);
-    Map1 mzp = map_coord(z0 + 1, A.nz, A.bc[4], A.bc[5]);
-    Cell4 nxt = load4(A, col + uint32_t(mzp.idx) * plane, mx.sign, my.sign, mzp.sign);
-    Cell4 hal{0.f, 0.f, 0.f, 0.f};
-    if (has_halo) hal = load4(A, hcol + uint32_t(z0) * plane, hx.sign, hy.sign, 1.0f);
-    float c_xh = A.xHI[col + uint32_t(z0) * plane];
-    float c_T = A.T[col + uint32_t(z0) * plane];
-    float c_nh = A.nH[col + uint32_t(z0) * plane];
+    // Prefetched planes live in two register sets that swap roles every
+    // plane: the loop below is unrolled by two so that a value loaded for
+    // the next plane is never copied, and its load stays in flight across
+    // the plane boundary instead of being waited for at the end of an
+    // iteration.  Set k holds the planes z with (z - z0) % 2 == k.  (A
+    // two-plane prefetch distance was measured to gain nothing.)
+    const uint32_t hsrc = has_halo ? hcol : col;
+    const float hsx_sign = has_halo ? hx.sign : 1.0f, hsy_sign = has_halo ? hy.sign : 1.0f;
+    auto load_ch = [&](float3 &c, int zz) {
+        const uint32_t i = col + uint32_t(zz) * plane;
+        c.x = A.xHI[i];
+        c.y = A.T[i];
+        c.z = A.nH[i];
+    };
+    const Cell4 zero4{0.f, 0.f, 0.f, 0.f};
+    const float3 zero3 = make_float3(0.f, 0.f, 0.f);
+    Cell4 nx0 = zero4, nx1 = zero4;
+    Cell4 ha0 = zero4, ha1 = zero4;
+    float3 ch0 = zero3, ch1 = zero3;
+    nx1 = load_raw(A, col + uint32_t(map_coord(z0 + 1, A.nz, A.bc[4], A.bc[5]).idx) * plane);
+    ha0 = load_raw(A, hsrc + uint32_t(z0) * plane);
+    load_ch(ch0, z0);
 
-    for (int z = z0; z < z1; ++z) {
-        // prefetch plane z+1 (halo, chemistry fields) and z+2 (own column)
-        const bool more = z + 1 < z1;
-        const int zn = more ? z + 1 : z;
-        const Map1 mzq = map_coord(z + 2, A.nz, A.bc[4], A.bc[5]);
-        Cell4 nx2 = nxt;
-        if (more) nx2 = load4(A, col + uint32_t(mzq.idx) * plane, mx.sign, my.sign, mzq.sign);
-        Cell4 hal2 = hal;
-        if (has_halo && more) hal2 = load4(A, hcol + uint32_t(zn) * plane, hx.sign, hy.sign, 1.0f);
-        const uint32_t inext = col + uint32_t(zn) * plane;
-        const float n_xh = A.xHI[inext];
-        const float n_T = A.T[inext];
-        const float n_nh = A.nH[inext];
+    // One plane z.  nxt: plane z+1 of the own column (loaded earlier);
+    // nx_ld receives plane z+2.  hal: this thread's halo cell of plane z;
+    // hal_ld receives plane z+1's.  ch: xHI, T, nH of plane z; ch_ld
+    // receives plane z+1's.
+    auto plane_step = [&](const int z, const Cell4 &nxt_raw, Cell4 &nx_ld, const Cell4 &hal_raw,
+                          Cell4 &hal_ld, const float3 &ch, float3 &ch_ld) {
+        const float c_xh = ch.x, c_T = ch.y, c_nh = ch.z;
+        // Prefetch (unconditionally, so that every lane of every plane issues
+        // the same loads and the compiler's count of outstanding memory
+        // operations stays exact: non-halo lanes re-load their own cell, the
+        // chunk's last plane loads a valid neighbour that is not used).
+        {
+            const Map1 mzq = map_coord(z + 2, A.nz, A.bc[4], A.bc[5]);
+            const int zh = z + 1 < z1 ? z + 1 : z;
+            nx_ld = load_raw(A, col + uint32_t(mzq.idx) * plane);
+            hal_ld = load_raw(A, hsrc + uint32_t(zh) * plane);
+            load_ch(ch_ld, zh);
+        }
+
+        // boundary-image signs of the prefetched planes, applied on use
+        const Cell4 nxt = signed4(nxt_raw, mx.sign, my.sign,
+                                  map_coord(z + 1, A.nz, A.bc[4], A.bc[5]).sign);
+        const Cell4 hal = signed4(hal_raw, hsx_sign, hsy_sign, 1.0f);
 
         // plane z into LDS: own cell and its halo
         {
@@ -252,9 +321,19 @@ __global__ __launch_bounds__(NTHREADS, SURR ? 2 : 4) void m1_step_kernel(StepArg
         float S = 0.0f;
         const int zl = z - z0;
         while (sp < sp_end) {
-            const int key = A.src_key[sp];
+            if (sp - buf_base >= buf_n) {          // uniform: refill the staging
+                __syncthreads();
+                buf_base = sp;
+                buf_n = min(SRC_LDS, sp_end - sp);
+                for (int i = tid; i < buf_n; i += NTHREADS) {
+                    s_skey[i] = A.src_key[buf_base + i];
+                    s_srate[i] = A.src_rate[buf_base + i];
+                }
+                __syncthreads();
+            }
+            const int key = s_skey[sp - buf_base];
             if (key / NTHREADS != zl) break;
-            if (key - zl * NTHREADS == tid) S += A.src_rate[sp];
+            if (key - zl * NTHREADS == tid) S += s_srate[sp - buf_base];
             ++sp;
         }
 
@@ -301,7 +380,10 @@ __global__ __launch_bounds__(NTHREADS, SURR ? 2 : 4) void m1_step_kernel(StepArg
         int ncyc = 0;
         bool used64 = false;
         bool fallback = true;
-        if (SURR) {
+        // Phi leaves a dark, fully neutral cell exactly as it is; a
+        // wavefront of such cells branches around the chemistry entirely
+        const bool dark = !(Nt > 0.0f) && c_xh >= 1.0f;
+        if (SURR && __ballot(!dark) != 0ull) {
             // learned Phi for the 64 cells of this wavefront (uniform control
             // flow: every lane takes part in the matrix products)
             const float *nm = A.surr_norm;
@@ -345,23 +427,26 @@ __global__ __launch_bounds__(NTHREADS, SURR ? 2 : 4) void m1_step_kernel(StepArg
             // photons absorbed over dt: net ionisations + recombinations -
             // collisional ionisations at the predicted end state
             const RateSet rs = rates_f32(Ts, A.inv15kB);
+            float sR, sI;
+            clump_f32(A.cl, c_nh, sR, sI);
             const float x1 = 1.0f - xs, x0 = 1.0f - c_xh;
             const float nh2dt = c_nh * c_nh * A.dt;
-            float Ph = c_nh * (c_xh - xs) + rs.alpha * nh2dt * x1 * x1 - rs.beta * nh2dt * x1 * xs;
+            float Ph = c_nh * (c_xh - xs) + sR * rs.alpha * nh2dt * x1 * x1 -
+                       rs.beta * nh2dt * x1 * xs;
             Ph = rmin(rmax(Ph, 0.0f), Nt);
             const float Ns = Nt - Ph;
             // backward-Euler residuals of one step dt at the predicted end
             const float inv_nh = frcp(c_nh);
-            const float rx = fabsf(Ph - A.csig * A.dt * Ns * c_nh * xs) * inv_nh;
+            const float rx = fabsf(Ph - sI * A.csig * A.dt * Ns * c_nh * xs) * inv_nh;
             float rT = 0.0f;
             if (A.chem == RT_CHEM_FULL) {
-                const float lu = A.dt * c_nh * (x1 * x1 * rs.crb + x1 * xs * rs.cci) *
+                const float lu = A.dt * c_nh * (x1 * x1 * sR * rs.crb + x1 * xs * rs.cci) *
                                  frcp((1.0f + x1) * Ts);
                 const float TBE = ((1.0f + x0) * c_T + Ph * inv_nh * A.T_h) *
                                   frcp((1.0f + lu) * (1.0f + x1));
                 rT = fabsf(Ts - TBE) * frcp(Ts);
             }
-            const bool ok = A.chem == RT_CHEM_FULL && !ood && xs >= 1e-12f && xs <= 1.0f &&
+            const bool ok = A.chem == RT_CHEM_FULL && !dark && !ood && xs >= 1e-12f && xs <= 1.0f &&
                             Ts >= A.T_floor && isfinite(Ts) && rx <= A.surr_tol &&
                             rT <= A.surr_tol;
             if (ok) {
@@ -372,23 +457,23 @@ __global__ __launch_bounds__(NTHREADS, SURR ? 2 : 4) void m1_step_kernel(StepArg
                 pabs = Ph;
             }
         }
-        // Phi leaves a dark, fully neutral cell exactly as it is; a
-        // wavefront of such cells branches around the chemistry entirely
-        const bool dark = !(Nt > 0.0f) && c_xh >= 1.0f;
         if (A.chem != RT_CHEM_OFF && fallback && !dark) {
             if (MIXED && c_xh < A.xhi_thr) {
                 double Nd = Nt, xd = c_xh, Td = c_T, ad = 0.0;
-                ncyc = chem_cell<double>(A.chem, A.nsub, A.adaptive, A.inv15kB, Kd,
-                                         double(c_nh), Nd, xd, Td, ad);
+                float cR, cI;
+                clump_f32(A.cl, c_nh, cR, cI);
+                ncyc = chem_cell<double>(A.chem, A.nsub, A.adaptive, A.inv15kB, Kd, double(cR),
+                                         double(cI), double(c_nh), Nd, xd, Td, ad);
                 Nn = float(Nd);
                 xh = float(xd);
                 Tc = float(Td);
                 pabs = ad;
                 used64 = true;
             } else {
-                float af = 0.0f;
-                ncyc = chem_cell<float>(A.chem, A.nsub, A.adaptive, A.inv15kB, Kf, c_nh, Nn,
-                                        xh, Tc, af);
+                float af = 0.0f, cR, cI;
+                clump_f32(A.cl, c_nh, cR, cI);
+                ncyc = chem_cell<float>(A.chem, A.nsub, A.adaptive, A.inv15kB, Kf, cR, cI, c_nh,
+                                        Nn, xh, Tc, af);
                 pabs = af;
             }
         }
@@ -399,20 +484,19 @@ __global__ __launch_bounds__(NTHREADS, SURR ? 2 : 4) void m1_step_kernel(StepArg
             Fzt *= sc;
         }
 
-        if (active) {
+        {
+            // lanes outside a ragged tile write to the sink, so that stores
+            // are issued unconditionally too
             const uint32_t i = uint32_t(gy) * uint32_t(A.nx) + uint32_t(gx) + uint32_t(z) * plane;
-            store_out(&A.No[i], Nn);
-            store_out(&A.Fxo[i], Fxt);
-            store_out(&A.Fyo[i], Fyt);
-            store_out(&A.Fzo[i], Fzt);
-            store_out(&A.xHI[i], xh);
-            store_out(&A.T[i], Tc);
-            acc_xhi += double(xh);
-            acc_nhxhi = fma(double(c_nh), double(xh), acc_nhxhi);
-            acc_N += double(Nn);
-            acc_abs += pabs;
-            if (A.any_outflow) acc_esc += double(esc);
-            if (flo > 0.0f) acc_floor += double(flo);
+            float *sink = A.sink + tid;
+            store_out(active ? &A.No[i] : sink, Nn);
+            store_out(active ? &A.Fxo[i] : sink, Fxt);
+            store_out(active ? &A.Fyo[i] : sink, Fyt);
+            store_out(active ? &A.Fzo[i] : sink, Fzt);
+            store_out(active ? &A.xHI[i] : sink, xh);
+            store_out(active ? &A.T[i] : sink, Tc);
+        }
+        if (active) {
             // 0 * v is NaN exactly when v is infinite or NaN; inputs are
             // checked too, since the clamps of Phi would turn a NaN into a bound
             float z0 = 0.0f * Nn + 0.0f * Fxt + 0.0f * Fyt + 0.0f * Fzt + 0.0f * xh + 0.0f * Tc;
@@ -421,7 +505,27 @@ __global__ __launch_bounds__(NTHREADS, SURR ? 2 : 4) void m1_step_kernel(StepArg
             const bool fin = z0 == 0.0f;
             n_bad += fin ? 0 : 1;
             n_fp64 += used64 ? 1 : 0;
-            n_fb += (SURR && fallback && A.chem != RT_CHEM_OFF) ? 1 : 0;
+            n_fb += (SURR && fallback && !dark && A.chem != RT_CHEM_OFF) ? 1 : 0;
+        }
+        if (active) {
+            acc_xhi += double(xh);
+            acc_nhxhi = fma(double(c_nh), double(xh), acc_nhxhi);
+            acc_N += double(Nn);
+            acc_abs += pabs;
+        }
+        {
+            if (A.any_outflow) {
+                double e = active ? double(esc) : 0.0;
+#pragma unroll
+                for (int off = 32; off > 0; off >>= 1) e += __shfl_xor(e, off);
+                if (lx == 0) s_acc[wave][4] += e;
+            }
+            if (__ballot(active && flo > 0.0f) != 0ull) {
+                double f = active ? double(flo) : 0.0;
+#pragma unroll
+                for (int off = 32; off > 0; off >>= 1) f += __shfl_xor(f, off);
+                if (lx == 0) s_acc[wave][5] += f;
+            }
         }
         if ((A.adaptive || SURR) && A.chem != RT_CHEM_OFF) {
             const int bin = hist_bin(ncyc);
@@ -432,43 +536,59 @@ __global__ __launch_bounds__(NTHREADS, SURR ? 2 : 4) void m1_step_kernel(StepArg
             }
         }
 
-        // rotate the z pipeline
+        // advance the z window (values loaded at least one plane ago)
         prv = cur;
         pprv = pcur;
         cur = nxt;
         pcur = pnxt;
-        nxt = nx2;
-        hal = hal2;
-        c_xh = n_xh;
-        c_T = n_T;
-        c_nh = n_nh;
+    };
+
+    if constexpr (SURR) {
+        // the surrogate forms need their registers for the network: no
+        // unrolling, the prefetched set is copied forward every plane
+        for (int z = z0; z < z1; ++z) {
+            plane_step(z, nx1, nx0, ha0, ha1, ch0, ch1);
+            nx1 = nx0;
+            ha0 = ha1;
+            ch0 = ch1;
+        }
+    } else {
+        for (int z = z0; z < z1; z += 2) {
+            plane_step(z, nx1, nx0, ha0, ha1, ch0, ch1);
+            if (z + 1 < z1) plane_step(z + 1, nx0, nx1, ha1, ha0, ch1, ch0);
+        }
+    }
+    {
+        double d[4] = {acc_xhi, acc_nhxhi, acc_N, acc_abs};
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) d[j] += __shfl_xor(d[j], off);
+        }
+        if (lx == 0) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) s_acc[wave][j] += d[j];
+        }
     }
 
     // block reduction of the partial sums (fixed order, FP64)
-    double v[NRED];
-    v[R_XHI] = acc_xhi;
-    v[R_NHXHI] = acc_nhxhi;
-    v[R_NH] = 0.0;  // static: summed once at rt_init
-    v[R_N] = acc_N;
-    v[R_ABS] = acc_abs * A.vol;
-    v[R_ESC] = acc_esc * A.esc_scale;
-    v[R_FLOOR] = acc_floor * A.vol;
-    v[R_NONFINITE] = double(n_bad);
-    v[R_FP64] = double(n_fp64);
-    v[R_FALLBACK] = double(n_fb);
+    double v[3] = {double(n_bad), double(n_fp64), double(n_fb)};
 #pragma unroll
-    for (int hb = 0; hb < 8; ++hb) v[R_HIST0 + hb] = 0.0;
+    for (int j = 0; j < 3; ++j) {
 #pragma unroll
-    for (int j = 0; j < R_HIST0; ++j) {
-        double s = v[j];
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
-        v[j] = s;
+        for (int off = 32; off > 0; off >>= 1) v[j] += __shfl_xor(v[j], off);
     }
-    const int wave = tid >> 6;
     if (lx == 0) {
-#pragma unroll
-        for (int j = 0; j < R_HIST0; ++j) sred[wave][j] = v[j];
+        sred[wave][R_XHI] = s_acc[wave][0];
+        sred[wave][R_NHXHI] = s_acc[wave][1];
+        sred[wave][R_NH] = 0.0;  // static: summed once at rt_init
+        sred[wave][R_N] = s_acc[wave][2];
+        sred[wave][R_ABS] = s_acc[wave][3] * A.vol;
+        sred[wave][R_ESC] = s_acc[wave][4] * A.esc_scale;
+        sred[wave][R_FLOOR] = s_acc[wave][5] * A.vol;
+        sred[wave][R_NONFINITE] = v[0];
+        sred[wave][R_FP64] = v[1];
+        sred[wave][R_FALLBACK] = v[2];
     }
     __syncthreads();
     if (tid < NRED) {
@@ -486,29 +606,50 @@ __global__ __launch_bounds__(NTHREADS, SURR ? 2 : 4) void m1_step_kernel(StepArg
 // ---------------------------------------------- finalisation (one block)
 // mode 0: a step -- ACC_CUR = sums, ACC_CUM += sums.
 // mode 1: initial state -- ACC_CUR = sums, ACC_CUM = 0.
-__global__ __launch_bounds__(256) void finalize_kernel(const double *__restrict__ part,
-                                                       int nb, double *__restrict__ acc,
-                                                       int mode)
+// Each thread sums a fixed strided subset of the block partials in FP64,
+// then wavefronts and finally one thread per value combine them in a fixed
+// order: the result does not depend on timing.
+constexpr int FIN_THREADS = 1024;
+
+__global__ __launch_bounds__(FIN_THREADS) void finalize_kernel(const double *__restrict__ part,
+                                                               int nb, double *__restrict__ acc,
+                                                               int mode, double tau_coef,
+                                                               double nh_sum)
 {
-    __shared__ double s[256];
-    const int t = threadIdx.x;
+    __shared__ double s[FIN_THREADS / 64][NRED];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    double v[NRED];
+#pragma unroll
+    for (int j = 0; j < NRED; ++j) v[j] = 0.0;
+    for (int b = t; b < nb; b += FIN_THREADS) {
+        const double *p = part + size_t(b) * NRED;
+#pragma unroll
+        for (int j = 0; j < NRED; ++j) v[j] += p[j];
+    }
+#pragma unroll
     for (int j = 0; j < NRED; ++j) {
-        double v = 0.0;
-        for (int b = t; b < nb; b += 256) v += part[size_t(b) * NRED + j];
-        s[t] = v;
-        __syncthreads();
-        for (int w = 128; w > 0; w >>= 1) {
-            if (t < w) s[t] += s[t + w];
-            __syncthreads();
-        }
-        if (t == 0) {
-            acc[ACC_CUR + j] = s[0];
+        double x = v[j];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off);
+        if (lane == 0) s[wave][j] = x;
+    }
+    __syncthreads();
+    if (t < NRED) {
+        double x = 0.0;
+#pragma unroll
+        for (int w = 0; w < FIN_THREADS / 64; ++w) x += s[w][t];
+        acc[ACC_CUR + t] = x;
+        if (mode == 0)
+            acc[ACC_CUM + t] += x;
+        else
+            acc[ACC_CUM + t] = 0.0;
+        // Thomson depth: c sigma_T dt <nH (1 - xHI)> after the step
+        if (t == R_NHXHI) {
             if (mode == 0)
-                acc[ACC_CUM + j] += s[0];
+                acc[ACC_CUM + ACC_TAU] += tau_coef * (nh_sum - x);
             else
-                acc[ACC_CUM + j] = 0.0;
+                acc[ACC_CUM + ACC_TAU] = 0.0;
         }
-        __syncthreads();
     }
 }
 
@@ -573,10 +714,10 @@ hipError_t launch_step(const StepArgs &a, hipStream_t s)
 }
 
 hipError_t launch_finalize(const double *partials, int nblocks, double *acc, int mode,
-                           hipStream_t s)
+                           double tau_coef, double nh_sum, hipStream_t s)
 {
-    hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(256), 0, s, partials, nblocks, acc,
-                       mode);
+    hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(FIN_THREADS), 0, s, partials, nblocks,
+                       acc, mode, tau_coef, nh_sum);
     return hipGetLastError();
 }
 

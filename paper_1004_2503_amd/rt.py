@@ -43,11 +43,13 @@ class rt_params(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
                 ("bc", ctypes.c_int32 * 6), ("chem", ctypes.c_int32),
                 ("prec", ctypes.c_int32), ("sub", ctypes.c_int32),
-                ("reserved", ctypes.c_int32),
+                ("clump", ctypes.c_int32),
                 ("dx_cm", ctypes.c_double), ("c_cms", ctypes.c_double),
                 ("sigma_n", ctypes.c_double), ("sigma_e", ctypes.c_double),
                 ("egamma_eV", ctypes.c_double), ("T_floor", ctypes.c_double),
-                ("sub_eps", ctypes.c_double), ("xhi_fp64_thr", ctypes.c_double)]
+                ("sub_eps", ctypes.c_double), ("xhi_fp64_thr", ctypes.c_double),
+                ("clump_cr_norm", ctypes.c_double), ("clump_cr_exp", ctypes.c_double),
+                ("clump_ci_norm", ctypes.c_double), ("clump_ci_exp", ctypes.c_double)]
 
 
 class rt_reductions(ctypes.Structure):
@@ -58,7 +60,7 @@ class rt_reductions(ctypes.Structure):
                 ("photons_escaped", ctypes.c_double), ("photons_floor", ctypes.c_double),
                 ("steps", ctypes.c_int64), ("n_nonfinite", ctypes.c_int64),
                 ("n_fp64", ctypes.c_int64), ("n_fallback", ctypes.c_int64),
-                ("subcycle_hist", ctypes.c_int64 * 8)]
+                ("subcycle_hist", ctypes.c_int64 * 8), ("tau_e", ctypes.c_double)]
 
     def as_dict(self) -> dict:
         d = {k: getattr(self, k) for k, _ in self._fields_ if k != "subcycle_hist"}
@@ -67,7 +69,11 @@ class rt_reductions(ctypes.Structure):
 
 
 EXPORTS = ["rt_init", "rt_inject_sources", "rt_step", "rt_reduce", "rt_state",
-           "rt_current", "rt_profile", "rt_profile_read", "rt_destroy", "rt_strerror"]
+           "rt_current", "rt_profile", "rt_profile_read", "rt_destroy", "rt_strerror",
+           "rt_histogram"]
+
+HQ_XHI, HQ_GAMMA = 0, 1
+HIST_MAX_BINS = 8192
 
 _lib = None
 
@@ -98,6 +104,9 @@ def lib():
         L.rt_profile.argtypes = [vp, ctypes.c_int32]
         L.rt_profile_read.argtypes = [vp, P(ctypes.c_double), P(ctypes.c_int64)]
         L.rt_destroy.argtypes = [vp]
+        L.rt_histogram.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
+                                   ctypes.c_double, ctypes.c_int32, ctypes.c_double,
+                                   ctypes.c_double, P(ctypes.c_int64), P(ctypes.c_double)]
         L.rt_strerror.argtypes = [ctypes.c_int]
         L.rt_strerror.restype = ctypes.c_char_p
         for name in EXPORTS:
@@ -140,6 +149,20 @@ def rt_reduce(ctx):
     return rc, out
 
 
+def rt_histogram(ctx, quantity: int, xrange, yrange):
+    """Returns (code, counts (nbx, nby) int64, sums (nbx,) float64);
+    xrange = (lo, hi, nb) in log10 nH, yrange = (lo, hi, nb) in log10 q."""
+    lox, hix, nbx = xrange
+    loy, hiy, nby = yrange
+    counts = np.zeros((max(int(nbx), 0), max(int(nby), 0)), np.int64)
+    sums = np.zeros(max(int(nbx), 0), np.float64)
+    rc = lib().rt_histogram(ctx, int(quantity), int(nbx), float(lox), float(hix), int(nby),
+                            float(loy), float(hiy),
+                            counts.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                            sums.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    return rc, counts, sums
+
+
 def rt_state(ctx, field: int, dst_ptr: int, on_device: bool) -> int:
     return lib().rt_state(ctx, int(field), ctypes.c_void_p(dst_ptr), int(bool(on_device)))
 
@@ -172,12 +195,16 @@ def check(rc: int, what: str):
 
 def make_params(shape, dx, bc=(BC_PERIODIC,) * 6, chem=CHEM_FULL, prec=PREC_FP32,
                 sub=SUB_FIXED, c=C_LIGHT, T_floor=10.0, sub_eps=0.1,
-                xhi_fp64_thr=1e-3) -> rt_params:
-    """``shape`` is (nz, ny, nx), the torch/numpy order of every field."""
+                xhi_fp64_thr=1e-3, clump=None) -> rt_params:
+    """``shape`` is (nz, ny, nx), the torch/numpy order of every field.
+    ``clump`` is None (no subgrid clumping) or (cr_norm, cr_exp, ci_norm,
+    ci_exp): C_R = max(1, cr_norm nH^cr_exp), C_I = ci_norm nH^ci_exp."""
     nz, ny, nx = shape
-    return rt_params(nx, ny, nz, (ctypes.c_int32 * 6)(*bc), chem, prec, sub, 0,
+    cl = (1.0, 0.0, 1.0, 0.0) if clump is None else tuple(float(v) for v in clump)
+    return rt_params(nx, ny, nz, (ctypes.c_int32 * 6)(*bc), chem, prec, sub,
+                     0 if clump is None else 1,
                      float(dx), float(c), SIGMA_N, SIGMA_E, EGAMMA_EV, float(T_floor),
-                     float(sub_eps), float(xhi_fp64_thr))
+                     float(sub_eps), float(xhi_fp64_thr), *cl)
 
 
 class RTGrid:
@@ -256,6 +283,12 @@ class RTGrid:
             check(rt_state(self.ctx, fid, a.ctypes.data, False), "rt_state")
             out[name] = a
         return out
+
+    def histogram(self, quantity: int, xrange, yrange):
+        """(counts, per-density-bin sums) of the current state, see rt_histogram."""
+        rc, counts, sums = rt_histogram(self.ctx, quantity, xrange, yrange)
+        check(rc, "rt_histogram")
+        return counts, sums
 
     def profile(self, enable: bool):
         check(rt_profile(self.ctx, enable), "rt_profile")

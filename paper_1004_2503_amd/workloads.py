@@ -173,6 +173,18 @@ def stromgren_sources(w: Workload):
     return ijk, np.array([w.extra["ndot"] / 8.0])
 
 
+# Subgrid clumping laws (cr_norm, cr_exp, ci_norm, ci_exp) for
+# C_R = max(1, cr_norm nH^cr_exp), C_I = ci_norm nH^ci_exp (nH in cm^-3).
+# Sec. 3.2.1 fits C_R ~ nH^0.7 and C_I ~ nH^0.1 ('B' trends; C_R above one
+# from ~4e-3 cm^-3, C_I ~ 1 at the mean density), and reports C_R ~ nH^2.5
+# with C_I = 1 for the densest cells ('A' trends); the normalisations here
+# are chosen in that spirit, the paper gives them only in figures.
+CLUMP_LAWS = {
+    "B": (50.0, 0.7, 2.3, 0.1),
+    "A": (1.0e4, 2.5, 1.0, 0.0),
+}
+
+
 def cosmo_inputs(w: Workload, device: str = "cpu"):
     """(nH tensor on device, ijk, ndot) of a cosmological workload."""
     nH = lognormal_density(w.n, mean=w.nH_mean, device=device)

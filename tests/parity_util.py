@@ -20,12 +20,15 @@ TOL = dict(N=1e-4, F=1e-4, xHI=1e-3, T=1e-3)
 FIELDS = ("N", "Fx", "Fy", "Fz", "xHI", "T")
 
 
-def gpu_params(shape, dx, bc, chem, prec=rt.PREC_FP32, sub=rt.SUB_FIXED, sub_eps=0.1):
-    return rt.make_params(shape, dx, bc=bc, chem=chem, prec=prec, sub=sub, sub_eps=sub_eps)
+def gpu_params(shape, dx, bc, chem, prec=rt.PREC_FP32, sub=rt.SUB_FIXED, sub_eps=0.1,
+               clump=None):
+    return rt.make_params(shape, dx, bc=bc, chem=chem, prec=prec, sub=sub, sub_eps=sub_eps,
+                          clump=clump)
 
 
-def oracle_grid(state, shape, dx, bc, chem, sub=oracle.SUB_FIXED, sub_eps=0.1, sources=None):
-    p = oracle.make_params(shape, dx, bc=bc, chem=chem, sub=sub, sub_eps=sub_eps)
+def oracle_grid(state, shape, dx, bc, chem, sub=oracle.SUB_FIXED, sub_eps=0.1, sources=None,
+                clump=None):
+    p = oracle.make_params(shape, dx, bc=bc, chem=chem, sub=sub, sub_eps=sub_eps, clump=clump)
     g = oracle.Grid(p)
     g.set_state(**{k: np.asarray(state[k], dtype=np.float64) for k in
                    ("N", "Fx", "Fy", "Fz", "xHI", "T", "nH") if k in state})
@@ -55,16 +58,17 @@ def oracle_state(g) -> dict:
 
 
 def one_step_pair(state, shape, dx, dt, nsub, bc, chem, prec=rt.PREC_FP32,
-                  sub=rt.SUB_FIXED, sub_eps=0.1, sources=None):
-    """Step the library and the oracle once from the same state.
+                  sub=rt.SUB_FIXED, sub_eps=0.1, sources=None, clump=None):
+    """Step the library and the oracle once from the same state (``clump``:
+    None or the (cr_norm, cr_exp, ci_norm, ci_exp) laws on both sides).
     Returns (gpu numpy state, oracle numpy state, gpu reductions, oracle grid)."""
-    G = rt.RTGrid(gpu_params(shape, dx, bc, chem, prec, sub, sub_eps), state)
+    G = rt.RTGrid(gpu_params(shape, dx, bc, chem, prec, sub, sub_eps, clump), state)
     if sources is not None:
         G.inject_sources(*sources)
     G.step(dt, nsub)
     red = G.reduce(allow_nonfinite=True)
     out = G.state_numpy()
     G.close()
-    g = oracle_grid(state, shape, dx, bc, chem, sub, sub_eps, sources)
+    g = oracle_grid(state, shape, dx, bc, chem, sub, sub_eps, sources, clump)
     g.step(dt, nsub)
     return out, oracle_state(g), red, g

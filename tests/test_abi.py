@@ -107,7 +107,9 @@ def _params(**kw):
     dict(nx=0), dict(ny=-3), dict(nz=0), dict(nx=2048, ny=2048, nz=2048),
     dict(bc=(0, 1, 0, 0, 0, 0)),          # periodic on one face only
     dict(bc=(5, 5, 0, 0, 0, 0)),
-    dict(chem=7), dict(prec=2), dict(sub=3), dict(reserved=1),
+    dict(chem=7), dict(prec=2), dict(sub=3), dict(clump=2),
+    dict(clump=1, clump_cr_norm=0.0), dict(clump=1, clump_ci_norm=-1.0),
+    dict(clump=1, clump_cr_exp=float("inf")), dict(clump=1, clump_ci_exp=11.0),
     dict(dx_cm=0.0), dict(dx_cm=float("nan")), dict(c_cms=-1.0),
     dict(sigma_n=0.0), dict(T_floor=-1.0), dict(xhi_fp64_thr=2.0),
     dict(sub=1, sub_eps=0.0),
@@ -137,3 +139,13 @@ def test_null_context_is_a_state_error():
     assert L.rt_profile(None, 1) == rt.RT_E_STATE
     assert L.rt_profile_read(None, None, None) == rt.RT_E_STATE
     assert L.rt_destroy(None) == rt.RT_E_STATE
+
+
+@pytest.mark.parametrize("kw", [dict(clump=3), dict(clump=1, clump_cr_norm=float("nan")),
+                                dict(chem=9), dict(sub=1, sub_eps=2.0)])
+def test_chem_apply_rejects_invalid_params_on_host(kw):
+    # validated before any HIP call: no device needed
+    L = rt._bind_extra(rt.lib())
+    p = _params(**kw)
+    rc = L.rt_chem_apply(ctypes.byref(p), 16, None, None, None, None, None, 1, None, None)
+    assert rc == rt.RT_E_ARG

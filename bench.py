@@ -150,7 +150,7 @@ def surrogate_leg(args, G, w, dt, params, src):
     n_pairs = int(X.shape[0])
     del states
     t_pairs = time.perf_counter() - t0
-    s = surrogate.fit(X, Y, steps=args.surrogate_steps, batch=65536, lr=1e-3,
+    s = surrogate.fit(X, Y, steps=args.surrogate_steps, batch=65536, lr=2e-3,
                       grad_blocks=1024, log_every=max(args.surrogate_steps // 6, 1),
                       verbose=False)
     t_train = time.perf_counter() - t0 - t_pairs
@@ -158,7 +158,9 @@ def surrogate_leg(args, G, w, dt, params, src):
     P = surrogate.predict(s, Xv)
     dxv = (10 ** P[:, 0] - 10 ** Yv[:, 0]).abs()
     held = {"pairs": int(Xv.shape[0]), "mean_abs_dxHI": float(dxv.mean()),
-            "p99_abs_dxHI": float(torch.quantile(dxv[:200_000].float(), 0.99))}
+            "p99_abs_dxHI": float(torch.quantile(dxv[:200_000].float(), 0.99)),
+            "loss_untrained": surrogate.mse(surrogate.untrained(s), Xv, Yv),
+            "loss_trained": surrogate.mse(s, Xv, Yv)}
     del Xv, Yv, P, dxv
 
     # the adaptive context starts from a copy of the same state

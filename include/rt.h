@@ -182,10 +182,14 @@ int rt_step(rt_ctx *ctx, double dt, int32_t nsub);
 /* Switch the learned chemistry on (theta != NULL) or off (theta == NULL).
  * Not part of the paper's method.  theta: device, RT_MLP_NPARAM FP32 network
  * parameters (copied into the context's own packed bf16 operands, so the
- * caller may free it afterwards).  norm: host float[24] = mu_in[5],
- * sd_in[5], mu_out[2], sd_out[2] (standardisation of the log10 features nH,
- * xHI, T, N, dt and targets xHI', T') and in_min[5], in_max[5] (the training
- * range of the raw log10 features).  With it on and chem == RT_CHEM_FULL,
+ * caller may free it afterwards).  The network maps the standardised log10
+ * features (nH, xHI, T, N, dt; xHI and N floored at 1e-30) to the
+ * standardised u = asinh(d / 1e-3) of the changes d = log10(xHI'/xHI) and
+ * d = log10(T'/T) over dt (linear for small changes, logarithmic for
+ * large ones; decoded as d = 1e-3 sinh u).  norm: host
+ * float[24] = mu_in[5], sd_in[5], mu_out[2], sd_out[2] (the two
+ * standardisations) and in_min[5], in_max[5] (the training range of the raw
+ * log10 features).  With it on and chem == RT_CHEM_FULL,
  * rt_step evaluates the network on the matrix cores for every cell, derives
  * the absorbed photons from the predicted (xHI', T') (net ionisations +
  * recombinations - collisional ionisations) so the photon budget stays

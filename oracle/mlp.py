@@ -3,7 +3,7 @@ ONLY; not part of the paper, which integrates the chemistry exactly).
 
 Network: 5 standardised inputs (log10 nH, log10 xHI, log10 T, log10 N,
 log10 dt) -> three hidden layers of 64 SiLU units -> 2 standardised outputs
-(log10 xHI', log10 T').  Loss: mean over samples and outputs of the squared
+(the surrogate uses them for asinh-compressed changes of log10 xHI, log10 T).  Loss: mean over samples and outputs of the squared
 error of the standardised outputs.  Parameters are one flat vector in the
 order W1 (64x5), b1, W2 (64x64), b2, W3 (64x64), b3, W4 (2x64), b4 -- each W
 row-major as (out, in) -- 8834 values.

@@ -420,9 +420,16 @@ __global__ __launch_bounds__(NTHREADS, SURR ? 2 : RT_M1_MINW) void m1_step_kerne
             mlp_forward32<false>(spk, mb, xb, unused, yb0, yb1);
             const float sb0 = __shfl(yb0, lane & 31), sb1 = __shfl(yb1, lane & 31);
             const float y0 = lane < 32 ? ya0 : sb0, y1 = lane < 32 ? ya1 : sb1;
-            // decode: log10 xHI', log10 T'
-            const float xs = fexp2((y0 * nm[12] + nm[10]) * 3.321928094887362f);
-            float Ts = fexp2((y1 * nm[13] + nm[11]) * 3.321928094887362f);
+            // decode: the network predicts u = asinh(d / 1e-3) for the
+            // changes d = log10(xHI'/xHI) and log10(T'/T); d = 1e-3 sinh u
+            auto change = [](float u) {
+                const float e = fexp2(u * 1.4426950408889634f);
+                return 0.5e-3f * (e - frcp(e));
+            };
+            const float dx0 = change(y0 * nm[12] + nm[10]);
+            const float dT0 = change(y1 * nm[13] + nm[11]);
+            const float xs = fexp2((f[1] + dx0) * 3.321928094887362f);
+            float Ts = fexp2((f[2] + dT0) * 3.321928094887362f);
             if (A.chem != RT_CHEM_FULL) Ts = c_T;
             // photons absorbed over dt: net ionisations + recombinations -
             // collisional ionisations at the predicted end state

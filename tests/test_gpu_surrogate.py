@@ -1,8 +1,9 @@
 """The learned chemistry surrogate, end to end on the GPU:
 
   * training on exact-operator pairs drawn from an evolved cosmological run
-    (the project's own matrix-core gradient and Adam kernels) lowers the loss
-    and reaches a held-out mean |dxHI| <= 1e-3 against the exact operator;
+    (the project's own matrix-core gradient and Adam kernels) lowers the
+    held-out loss twentyfold and reaches a held-out mean |dxHI| <= 1e-3
+    against the exact operator;
   * the fused step kernel's surrogate path agrees with the batch network on
     the same transported state, cells flagged for fallback equal the exact
     operator, and the photon budget still closes;
@@ -64,16 +65,19 @@ def pairs(run, n_per_state, seed):
 @pytest.fixture(scope="module")
 def trained(run64):
     X, Y = pairs(run64, 200_000, 1)
-    s = surrogate.fit(X, Y, steps=2000, batch=32768, lr=1e-3, grad_blocks=256,
-                      log_every=250, verbose=True)
+    s = surrogate.fit(X, Y, steps=4000, batch=32768, lr=1e-3, grad_blocks=256,
+                      log_every=500, verbose=True)
     return s, X, Y
 
 
 def test_training_lowers_loss_and_meets_accuracy(run64, trained):
     s, X, Y = trained
-    first, last = s.history[0][1], s.history[-1][1]
-    assert last < 0.05 * first, s.history
     Xv, Yv = pairs(run64, 30_000, 99)            # held out
+    # single-batch losses are noisy (heavy-tailed changes): compare the
+    # held-out loss of the untrained and the trained network
+    before, after = surrogate.mse(surrogate.untrained(s), Xv, Yv), surrogate.mse(s, Xv, Yv)
+    print(f"held-out loss {before:.3e} -> {after:.3e}", flush=True)
+    assert after < 0.05 * before, (before, after, s.history)
     P = surrogate.predict(s, Xv)
     dx = (10 ** P[:, 0] - 10 ** Yv[:, 0]).abs()
     mean_dx = float(dx.mean())

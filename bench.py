@@ -244,6 +244,29 @@ def diagnostics_leg(G, w, reps: int = 5):
     return out
 
 
+def sources_leg(G, w, nH_dev, n: int = 1_000_000, reps: int = 3):
+    """Time rt_sources_from_particles: n seeded star particles in the
+    densest cells of the grid (Sec. 2.3 pipeline: lifetimes, interval
+    dilution, escape fraction and boost, NGP binning into the per-tile
+    source lists).  Replaces the grid's sources, so it runs last."""
+    import torch
+
+    from paper_1004_2503_amd import workloads as W
+
+    parts = W.star_particles(nH_dev, w.dx, n)
+    d = {k: torch.tensor(v, dtype=torch.float64, device="cuda").contiguous()
+         for k, v in parts.items()}
+    myr = W.MYR_S
+    args = (700 * myr, 703 * myr, 0.02, 1.2, 3000 * myr)
+    G.sources_from_particles(d, *args)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        m = G.sources_from_particles(d, *args)
+    dt = (time.perf_counter() - t0) / reps
+    return {"particles": n, "emitting": m, "ms": dt * 1e3}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -348,6 +371,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(G, w, dt, args.nsub, args.cpu_seconds, args.chem, clump)
+    srcs = sources_leg(G, w, G.nH)
     G.close()
 
     out = {
@@ -375,6 +399,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "diagnostics": diag,
+        "source_pipeline": srcs,
         "surrogate": surr,
         "hbm_frac_whole_step": BYTES_PER_CELL * value / (HBM_PEAK_GBS * 1e9),
         "state_after": {"xhi_vol": red["xhi_vol"], "xhi_mass": red["xhi_mass"],

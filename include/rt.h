@@ -170,6 +170,30 @@ int rt_init(const rt_params *params, const rt_fields *fields, void *hip_stream,
 int rt_inject_sources(rt_ctx *ctx, int64_t n, const int32_t *ijk,
                       const double *ndot);
 
+/* Sources from the stellar particles of a snapshot (Sec. 2.3), for the
+ * interval [t_p, t_next] (seconds, 0 < t_p < t_next; t is the age of the
+ * Universe); replaces the context's source set like rt_inject_sources.
+ * Device arrays of n particles: pos (3n doubles, x y z in cm, wrapped into
+ * the periodic box of nx*dx by ny*dx by nz*dx), age_next (age at t_next, s),
+ * lifetime (ionising lifetime L > 0, s), q_per_baryon (ionising photons per
+ * stellar baryon over L, >= 0), mass_g (>= 0, g).  A particle emits
+ * Ndot = Q m / m_b / L (m_b = 1.67262192e-24 g) while its age lies in
+ * [0, L]; over the interval it is given the rate Ndot * overlap / Delta
+ * (Delta = t_next - t_p; overlap = the time its emitting ages share with
+ * [age_next - Delta, age_next]: the photons it emits within the interval,
+ * spread evenly over it), times f_esc (in [0, 1]) and the boost factor
+ * B = max(1, a_b exp(k_b / t_mid)) at the interval's middle (a_b >= 0,
+ * k_b >= 0 in s).  Each particle goes to the cell holding it (nearest grid
+ * point), duplicate cells summed in particle order.  *n_active (host, may be
+ * NULL) receives the number of emitting particles.  RT_E_ARG for invalid
+ * scalars or particles (non-finite values, L <= 0, negative Q or m), leaving
+ * the previous source set.  Waits for the stream. */
+int rt_sources_from_particles(rt_ctx *ctx, int64_t n, const double *pos,
+                              const double *age_next, const double *lifetime,
+                              const double *q_per_baryon, const double *mass_g, double t_p,
+                              double t_next, double f_esc, double a_b, double k_b,
+                              int64_t *n_active);
+
 /* Advance one radiative-transfer step of length dt (Appendix A): the
  * unsplit explicit update of (N, F) with Lax-Friedrichs fluxes of the M1
  * system plus dt*S, then Phi per cell -- nsub chemistry sub-cycles (fixed

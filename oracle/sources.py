@@ -24,6 +24,8 @@ cells summed.
 
 from __future__ import annotations
 
+import math
+
 import numpy as np
 
 M_BARYON = 1.67262192e-24   # g (proton mass)
@@ -46,8 +48,8 @@ def intrinsic_rate(q_per_baryon, mass_g, lifetime):
 
 
 def boost(t, a_b, k_b):
-    """B(t) = max(1, a_b exp(k_b / t))."""
-    return max(1.0, a_b * np.exp(k_b / t))
+    """B(t) = max(1, a_b exp(k_b / t)), exp from the host libm."""
+    return max(1.0, a_b * math.exp(k_b / t))
 
 
 def particle_rates(age_next, lifetime, q_per_baryon, mass_g, t_p, t_next, f_esc, a_b, k_b):

@@ -210,6 +210,80 @@ extern "C" int rt_inject_sources(rt_ctx *c, int64_t n, const int32_t *ijk, const
     if (!c) return RT_E_STATE;
     if (n < 0 || n > (int64_t(1) << 31) - 1) return RT_E_ARG;
     if (n > 0 && (!ijk || !ndot)) return RT_E_ARG;
+    return rtk::inject_host(c, n, ijk, ndot);
+}
+
+extern "C" int rt_sources_from_particles(rt_ctx *c, int64_t n, const double *pos,
+                                         const double *age_next, const double *lifetime,
+                                         const double *q_per_baryon, const double *mass_g,
+                                         double t_p, double t_next, double f_esc, double a_b,
+                                         double k_b, int64_t *n_active)
+{
+    if (!c) return RT_E_STATE;
+    if (n < 0 || n > (int64_t(1) << 31) - 1) return RT_E_ARG;
+    if (n > 0 && (!pos || !age_next || !lifetime || !q_per_baryon || !mass_g)) return RT_E_ARG;
+    if (!(t_p > 0.0) || !(t_next > t_p) || !isfinite(t_next)) return RT_E_ARG;
+    if (!(f_esc >= 0.0 && f_esc <= 1.0)) return RT_E_ARG;
+    if (!(a_b >= 0.0) || !isfinite(a_b) || !(k_b >= 0.0) || !isfinite(k_b)) return RT_E_ARG;
+    // boost factor at the middle of the interval (libm exp, as on any host)
+    const double t_mid = 0.5 * (t_p + t_next);
+    const double boost = fmax(1.0, a_b * exp(k_b / t_mid));
+    if (!isfinite(boost)) return RT_E_ARG;
+    if (n == 0) {
+        if (n_active) *n_active = 0;
+        return inject_host(c, 0, nullptr, nullptr);
+    }
+    int32_t *d_ijk = nullptr, *d_bad = nullptr;
+    double *d_rate = nullptr;
+    if (hipMalloc(&d_ijk, size_t(n) * 3 * sizeof(int32_t)) != hipSuccess ||
+        hipMalloc(&d_rate, size_t(n) * sizeof(double)) != hipSuccess ||
+        hipMalloc(&d_bad, sizeof(int32_t)) != hipSuccess) {
+        (void)hipGetLastError();
+        if (d_ijk) (void)hipFree(d_ijk);
+        if (d_rate) (void)hipFree(d_rate);
+        return RT_E_NOMEM;
+    }
+    std::vector<int32_t> ijk(static_cast<size_t>(n) * 3);
+    std::vector<double> rate(static_cast<size_t>(n));
+    int32_t bad = 0;
+    const rt_params &p = c->p;
+    int rc = RT_OK;
+    if (hipMemsetAsync(d_bad, 0, sizeof(int32_t), c->stream) != hipSuccess ||
+        launch_particle_rates(n, pos, age_next, lifetime, q_per_baryon, mass_g, t_next - t_p,
+                              f_esc, boost, p.dx_cm, p.nx, p.ny, p.nz, d_ijk, d_rate, d_bad,
+                              c->stream) != hipSuccess ||
+        hipMemcpyAsync(ijk.data(), d_ijk, ijk.size() * sizeof(int32_t), hipMemcpyDeviceToHost,
+                       c->stream) != hipSuccess ||
+        hipMemcpyAsync(rate.data(), d_rate, rate.size() * sizeof(double),
+                       hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+        hipMemcpyAsync(&bad, d_bad, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream) !=
+            hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess)
+        rc = RT_E_HIP;
+    (void)hipFree(d_ijk);
+    (void)hipFree(d_rate);
+    (void)hipFree(d_bad);
+    if (rc != RT_OK) return rc;
+    if (bad) return RT_E_ARG;   // the old source set stays
+    // emitting particles, in particle order
+    int64_t m = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        if (rate[size_t(i)] > 0.0) {
+            ijk[size_t(3 * m)] = ijk[size_t(3 * i)];
+            ijk[size_t(3 * m + 1)] = ijk[size_t(3 * i + 1)];
+            ijk[size_t(3 * m + 2)] = ijk[size_t(3 * i + 2)];
+            rate[size_t(m)] = rate[size_t(i)];
+            ++m;
+        }
+    }
+    if (n_active) *n_active = m;
+    return inject_host(c, m, ijk.data(), rate.data());
+}
+
+// Bin host sources into the per-tile lists (duplicate cells summed in input
+// order) and replace the context's source set.
+int rtk::inject_host(rt_ctx *c, int64_t n, const int32_t *ijk, const double *ndot)
+{
     const rt_params &p = c->p;
     struct Src {
         int32_t tile, key;
@@ -229,7 +303,9 @@ extern "C" int rt_inject_sources(rt_ctx *c, int64_t n, const int32_t *ijk, const
         v.push_back({tile, key, q});
         total += q;
     }
-    std::sort(v.begin(), v.end(), [](const Src &a, const Src &b) {
+    // stable: duplicate cells are summed in input order, so the result does
+    // not depend on the sort's tie-breaking
+    std::stable_sort(v.begin(), v.end(), [](const Src &a, const Src &b) {
         return a.tile != b.tile ? a.tile < b.tile : a.key < b.key;
     });
     // merge duplicate cells (nearest-grid-point projection sums them)

@@ -84,6 +84,12 @@ constexpr int SURR_NNORM = 24;
 
 hipError_t launch_step(const StepArgs &a, hipStream_t s);
 ClumpLaw make_clump_law(const rt_params &p);
+int inject_host(rt_ctx *c, int64_t n, const int32_t *ijk, const double *ndot);
+hipError_t launch_particle_rates(int64_t n, const double *pos, const double *age_next,
+                                 const double *lifetime, const double *q, const double *mass,
+                                 double delta, double f_esc, double boost, double dx, int nx,
+                                 int ny, int nz, int32_t *ijk, double *rate, int32_t *bad,
+                                 hipStream_t s);
 int check_clump(const rt_params &p);
 hipError_t launch_mlp_pack(const float *theta, __bf16 *pk, hipStream_t s);
 // mode 0 also adds tau_coef * (nh_sum - sum nH xHI) to acc[ACC_CUM + ACC_TAU]

@@ -284,6 +284,16 @@ class RTGrid:
             out[name] = a
         return out
 
+    def sources_from_particles(self, parts: dict, t_p, t_next, f_esc, a_b, k_b) -> int:
+        """Replace the sources by those of a particle set (dict of float64
+        device tensors pos, age_next, lifetime, q, mass); returns the number
+        of emitting particles."""
+        rc, m = rt_sources_from_particles(self.ctx, parts["pos"], parts["age_next"],
+                                          parts["lifetime"], parts["q"], parts["mass"], t_p,
+                                          t_next, f_esc, a_b, k_b)
+        check(rc, "rt_sources_from_particles")
+        return m
+
     def histogram(self, quantity: int, xrange, yrange):
         """(counts, per-density-bin sums) of the current state, see rt_histogram."""
         rc, counts, sums = rt_histogram(self.ctx, quantity, xrange, yrange)
@@ -376,7 +386,29 @@ def rt_mlp_destroy(m) -> int:
     return _bind_extra(lib()).rt_mlp_destroy(m)
 
 
-EXPORTS += ["rt_set_surrogate"]
+EXPORTS += ["rt_set_surrogate", "rt_sources_from_particles"]
+
+
+def rt_sources_from_particles(ctx, pos, age_next, lifetime, q_per_baryon, mass_g, t_p: float,
+                              t_next: float, f_esc: float, a_b: float, k_b: float):
+    """Particles as float64 device tensors (pos (n, 3) in cm, the rest (n,)).
+    Returns (code, number of emitting particles)."""
+    L = lib()
+    vp = ctypes.c_void_p
+    L.rt_sources_from_particles.argtypes = [vp, ctypes.c_int64, vp, vp, vp, vp, vp] + [
+        ctypes.c_double] * 5 + [ctypes.POINTER(ctypes.c_int64)]
+    L.rt_sources_from_particles.restype = ctypes.c_int
+    n = int(age_next.numel())
+    for t in (lifetime, q_per_baryon, mass_g):
+        if t.numel() != n:
+            return RT_E_ARG, 0
+    if pos.numel() != 3 * n:
+        return RT_E_ARG, 0
+    out = ctypes.c_int64(0)
+    rc = L.rt_sources_from_particles(ctx, n, _p(pos), _p(age_next), _p(lifetime),
+                                     _p(q_per_baryon), _p(mass_g), float(t_p), float(t_next),
+                                     float(f_esc), float(a_b), float(k_b), ctypes.byref(out))
+    return rc, out.value
 
 
 def rt_set_surrogate(ctx, theta, norm, residual_tol: float) -> int:

@@ -185,6 +185,39 @@ CLUMP_LAWS = {
 }
 
 
+SEED_PARTICLES = 20100418
+M_SUN = 1.98892e33        # g
+MYR_S = 3.15576e13        # s
+
+
+def star_particles(nH, dx: float, n: int, seed: int = SEED_PARTICLES, hosts: int = 4096,
+                   mass_msun: float = 5.81e4, max_age_myr: float = 30.0):
+    """Seeded synthetic stellar particles standing in for a snapshot's
+    (Sec. 2.3 uses the simulations' star particles, not available here):
+    n particles placed uniformly inside the `hosts` densest cells of nH
+    (several per cell, so cells hold duplicates), a few shifted by one box
+    length to exercise the periodic wrap; ages at the snapshot uniform in
+    [0, max_age] Myr, ionising lifetimes uniform in [5, 20] Myr, photons per
+    stellar baryon uniform in [24000, 98000], masses mass_msun.  Returns a
+    dict of float64 numpy arrays: pos (n, 3) [cm], age_next [s],
+    lifetime [s], q, mass [g]."""
+    import torch
+
+    nz, ny, nx = nH.shape
+    cells = densest_cells(torch.as_tensor(nH), min(hosts, int(np.prod(nH.shape))))
+    rng = np.random.Generator(np.random.PCG64(seed))
+    pick = cells[rng.integers(0, len(cells), n)].astype(np.float64)
+    pos = (pick + rng.random((n, 3))) * dx
+    shift = rng.random(n) < 0.02
+    box = np.array([nx, ny, nz], dtype=np.float64) * dx
+    pos[shift] += box * rng.choice([-1.0, 1.0], (int(shift.sum()), 3))
+    return dict(pos=pos,
+                age_next=rng.uniform(0.0, max_age_myr, n) * MYR_S,
+                lifetime=rng.uniform(5.0, 20.0, n) * MYR_S,
+                q=rng.uniform(24000.0, 98000.0, n),
+                mass=np.full(n, mass_msun * M_SUN))
+
+
 def cosmo_inputs(w: Workload, device: str = "cpu"):
     """(nH tensor on device, ijk, ndot) of a cosmological workload."""
     nH = lognormal_density(w.n, mean=w.nH_mean, device=device)

@@ -23,6 +23,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 BC_PERIODIC, BC_OUTFLOW, BC_REFLECT, BC_GIVEN = 0, 1, 2, 3
 CHEM_FULL, CHEM_ISOTHERMAL, CHEM_OFF, CHEM_FROZEN = 0, 1, 2, 3
 SUB_FIXED, SUB_ADAPTIVE = 0, 1
+FLUX_LF, FLUX_HLL = 0, 1
 
 # gray single-group constants of Sec. 2.2 and the physical constants
 SIGMA_N = 2.93e-18
@@ -46,7 +47,7 @@ class Params(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
                 ("nz", ctypes.c_int32), ("bc", ctypes.c_int32 * 6),
                 ("chem", ctypes.c_int32), ("sub", ctypes.c_int32),
-                ("clump", ctypes.c_int32),
+                ("clump", ctypes.c_int32), ("flux", ctypes.c_int32),
                 ("dx", ctypes.c_double), ("c", ctypes.c_double),
                 ("sigma_n", ctypes.c_double), ("sigma_e", ctypes.c_double),
                 ("egamma_eV", ctypes.c_double), ("T_floor", ctypes.c_double),
@@ -71,6 +72,9 @@ def lib():
         L.orc_eddington.argtypes = [ctypes.c_double] * 5 + [dp]
         L.orc_rates.restype = None
         L.orc_rates.argtypes = [ctypes.c_double, dp]
+        L.orc_step_flux.restype = ctypes.c_int32
+        L.orc_step_flux.argtypes = [ctypes.POINTER(Params), ctypes.c_double, ctypes.c_int32] + [
+            dp] * 10
         L.orc_clumping.restype = None
         L.orc_clumping.argtypes = [ctypes.POINTER(Params), ctypes.c_double, dp, dp]
         L.orc_heat_per_ionisation_erg.restype = ctypes.c_double
@@ -103,14 +107,14 @@ def _ptr(a):
 
 def make_params(shape, dx, bc=(0,) * 6, chem=CHEM_FULL, sub=SUB_FIXED,
                 c=C_LIGHT, sigma_n=SIGMA_N, sigma_e=SIGMA_E, egamma_eV=EGAMMA_EV,
-                T_floor=10.0, sub_eps=0.1, clump=None) -> Params:
+                T_floor=10.0, sub_eps=0.1, clump=None, flux=0) -> Params:
     """``shape`` is (nz, ny, nx), the numpy order of every field.  ``clump``
     is None (no subgrid clumping) or (cr_norm, cr_exp, ci_norm, ci_exp):
     C_R = max(1, cr_norm nH^cr_exp), C_I = ci_norm nH^ci_exp."""
     nz, ny, nx = shape
     cl = (0.0, 0.0, 1.0, 0.0) if clump is None else tuple(float(v) for v in clump)
     return Params(nx, ny, nz, (ctypes.c_int32 * 6)(*bc), chem, sub,
-                  0 if clump is None else 1, dx, c,
+                  0 if clump is None else 1, int(flux), dx, c,
                   sigma_n, sigma_e, egamma_eV, T_floor, sub_eps, *cl)
 
 
@@ -227,7 +231,29 @@ class Grid:
                 _ptr(self.S))
         self.nsrc_rate = float(np.sum(ndot))
 
+    def _lam(self):
+        """Per padded cell extreme Jacobian eigenvalues (HLL), ghosts filled."""
+        from . import hll
+        self.fill_ghosts()
+        return np.ascontiguousarray(hll.eigen_extremes(*self._U, self.p.c))
+
     def step(self, dt, nsub=1, nsteps=1):
+        if self.p.flux == FLUX_HLL:
+            acc = np.zeros(4)
+            for _ in range(int(nsteps)):
+                lam = self._lam()
+                tl = np.zeros(4)
+                rc = lib().orc_step_flux(ctypes.byref(self.p), float(dt), int(nsub),
+                                         *[_ptr(u) for u in self._U], _ptr(self.xHI),
+                                         _ptr(self.T), _ptr(self.nH), _ptr(self.S), _ptr(lam),
+                                         _ptr(tl))
+                if rc != 0:
+                    raise ValueError(f"orc_step_flux failed with {rc}")
+                acc += tl
+            self.tally += acc
+            self.emitted += self.nsrc_rate * dt * nsteps
+            self.t += dt * nsteps
+            return acc
         tl = np.zeros(4)
         rc = lib().orc_run(ctypes.byref(self.p), float(dt), int(nsub), int(nsteps),
                            *[_ptr(u) for u in self._U], _ptr(self.xHI),
@@ -286,8 +312,14 @@ def step_subblock(params: Params, dt, nsub, Npad, Fpad, xHI, T, nH, S=None):
     S = None if S is None else np.ascontiguousarray(S, dtype=np.float64)
     U = [u.copy() for u in U]
     tl = np.zeros(4)
-    rc = lib().orc_step(ctypes.byref(p), float(dt), int(nsub), *[_ptr(u) for u in U],
-                        _ptr(xHI), _ptr(T), _ptr(nH), _ptr(S), _ptr(tl))
+    if p.flux == FLUX_HLL:
+        from . import hll
+        lam = np.ascontiguousarray(hll.eigen_extremes(*U, p.c))
+        rc = lib().orc_step_flux(ctypes.byref(p), float(dt), int(nsub), *[_ptr(u) for u in U],
+                                 _ptr(xHI), _ptr(T), _ptr(nH), _ptr(S), _ptr(lam), _ptr(tl))
+    else:
+        rc = lib().orc_step(ctypes.byref(p), float(dt), int(nsub), *[_ptr(u) for u in U],
+                            _ptr(xHI), _ptr(T), _ptr(nH), _ptr(S), _ptr(tl))
     if rc != 0:
         raise ValueError(f"orc_step failed with {rc}")
     inner = tuple(u[1:-1, 1:-1, 1:-1].copy() for u in U)

@@ -307,6 +307,30 @@ static void lf_flux(int d, const double UL[4], const double PL[6],
                    0.5 * c * (UR[1 + k] - UL[1 + k]);
 }
 
+/* HLL (Sec. 2.2 names it beside LF): with the signal speeds
+ * a+ = c max(0, lmax_L, lmax_R) and a- = c min(0, lmin_L, lmin_R),
+ *   G = (a+ G(U_L) - a- G(U_R) + a+ a- (U_R - U_L)) / (a+ - a-). */
+static void hll_flux(int d, const double UL[4], const double PL[6], const double lL[2],
+                     const double UR[4], const double PR[6], const double lR[2],
+                     double c, double G[4])
+{
+    double GL[4], GR[4];
+    GL[0] = UL[1 + d];
+    GR[0] = UR[1 + d];
+    for (int k = 0; k < 3; ++k) {
+        GL[1 + k] = c * c * pcomp(PL, k, d);
+        GR[1 + k] = c * c * pcomp(PR, k, d);
+    }
+    double ap = c * fmax(0.0, fmax(lL[1], lR[1]));
+    double am = c * fmin(0.0, fmin(lL[0], lR[0]));
+    if (!(ap - am > 0.0)) {
+        for (int m = 0; m < 4; ++m) G[m] = 0.5 * (GL[m] + GR[m]);
+        return;
+    }
+    for (int m = 0; m < 4; ++m)
+        G[m] = (ap * GL[m] - am * GR[m] + ap * am * (UR[m] - UL[m])) / (ap - am);
+}
+
 static int check_params(const orc_params *p)
 {
     if (p->nx < 1 || p->ny < 1 || p->nz < 1) return -1;
@@ -319,6 +343,7 @@ static int check_params(const orc_params *p)
     if (p->chem < 0 || p->chem > ORC_CHEM_FROZEN) return -1;
     if (p->sub != ORC_SUB_FIXED && p->sub != ORC_SUB_ADAPTIVE) return -1;
     if (!(p->dx > 0.0) || !(p->c > 0.0)) return -1;
+    if (p->flux != ORC_FLUX_LF && p->flux != ORC_FLUX_HLL) return -1;
     return 0;
 }
 
@@ -332,7 +357,16 @@ int32_t orc_step(const orc_params *p, double dt, int32_t nsub, double *N,
                  double *Fx, double *Fy, double *Fz, double *xHI, double *T,
                  const double *nH, const double *S, double *tally)
 {
+    return orc_step_flux(p, dt, nsub, N, Fx, Fy, Fz, xHI, T, nH, S, NULL, tally);
+}
+
+int32_t orc_step_flux(const orc_params *p, double dt, int32_t nsub, double *N,
+                      double *Fx, double *Fy, double *Fz, double *xHI, double *T,
+                      const double *nH, const double *S, const double *lam,
+                      double *tally)
+{
     if (check_params(p) != 0 || nsub < 1 || !(dt > 0.0)) return -1;
+    if (p->flux == ORC_FLUX_HLL && !lam) return -1;
     const int nx = p->nx, ny = p->ny, nz = p->nz;
     const size_t npad = (size_t)(nx + 2) * (ny + 2) * (nz + 2);
     const double c = p->c, vol = p->dx * p->dx * p->dx;
@@ -375,8 +409,15 @@ int32_t orc_step(const orc_params *p, double dt, int32_t nsub, double *N,
                         Um[m] = U[m][qm];
                         Up[m] = U[m][qp];
                     }
-                    lf_flux(d, Um, P + 6 * qm, Uc, P + 6 * q, c, Gm);
-                    lf_flux(d, Uc, P + 6 * q, Up, P + 6 * qp, c, Gp);
+                    if (p->flux == ORC_FLUX_HLL) {
+                        hll_flux(d, Um, P + 6 * qm, lam + 6 * qm + 2 * d, Uc, P + 6 * q,
+                                 lam + 6 * q + 2 * d, c, Gm);
+                        hll_flux(d, Uc, P + 6 * q, lam + 6 * q + 2 * d, Up, P + 6 * qp,
+                                 lam + 6 * qp + 2 * d, c, Gp);
+                    } else {
+                        lf_flux(d, Um, P + 6 * qm, Uc, P + 6 * q, c, Gm);
+                        lf_flux(d, Uc, P + 6 * q, Up, P + 6 * qp, c, Gp);
+                    }
                     for (int m = 0; m < 4; ++m) div[m] += Gp[m] - Gm[m];
                     /* photons leaving through outflow faces */
                     if (ijk[d] == 0 && p->bc[2 * d] == ORC_BC_OUTFLOW)

@@ -54,6 +54,10 @@ extern "C" {
 #define ORC_CHEM_OFF 2        /* transport and sources only                  */
 #define ORC_CHEM_FROZEN 3     /* absorption by a fixed neutral density only  */
 
+/* intercell flux (Sec. 2.2 names both; the paper's runs use LF) */
+#define ORC_FLUX_LF 0  /* Lax-Friedrichs (Rusanov), dissipation speed c          */
+#define ORC_FLUX_HLL 1 /* HLL with the extreme eigenvalues of the flux Jacobian */
+
 /* sub-cycle modes */
 #define ORC_SUB_FIXED 0
 #define ORC_SUB_ADAPTIVE 1
@@ -73,6 +77,7 @@ typedef struct {
     int32_t chem;
     int32_t sub;
     int32_t clump;    /* 0 off, 1 power-law clumping factors    */
+    int32_t flux;     /* ORC_FLUX_LF or ORC_FLUX_HLL            */
     double dx;        /* cell size [cm]                         */
     double c;         /* speed of light [cm/s]                  */
     double sigma_n;   /* number-averaged cross-section [cm^2]   */
@@ -109,6 +114,15 @@ int32_t orc_step(const orc_params *p, double dt, int32_t nsub, double *N,
                  double *Fx, double *Fy, double *Fz, double *xHI, double *T,
                  const double *nH, const double *S, double *tally);
 
+/* One step as orc_step, with HLL face fluxes when p->flux == ORC_FLUX_HLL:
+ * lam holds, for every cell of the PADDED grid (ghosts included, filled
+ * from the boundary conditions before the call), the smallest and largest
+ * eigenvalue of the flux Jacobian along x, y, z in units of c: 6 doubles
+ * per cell (min x, max x, min y, max y, min z, max z). */
+int32_t orc_step_flux(const orc_params *p, double dt, int32_t nsub, double *N,
+                      double *Fx, double *Fy, double *Fz, double *xHI, double *T,
+                      const double *nH, const double *S, const double *lam,
+                      double *tally);
 int32_t orc_run(const orc_params *p, double dt, int32_t nsub, int64_t nsteps,
                 double *N, double *Fx, double *Fy, double *Fz, double *xHI,
                 double *T, const double *nH, const double *S, double *tally);

@@ -244,6 +244,39 @@ def diagnostics_leg(G, w, reps: int = 5):
     return out
 
 
+def hll_leg(G, w, dt, params, src, nsub: int, steps: int = 20):
+    """Time the step with HLL intercell fluxes (Sec. 2.2) on a copy of the
+    run's current state: same fields read and written (52 bytes per cell),
+    the six signal speeds of every cell computed in the kernel.  Kernel time
+    from the library's own events, as for the main step."""
+    import torch
+
+    from paper_1004_2503_amd import rt
+
+    ph = rt.rt_params.from_buffer_copy(params)
+    ph.flux = rt.FLUX_HLL
+    H = rt.RTGrid(ph, {k: v for k, v in G.tensors().items()}, device=G.device)
+    H.inject_sources(*src)
+    H.step(dt, nsub, 2)
+    torch.cuda.synchronize()
+    H.profile(True)
+    t0 = time.perf_counter()
+    H.step(dt, nsub, steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_kernel, launches = H.profile_read()
+    H.profile(False)
+    red = H.reduce()
+    H.close()
+    del H
+    torch.cuda.empty_cache()
+    avg = ms_kernel / max(launches, 1)
+    gbs = BYTES_PER_CELL * w.cells / (avg * 1e-3) / 1e9
+    return {"steps": steps, "ms_per_step": wall / steps * 1e3, "avg_launch_ms": avg,
+            "achieved_GBs": gbs, "frac": gbs / HBM_PEAK_GBS,
+            "n_nonfinite": red["n_nonfinite"]}
+
+
 def sources_leg(G, w, nH_dev, n: int = 1_000_000, reps: int = 3):
     """Time rt_sources_from_particles: n seeded star particles in the
     densest cells of the grid (Sec. 2.3 pipeline: lifetimes, interval
@@ -279,6 +312,10 @@ def main():
     ap.add_argument("--chem", default="full", choices=["full", "isothermal", "off"])
     ap.add_argument("--clump", default=None, choices=["A", "B"],
                     help="subgrid clumping laws in the chemistry (default: none)")
+    ap.add_argument("--flux", default="lf", choices=["lf", "hll"],
+                    help="intercell flux of the timed step (the paper's runs use LF)")
+    ap.add_argument("--no-hll", action="store_true",
+                    help="skip the extra timing of the HLL step on the evolved state")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="instead of the step, time a plain device copy of MIB MiB "
@@ -292,6 +329,8 @@ def main():
     ap.add_argument("--adaptive-cap", type=int, default=32,
                     help="sub-cycle cap of the adaptive forms in the surrogate comparison")
     args = ap.parse_args()
+    if args.surrogate and args.flux == "hll":
+        ap.error("the learned chemistry runs with LF fluxes only")
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the fused step kernel runs on a single "
@@ -332,7 +371,8 @@ def main():
 
     chem = {"full": rt.CHEM_FULL, "isothermal": rt.CHEM_ISOTHERMAL, "off": rt.CHEM_OFF}[args.chem]
     clump = None if args.clump is None else W.CLUMP_LAWS[args.clump]
-    params = rt.make_params((w.n,) * 3, w.dx, chem=chem, prec=prec, clump=clump)
+    flux = rt.FLUX_HLL if args.flux == "hll" else rt.FLUX_LF
+    params = rt.make_params((w.n,) * 3, w.dx, chem=chem, prec=prec, clump=clump, flux=flux)
     T0 = torch.full((w.n,) * 3, w.T0, dtype=torch.float32, device=dev)
     G = rt.RTGrid(params, dict(nH=nH, T=T0), device=dev)
     del nH, T0
@@ -363,6 +403,9 @@ def main():
             "bytes_per_cell": BYTES_PER_CELL}
 
     diag = diagnostics_leg(G, w)
+    hll = None
+    if flux == rt.FLUX_LF and not args.no_hll:
+        hll = hll_leg(G, w, dt, params, (ijk, ndot), args.nsub)
 
     surr = None
     if args.surrogate:
@@ -391,15 +434,17 @@ def main():
                                f"{len(ijk)} sources, plain exact chemistry"
                                + ("" if args.chem == "full" else f" (chemistry {args.chem})")
                                + ("" if clump is None else
-                                  f", subgrid clumping {args.clump} laws {clump}"),
+                                  f", subgrid clumping {args.clump} laws {clump}")
+                               + ("" if flux == rt.FLUX_LF else ", HLL fluxes"),
                    "grid": w.n, "sources": len(ijk), "nsub": args.nsub, "chem": args.chem,
-                   "clump": args.clump,
+                   "clump": args.clump, "flux": args.flux,
                    "precision": args.prec, "dt_s": dt, "dx_cm": w.dx,
                    "parallelism": "single GPU, whole grid"},
         "roofline": roof,
         "cpu_baseline": cpu,
         "diagnostics": diag,
         "source_pipeline": srcs,
+        "hll_step": hll,
         "surrogate": surr,
         "hbm_frac_whole_step": BYTES_PER_CELL * value / (HBM_PEAK_GBS * 1e9),
         "state_after": {"xhi_vol": red["xhi_vol"], "xhi_mass": red["xhi_mass"],

@@ -53,6 +53,11 @@ extern "C" {
 #define RT_CHEM_OFF 2        /* transport and sources only                 */
 #define RT_CHEM_FROZEN 3     /* absorption by the fixed neutral density    */
 
+/* ---- intercell flux of the transport (Sec. 2.2) ------------------------- */
+#define RT_FLUX_LF 0  /* Lax-Friedrichs: signal speeds -c, +c (the paper's) */
+#define RT_FLUX_HLL 1 /* HLL: signal speeds c times the extreme eigenvalues
+                         of the M1 flux Jacobian on the two sides of a face */
+
 /* ---- precision of the chemistry ---------------------------------------- */
 #define RT_PREC_FP32 0  /* every cell in FP32                               */
 #define RT_PREC_MIXED 1 /* FP64 for cells with xHI < xhi_fp64_thr at step
@@ -112,6 +117,7 @@ typedef struct {
     int32_t prec;
     int32_t sub;
     int32_t clump;    /* 0 off, 1 power-law clumping factors */
+    int32_t flux;     /* RT_FLUX_LF or RT_FLUX_HLL */
     double dx_cm;
     double c_cms;
     double sigma_n;
@@ -195,8 +201,8 @@ int rt_sources_from_particles(rt_ctx *ctx, int64_t n, const double *pos,
                               int64_t *n_active);
 
 /* Advance one radiative-transfer step of length dt (Appendix A): the
- * unsplit explicit update of (N, F) with Lax-Friedrichs fluxes of the M1
- * system plus dt*S, then Phi per cell -- nsub chemistry sub-cycles (fixed
+ * unsplit explicit update of (N, F) with the intercell fluxes of
+ * rt_params.flux (Lax-Friedrichs or HLL) of the M1 system plus dt*S, then Phi per cell -- nsub chemistry sub-cycles (fixed
  * mode) or at most nsub (adaptive mode) -- and the global sums, all in one
  * fused kernel followed by a one-block finalisation.  dt must satisfy
  * dt <= dx/(3c) (the CFL bound of Sec. 2.2 for the 3-D unsplit update;

@@ -82,6 +82,7 @@ static int check_params(const rt_params *p)
     if (p->prec != RT_PREC_FP32 && p->prec != RT_PREC_MIXED) return RT_E_ARG;
     if (p->sub != RT_SUB_FIXED && p->sub != RT_SUB_ADAPTIVE) return RT_E_ARG;
     if (check_clump(*p) != RT_OK) return RT_E_ARG;
+    if (p->flux != RT_FLUX_LF && p->flux != RT_FLUX_HLL) return RT_E_ARG;
     if (!(p->dx_cm > 0.0) || !isfinite(p->dx_cm)) return RT_E_ARG;
     if (!(p->c_cms > 0.0) || !isfinite(p->c_cms)) return RT_E_ARG;
     if (!(p->sigma_n > 0.0) || !(p->sigma_e > 0.0) || !(p->egamma_eV > 0.0)) return RT_E_ARG;
@@ -447,6 +448,8 @@ static void fill_args(const rt_ctx *c, double dt, int nsub, StepArgs &a)
     a.sub_eps_d = p.sub_eps;
     a.vol = p.dx_cm * p.dx_cm * p.dx_cm;
     a.esc_scale = dt * p.dx_cm * p.dx_cm;
+    a.hll = p.flux == RT_FLUX_HLL ? 1 : 0;
+    a.c_d = p.c_cms;
     a.surr = c->surr ? 1 : 0;
     a.surr_pk = c->d_surr_pk;
     a.surr_bias = c->d_surr_bias;
@@ -503,6 +506,7 @@ extern "C" int rt_set_surrogate(rt_ctx *c, const float *theta, const float *norm
         return RT_OK;
     }
     if (!norm || !(residual_tol > 0.0) || !isfinite(residual_tol)) return RT_E_ARG;
+    if (c->p.flux != RT_FLUX_LF) return RT_E_ARG;   // surrogate step: LF only
     for (int k = 0; k < SURR_NNORM; ++k)
         if (!isfinite(norm[k])) return RT_E_ARG;
     for (int k = 0; k < 7; ++k)

@@ -58,6 +58,75 @@ __device__ __forceinline__ Press closure(float N, float Fx, float Fy, float Fz,
     return P;
 }
 
+// ------------------------------------------------- HLL signal speeds
+// Sec. 2.2 names HLL beside LF.  Its speeds are c times the smallest and
+// largest eigenvalue of the M1 flux Jacobian along an axis.  With f the
+// reduced flux, mu the cosine of its angle to the axis and S =
+// sqrt(4 - 3 f^2), the characteristic polynomial factors as
+// (lambda - m)^2 (lambda^2 - B lambda + C), B = mu chi'(f), so that
+//   lambda = (B -+ sqrt(B^2 - 4C)) / 2,
+//   B^2 - 4C = 8 (S-1) [(S-1)(1+mu^2) + (1-mu^2)] / (3 S^2),
+//   S - 1 = 3 (1 - f^2) / (S + 1):
+// every factor is a sum of non-negative terms, so nothing cancels near free
+// streaming, where both speeds tend to mu.  1 - f^2 is formed in FP64 from
+// the FP32 state; 1 - mu^2 from the other two flux components.  Empty cells
+// take the isotropic speeds -+1/sqrt(3).
+struct Speeds {
+    float xm, xp, ym, yp, zm, zp;
+};
+
+__device__ __forceinline__ Speeds m1_speeds(float N, float Fx, float Fy, float Fz, float inv_c,
+                                            double c_d)
+{
+    const float ISO = 0.5773502691896258f;
+    Speeds s{-ISO, ISO, -ISO, ISO, -ISO, ISO};
+    if (!(N > N_TINY)) return s;
+    const float q = inv_c * frcp(N);
+    const float ux = Fx * q, uy = Fy * q, uz = Fz * q;
+    const float x2 = ux * ux, y2 = uy * uy, z2 = uz * uz;
+    const float f2 = x2 + y2 + z2;
+    if (!(f2 > 1e-20f)) return s;
+    const double cn = double(N) * c_d;
+    const double g2d =
+        1.0 - (double(Fx) * double(Fx) + double(Fy) * double(Fy) + double(Fz) * double(Fz)) /
+                  (cn * cn);
+    const float g2 = float(g2d > 0.0 ? g2d : 0.0);    // 1 - f^2
+    const float fs = 1.0f - g2;
+    const float S = fsqrt(1.0f + 3.0f * g2);
+    const float Sm1 = 3.0f * g2 * frcp(S + 1.0f);
+    const float D = 5.0f + 2.0f * S;
+    const float Q = (8.0f * D + 6.0f * (3.0f + 4.0f * fs) * frcp(S)) * frcp(D * D);  // chi'/f
+    const float pref = 8.0f * Sm1 * frcp(3.0f * S * S);
+    const float inv_f2 = frcp(f2);
+    auto axis = [&](float ud, float a2, float o2, float &lm, float &lp) {
+        const float r = fsqrt(pref * (Sm1 * (1.0f + a2 * inv_f2) + o2 * inv_f2));
+        const float B = ud * Q;
+        lm = 0.5f * (B - r);
+        lp = 0.5f * (B + r);
+    };
+    axis(ux, x2, y2 + z2, s.xm, s.xp);
+    axis(uy, y2, x2 + z2, s.ym, s.yp);
+    axis(uz, z2, x2 + y2, s.zm, s.zp);
+    return s;
+}
+
+// HLL face flux of one component with speeds (units of c) lm*, lp* on the
+// two sides: a+ = c max(0, lpL, lpR), a- = c min(0, lmL, lmR),
+// G = (a+ GL - a- GR + a+ a- (UR - UL)) / (a+ - a-).
+struct HllW {
+    float wl, wr, wd;   // G = wl GL + wr GR + wd (UR - UL)
+};
+
+__device__ __forceinline__ HllW hll_weights(float lmL, float lpL, float lmR, float lpR, float c)
+{
+    const float ap = c * rmax(0.0f, rmax(lpL, lpR));
+    const float am = c * rmin(0.0f, rmin(lmL, lmR));
+    const float den = ap - am;
+    if (!(den > 0.0f)) return HllW{0.5f, 0.5f, 0.0f};
+    const float w = frcp(den);
+    return HllW{ap * w, -am * w, ap * am * w};
+}
+
 // ------------------------------------------------------- hydrogen rates
 // alpha_B and case-B recombination cooling: Hui & Gnedin (1997);
 // collisional ionisation, its cooling (13.6 eV each), collisional excitation

@@ -63,12 +63,14 @@ struct StepArgs {
     int ntx, nty, nzc, zc, nblocks;
     int bc[6];
     int chem, mixed, adaptive, nsub, any_outflow;
+    int hll;                         // 1: HLL fluxes, 0: LF
     ClumpLaw cl;
     // FP32 constants
     float c, inv_c, half_c, half_c2, k1, dt, csig, T_h, inv15kB, T_floor,
         sub_eps, xhi_thr;
     // FP64 constants for the FP64 chemistry path and the tallies
     double dt_d, csig_d, T_h_d, T_floor_d, sub_eps_d, vol, esc_scale;
+    double c_d;                      // c in FP64 (HLL reduced flux 1 - f^2)
     // learned chemistry (surrogate form): packed bf16 forward operands,
     // biases b1|b2|b3|b4 (194 floats), and mu_in[5] sd_in[5] mu_out[2]
     // sd_out[2] in_min[5] in_max[5]

@@ -106,7 +106,7 @@ __device__ __forceinline__ Cell4 load4(const StepArgs &A, uint32_t i, float sx, 
 #define RT_M1_MINW 2
 #endif
 
-template <bool MIXED, bool SURR>
+template <bool MIXED, bool SURR, bool HLL>
 __global__ __launch_bounds__(NTHREADS, SURR ? 2 : RT_M1_MINW) void m1_step_kernel(StepArgs A)
 {
     constexpr int SW = TX + 2;
@@ -115,6 +115,9 @@ __global__ __launch_bounds__(NTHREADS, SURR ? 2 : RT_M1_MINW) void m1_step_kerne
     __shared__ float sN[TY + 2][SW], sFx[TY + 2][SW], sFy[TY + 2][SW], sFz[TY + 2][SW];
     __shared__ float sPxx[TY + 2][SW], sPyy[TY + 2][SW], sPxy[TY + 2][SW];
     __shared__ float sPxz[TY + 2][SW], sPyz[TY + 2][SW];
+    // HLL: x and y signal speeds of the tile and its halo
+    constexpr int HY = HLL ? TY + 2 : 1, HX = HLL ? SW : 1;
+    __shared__ float sLxm[HY][HX], sLxp[HY][HX], sLym[HY][HX], sLyp[HY][HX];
     __shared__ double sred[NTHREADS / 64][NRED];
 
     const int tid = threadIdx.x;
@@ -211,6 +214,12 @@ __global__ __launch_bounds__(NTHREADS, SURR ? 2 : RT_M1_MINW) void m1_step_kerne
     Press pprv = closure(prv.N, prv.Fx, prv.Fy, prv.Fz, A.inv_c);
     Cell4 cur = load4(A, col + uint32_t(z0) * plane, mx.sign, my.sign, 1.0f);
     Press pcur = closure(cur.N, cur.Fx, cur.Fy, cur.Fz, A.inv_c);
+    // HLL signal speeds travel with the z window like the pressure tensors
+    Speeds lprv{}, lcur{};
+    if constexpr (HLL) {
+        lprv = m1_speeds(prv.N, prv.Fx, prv.Fy, prv.Fz, A.inv_c, A.c_d);
+        lcur = m1_speeds(cur.N, cur.Fx, cur.Fy, cur.Fz, A.inv_c, A.c_d);
+    }
     // Prefetched planes live in two register sets that swap roles every
     // plane: the loop below is unrolled by two so that a value loaded for
     // the next plane is never copied, and its load stays in flight across
@@ -270,6 +279,12 @@ __global__ __launch_bounds__(NTHREADS, SURR ? 2 : RT_M1_MINW) void m1_step_kerne
             sPxy[sy][sx] = pcur.xy;
             sPxz[sy][sx] = pcur.xz;
             sPyz[sy][sx] = pcur.yz;
+            if constexpr (HLL) {
+                sLxm[sy][sx] = lcur.xm;
+                sLxp[sy][sx] = lcur.xp;
+                sLym[sy][sx] = lcur.ym;
+                sLyp[sy][sx] = lcur.yp;
+            }
         }
         if (has_halo) {
             const Press ph = closure(hal.N, hal.Fx, hal.Fy, hal.Fz, A.inv_c);
@@ -282,10 +297,19 @@ __global__ __launch_bounds__(NTHREADS, SURR ? 2 : RT_M1_MINW) void m1_step_kerne
             sPxy[hsy][hsx] = ph.xy;
             sPxz[hsy][hsx] = ph.xz;
             sPyz[hsy][hsx] = ph.yz;
+            if constexpr (HLL) {
+                const Speeds lh = m1_speeds(hal.N, hal.Fx, hal.Fy, hal.Fz, A.inv_c, A.c_d);
+                sLxm[hsy][hsx] = lh.xm;
+                sLxp[hsy][hsx] = lh.xp;
+                sLym[hsy][hsx] = lh.ym;
+                sLyp[hsy][hsx] = lh.yp;
+            }
         }
         __syncthreads();
 
         const Press pnxt = closure(nxt.N, nxt.Fx, nxt.Fy, nxt.Fz, A.inv_c);
+        Speeds lnxt{};
+        if constexpr (HLL) lnxt = m1_speeds(nxt.N, nxt.Fx, nxt.Fy, nxt.Fz, A.inv_c, A.c_d);
         const int sy = ly + 1, sx = lx + 1;
         // neighbours: x-1 (L), x+1 (R), y-1 (D), y+1 (U), z-1 (prv), z+1 (nxt)
         const float NL = sN[sy][sx - 1], NR = sN[sy][sx + 1];
@@ -302,20 +326,71 @@ __global__ __launch_bounds__(NTHREADS, SURR ? 2 : RT_M1_MINW) void m1_step_kerne
         const float PxyD = sPxy[sy - 1][sx], PxyU = sPxy[sy + 1][sx];
         const float PyyD = sPyy[sy - 1][sx], PyyU = sPyy[sy + 1][sx];
         const float PyzD = sPyz[sy - 1][sx], PyzU = sPyz[sy + 1][sx];
+        float lxmL = 0.f, lxpL = 0.f, lxmR = 0.f, lxpR = 0.f;
+        float lymD = 0.f, lypD = 0.f, lymU = 0.f, lypU = 0.f;
+        if constexpr (HLL) {
+            lxmL = sLxm[sy][sx - 1];
+            lxpL = sLxp[sy][sx - 1];
+            lxmR = sLxm[sy][sx + 1];
+            lxpR = sLxp[sy][sx + 1];
+            lymD = sLym[sy - 1][sx];
+            lypD = sLyp[sy - 1][sx];
+            lymU = sLym[sy + 1][sx];
+            lypU = sLyp[sy + 1][sx];
+        }
         __syncthreads();
 
-        // sum over d of the LF face-flux differences G_{d,+1/2} - G_{d,-1/2}:
-        //   N   : 1/2 (F_d[+] - F_d[-]) - c/2 (N[+] + N[-] - 2N)
-        //   F_k : c^2/2 (P_kd[+] - P_kd[-]) - c/2 (F_k[+] + F_k[-] - 2F_k)
-        const float hc = A.half_c, hc2 = A.half_c2;
-        const float dN = 0.5f * ((FxR - FxL) + (FyU - FyD) + (nxt.Fz - prv.Fz)) -
-                         hc * ((NL + NR) + (ND + NU) + (prv.N + nxt.N) - 6.0f * cur.N);
-        const float dFx = hc2 * ((PxxR - PxxL) + (PxyU - PxyD) + (pnxt.xz - pprv.xz)) -
-                          hc * ((FxL + FxR) + (FxD + FxU) + (prv.Fx + nxt.Fx) - 6.0f * cur.Fx);
-        const float dFy = hc2 * ((PxyR - PxyL) + (PyyU - PyyD) + (pnxt.yz - pprv.yz)) -
-                          hc * ((FyL + FyR) + (FyD + FyU) + (prv.Fy + nxt.Fy) - 6.0f * cur.Fy);
-        const float dFz = hc2 * ((PxzR - PxzL) + (PyzU - PyzD) + (pnxt.zz - pprv.zz)) -
-                          hc * ((FzL + FzR) + (FzD + FzU) + (prv.Fz + nxt.Fz) - 6.0f * cur.Fz);
+        float dN, dFx, dFy, dFz;
+        if constexpr (HLL) {
+            // HLL face fluxes G = wl G(UL) + wr G(UR) + wd (UR - UL), the
+            // weights from the signal speeds of the two cells of each face;
+            // physical fluxes along d: N -> F_d, F_k -> c^2 P_kd
+            const float c = A.c, C2 = 2.0f * A.half_c2;
+            const HllW wxm = hll_weights(lxmL, lxpL, lcur.xm, lcur.xp, c);
+            const HllW wxp = hll_weights(lcur.xm, lcur.xp, lxmR, lxpR, c);
+            const HllW wym = hll_weights(lymD, lypD, lcur.ym, lcur.yp, c);
+            const HllW wyp = hll_weights(lcur.ym, lcur.yp, lymU, lypU, c);
+            const HllW wzm = hll_weights(lprv.zm, lprv.zp, lcur.zm, lcur.zp, c);
+            const HllW wzp = hll_weights(lcur.zm, lcur.zp, lnxt.zm, lnxt.zp, c);
+            auto face = [](const HllW &w, float gL, float gR, float uL, float uR) {
+                return w.wl * gL + w.wr * gR + w.wd * (uR - uL);
+            };
+            dN = (face(wxp, cur.Fx, FxR, cur.N, NR) - face(wxm, FxL, cur.Fx, NL, cur.N)) +
+                 (face(wyp, cur.Fy, FyU, cur.N, NU) - face(wym, FyD, cur.Fy, ND, cur.N)) +
+                 (face(wzp, cur.Fz, nxt.Fz, cur.N, nxt.N) -
+                  face(wzm, prv.Fz, cur.Fz, prv.N, cur.N));
+            dFx = (face(wxp, C2 * pcur.xx, C2 * PxxR, cur.Fx, FxR) -
+                   face(wxm, C2 * PxxL, C2 * pcur.xx, FxL, cur.Fx)) +
+                  (face(wyp, C2 * pcur.xy, C2 * PxyU, cur.Fx, FxU) -
+                   face(wym, C2 * PxyD, C2 * pcur.xy, FxD, cur.Fx)) +
+                  (face(wzp, C2 * pcur.xz, C2 * pnxt.xz, cur.Fx, nxt.Fx) -
+                   face(wzm, C2 * pprv.xz, C2 * pcur.xz, prv.Fx, cur.Fx));
+            dFy = (face(wxp, C2 * pcur.xy, C2 * PxyR, cur.Fy, FyR) -
+                   face(wxm, C2 * PxyL, C2 * pcur.xy, FyL, cur.Fy)) +
+                  (face(wyp, C2 * pcur.yy, C2 * PyyU, cur.Fy, FyU) -
+                   face(wym, C2 * PyyD, C2 * pcur.yy, FyD, cur.Fy)) +
+                  (face(wzp, C2 * pcur.yz, C2 * pnxt.yz, cur.Fy, nxt.Fy) -
+                   face(wzm, C2 * pprv.yz, C2 * pcur.yz, prv.Fy, cur.Fy));
+            dFz = (face(wxp, C2 * pcur.xz, C2 * PxzR, cur.Fz, FzR) -
+                   face(wxm, C2 * PxzL, C2 * pcur.xz, FzL, cur.Fz)) +
+                  (face(wyp, C2 * pcur.yz, C2 * PyzU, cur.Fz, FzU) -
+                   face(wym, C2 * PyzD, C2 * pcur.yz, FzD, cur.Fz)) +
+                  (face(wzp, C2 * pcur.zz, C2 * pnxt.zz, cur.Fz, nxt.Fz) -
+                   face(wzm, C2 * pprv.zz, C2 * pcur.zz, prv.Fz, cur.Fz));
+        } else {
+            // sum over d of the LF face-flux differences G_{d,+1/2} - G_{d,-1/2}:
+            //   N   : 1/2 (F_d[+] - F_d[-]) - c/2 (N[+] + N[-] - 2N)
+            //   F_k : c^2/2 (P_kd[+] - P_kd[-]) - c/2 (F_k[+] + F_k[-] - 2F_k)
+            const float hc = A.half_c, hc2 = A.half_c2;
+            dN = 0.5f * ((FxR - FxL) + (FyU - FyD) + (nxt.Fz - prv.Fz)) -
+                 hc * ((NL + NR) + (ND + NU) + (prv.N + nxt.N) - 6.0f * cur.N);
+            dFx = hc2 * ((PxxR - PxxL) + (PxyU - PxyD) + (pnxt.xz - pprv.xz)) -
+                  hc * ((FxL + FxR) + (FxD + FxU) + (prv.Fx + nxt.Fx) - 6.0f * cur.Fx);
+            dFy = hc2 * ((PxyR - PxyL) + (PyyU - PyyD) + (pnxt.yz - pprv.yz)) -
+                  hc * ((FyL + FyR) + (FyD + FyU) + (prv.Fy + nxt.Fy) - 6.0f * cur.Fy);
+            dFz = hc2 * ((PxzR - PxzL) + (PyzU - PyzD) + (pnxt.zz - pprv.zz)) -
+                  hc * ((FzL + FzR) + (FzD + FzU) + (prv.Fz + nxt.Fz) - 6.0f * cur.Fz);
+        }
 
         // point sources of this plane (uniform walk over the sorted list)
         float S = 0.0f;
@@ -548,6 +623,10 @@ __global__ __launch_bounds__(NTHREADS, SURR ? 2 : RT_M1_MINW) void m1_step_kerne
         pprv = pcur;
         cur = nxt;
         pcur = pnxt;
+        if constexpr (HLL) {
+            lprv = lcur;
+            lcur = lnxt;
+        }
     };
 
     if constexpr (SURR) {
@@ -706,16 +785,22 @@ int state_sums_blocks(uint32_t ncell)
 hipError_t launch_step(const StepArgs &a, hipStream_t s)
 {
     const dim3 g(a.nblocks), b(NTHREADS);
+    // the learned chemistry runs with the LF flux only (rejected on the host)
     if (a.surr) {
         if (a.mixed)
-            hipLaunchKernelGGL((m1_step_kernel<true, true>), g, b, 0, s, a);
+            hipLaunchKernelGGL((m1_step_kernel<true, true, false>), g, b, 0, s, a);
         else
-            hipLaunchKernelGGL((m1_step_kernel<false, true>), g, b, 0, s, a);
+            hipLaunchKernelGGL((m1_step_kernel<false, true, false>), g, b, 0, s, a);
+    } else if (a.hll) {
+        if (a.mixed)
+            hipLaunchKernelGGL((m1_step_kernel<true, false, true>), g, b, 0, s, a);
+        else
+            hipLaunchKernelGGL((m1_step_kernel<false, false, true>), g, b, 0, s, a);
     } else {
         if (a.mixed)
-            hipLaunchKernelGGL((m1_step_kernel<true, false>), g, b, 0, s, a);
+            hipLaunchKernelGGL((m1_step_kernel<true, false, false>), g, b, 0, s, a);
         else
-            hipLaunchKernelGGL((m1_step_kernel<false, false>), g, b, 0, s, a);
+            hipLaunchKernelGGL((m1_step_kernel<false, false, false>), g, b, 0, s, a);
     }
     return hipGetLastError();
 }

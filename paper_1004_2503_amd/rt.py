@@ -24,6 +24,7 @@ BC_PERIODIC, BC_OUTFLOW, BC_REFLECT = 0, 1, 2
 CHEM_FULL, CHEM_ISOTHERMAL, CHEM_OFF, CHEM_FROZEN = 0, 1, 2, 3
 PREC_FP32, PREC_MIXED = 0, 1
 SUB_FIXED, SUB_ADAPTIVE = 0, 1
+FLUX_LF, FLUX_HLL = 0, 1
 FIELD_N, FIELD_FX, FIELD_FY, FIELD_FZ, FIELD_XHI, FIELD_T, FIELD_NH = range(7)
 
 SIGMA_N = 2.93e-18
@@ -43,7 +44,7 @@ class rt_params(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
                 ("bc", ctypes.c_int32 * 6), ("chem", ctypes.c_int32),
                 ("prec", ctypes.c_int32), ("sub", ctypes.c_int32),
-                ("clump", ctypes.c_int32),
+                ("clump", ctypes.c_int32), ("flux", ctypes.c_int32),
                 ("dx_cm", ctypes.c_double), ("c_cms", ctypes.c_double),
                 ("sigma_n", ctypes.c_double), ("sigma_e", ctypes.c_double),
                 ("egamma_eV", ctypes.c_double), ("T_floor", ctypes.c_double),
@@ -195,14 +196,15 @@ def check(rc: int, what: str):
 
 def make_params(shape, dx, bc=(BC_PERIODIC,) * 6, chem=CHEM_FULL, prec=PREC_FP32,
                 sub=SUB_FIXED, c=C_LIGHT, T_floor=10.0, sub_eps=0.1,
-                xhi_fp64_thr=1e-3, clump=None) -> rt_params:
+                xhi_fp64_thr=1e-3, clump=None, flux=FLUX_LF) -> rt_params:
     """``shape`` is (nz, ny, nx), the torch/numpy order of every field.
     ``clump`` is None (no subgrid clumping) or (cr_norm, cr_exp, ci_norm,
-    ci_exp): C_R = max(1, cr_norm nH^cr_exp), C_I = ci_norm nH^ci_exp."""
+    ci_exp): C_R = max(1, cr_norm nH^cr_exp), C_I = ci_norm nH^ci_exp.
+    ``flux`` is FLUX_LF (the paper's Lax-Friedrichs) or FLUX_HLL."""
     nz, ny, nx = shape
     cl = (1.0, 0.0, 1.0, 0.0) if clump is None else tuple(float(v) for v in clump)
     return rt_params(nx, ny, nz, (ctypes.c_int32 * 6)(*bc), chem, prec, sub,
-                     0 if clump is None else 1,
+                     0 if clump is None else 1, int(flux),
                      float(dx), float(c), SIGMA_N, SIGMA_E, EGAMMA_EV, float(T_floor),
                      float(sub_eps), float(xhi_fp64_thr), *cl)
 

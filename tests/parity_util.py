@@ -21,14 +21,15 @@ FIELDS = ("N", "Fx", "Fy", "Fz", "xHI", "T")
 
 
 def gpu_params(shape, dx, bc, chem, prec=rt.PREC_FP32, sub=rt.SUB_FIXED, sub_eps=0.1,
-               clump=None):
+               clump=None, flux=rt.FLUX_LF):
     return rt.make_params(shape, dx, bc=bc, chem=chem, prec=prec, sub=sub, sub_eps=sub_eps,
-                          clump=clump)
+                          clump=clump, flux=flux)
 
 
 def oracle_grid(state, shape, dx, bc, chem, sub=oracle.SUB_FIXED, sub_eps=0.1, sources=None,
-                clump=None):
-    p = oracle.make_params(shape, dx, bc=bc, chem=chem, sub=sub, sub_eps=sub_eps, clump=clump)
+                clump=None, flux=oracle.FLUX_LF):
+    p = oracle.make_params(shape, dx, bc=bc, chem=chem, sub=sub, sub_eps=sub_eps, clump=clump,
+                           flux=flux)
     g = oracle.Grid(p)
     g.set_state(**{k: np.asarray(state[k], dtype=np.float64) for k in
                    ("N", "Fx", "Fy", "Fz", "xHI", "T", "nH") if k in state})
@@ -58,17 +59,18 @@ def oracle_state(g) -> dict:
 
 
 def one_step_pair(state, shape, dx, dt, nsub, bc, chem, prec=rt.PREC_FP32,
-                  sub=rt.SUB_FIXED, sub_eps=0.1, sources=None, clump=None):
+                  sub=rt.SUB_FIXED, sub_eps=0.1, sources=None, clump=None, flux=rt.FLUX_LF):
     """Step the library and the oracle once from the same state (``clump``:
-    None or the (cr_norm, cr_exp, ci_norm, ci_exp) laws on both sides).
+    None or the (cr_norm, cr_exp, ci_norm, ci_exp) laws on both sides; ``flux``
+    the intercell flux, LF or HLL, the same code on both sides).
     Returns (gpu numpy state, oracle numpy state, gpu reductions, oracle grid)."""
-    G = rt.RTGrid(gpu_params(shape, dx, bc, chem, prec, sub, sub_eps, clump), state)
+    G = rt.RTGrid(gpu_params(shape, dx, bc, chem, prec, sub, sub_eps, clump, flux), state)
     if sources is not None:
         G.inject_sources(*sources)
     G.step(dt, nsub)
     red = G.reduce(allow_nonfinite=True)
     out = G.state_numpy()
     G.close()
-    g = oracle_grid(state, shape, dx, bc, chem, sub, sub_eps, sources, clump)
+    g = oracle_grid(state, shape, dx, bc, chem, sub, sub_eps, sources, clump, flux)
     g.step(dt, nsub)
     return out, oracle_state(g), red, g

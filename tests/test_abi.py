@@ -107,7 +107,7 @@ def _params(**kw):
     dict(nx=0), dict(ny=-3), dict(nz=0), dict(nx=2048, ny=2048, nz=2048),
     dict(bc=(0, 1, 0, 0, 0, 0)),          # periodic on one face only
     dict(bc=(5, 5, 0, 0, 0, 0)),
-    dict(chem=7), dict(prec=2), dict(sub=3), dict(clump=2),
+    dict(chem=7), dict(prec=2), dict(sub=3), dict(clump=2), dict(flux=2), dict(flux=-1),
     dict(clump=1, clump_cr_norm=0.0), dict(clump=1, clump_ci_norm=-1.0),
     dict(clump=1, clump_cr_exp=float("inf")), dict(clump=1, clump_ci_exp=11.0),
     dict(dx_cm=0.0), dict(dx_cm=float("nan")), dict(c_cms=-1.0),

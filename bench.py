@@ -48,10 +48,11 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload: str, nsub: int, prec: str):
+def measured_traffic(workload: str, nsub: int, prec: str, flux: str = "lf"):
     """HBM bytes per launch of the step kernel from the committed rocprofv3
     counter summary, if it was taken on the current kernel source."""
-    path = os.path.join(ROOT, "profiles", f"m1_step_{workload}_traffic.json")
+    name = f"m1_step_{workload}" if flux == "lf" else f"m1_step_{flux}_{workload}"
+    path = os.path.join(ROOT, "profiles", f"{name}_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
@@ -244,7 +245,7 @@ def diagnostics_leg(G, w, reps: int = 5):
     return out
 
 
-def hll_leg(G, w, dt, params, src, nsub: int, steps: int = 20):
+def hll_leg(G, w, dt, params, src, nsub: int, prec: str, steps: int = 20):
     """Time the step with HLL intercell fluxes (Sec. 2.2) on a copy of the
     run's current state: same fields read and written (52 bytes per cell),
     the six signal speeds of every cell computed in the kernel.  Kernel time
@@ -274,6 +275,7 @@ def hll_leg(G, w, dt, params, src, nsub: int, steps: int = 20):
     gbs = BYTES_PER_CELL * w.cells / (avg * 1e-3) / 1e9
     return {"steps": steps, "ms_per_step": wall / steps * 1e3, "avg_launch_ms": avg,
             "achieved_GBs": gbs, "frac": gbs / HBM_PEAK_GBS,
+            "traffic": measured_traffic(w.name, nsub, prec, "hll"),
             "n_nonfinite": red["n_nonfinite"]}
 
 
@@ -396,7 +398,7 @@ def main():
     value = cells * args.steps / wall
     avg_ms = ms_kernel / max(launches, 1)
     achieved = BYTES_PER_CELL * cells / (avg_ms * 1e-3) / 1e9
-    traffic = measured_traffic(w.name, args.nsub, args.prec)
+    traffic = measured_traffic(w.name, args.nsub, args.prec, args.flux)
     roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
             "kernel": "m1_step_kernel", "avg_launch_ms": avg_ms,
@@ -405,7 +407,7 @@ def main():
     diag = diagnostics_leg(G, w)
     hll = None
     if flux == rt.FLUX_LF and not args.no_hll:
-        hll = hll_leg(G, w, dt, params, (ijk, ndot), args.nsub)
+        hll = hll_leg(G, w, dt, params, (ijk, ndot), args.nsub, args.prec)
 
     surr = None
     if args.surrogate:

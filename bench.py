@@ -231,17 +231,28 @@ def diagnostics_leg(G, w, reps: int = 5):
     from paper_1004_2503_amd import rt
 
     out = {}
+    xr = (-6.0, 1.0, 64)
     for name, q, yr in (("xHI", rt.HQ_XHI, (-7.0, 0.5, 64)),
                         ("gamma", rt.HQ_GAMMA, (-18.0, -8.0, 64))):
-        G.histogram(q, (-6.0, 1.0, 64), yr)
+        G.histogram(q, xr, yr)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(reps):
-            counts, _ = G.histogram(q, (-6.0, 1.0, 64), yr)
+            counts, sums = G.histogram(q, xr, yr)
         dt = (time.perf_counter() - t0) / reps
         out[name] = {"ms": dt * 1e3, "GBs": 8.0 * w.cells / dt / 1e9,
                      "nonzero_bins": int(np.count_nonzero(counts))}
     out["tau_e"] = G.reduce()["tau_e"]
+    # Sec. 3.1.5 analysis: plateau rate below 1e-3 cm^-3, then the equilibrium
+    # neutral fraction under the plateau, J1 and J4 models at a few densities
+    g0 = rt.gamma_plateau(counts, sums, xr, 1e-3)
+    dens = torch.tensor([1e-4, 1e-3, 1e-2, 1e-1], dtype=torch.float64, device=G.device)
+    temp = torch.full_like(dens, 1e4)
+    eq = {"gamma0": g0, "nH": dens.tolist()}
+    for name, model, ns in (("J0", rt.JMODEL_UNIFORM, 0.0), ("J1", rt.JMODEL_EXP1, 0.007),
+                            ("J4", rt.JMODEL_EXP4, 0.018)):
+        eq[name] = rt.equilibrium_xhi(G.params, model, g0, ns, dens, temp).tolist()
+    out["equilibrium_xhi"] = eq
     return out
 
 

@@ -255,6 +255,31 @@ int rt_reduce(rt_ctx *ctx, rt_reductions *out);
 int rt_histogram(rt_ctx *ctx, int32_t quantity, int32_t nbx, double lox, double hix,
                  int32_t nby, double loy, double hiy, int64_t *counts, double *sum_q);
 
+/* Self-shielding models of the photoionisation rate against density
+ * (Sec. 3.1.5 fits the intensity of its runs by a plateau J0 with an
+ * exponential cutoff; with the gray constants the rate is proportional to the
+ * intensity, so the models apply to Gamma). */
+#define RT_JMODEL_UNIFORM 0 /* Gamma(nH) = gamma0                    (J0) */
+#define RT_JMODEL_EXP1 1    /* Gamma(nH) = gamma0 exp(-nH / n_star)  (J1) */
+#define RT_JMODEL_EXP4 2    /* Gamma(nH) = gamma0 exp(-(nH/n_star)^4) (J4) */
+
+/* Equilibrium neutral fraction under a model (Sec. 3.1.5 compares the mean
+ * neutral fraction per density bin with it; clumped as in Sec. 3.2.1): per
+ * element, Gamma = model(nH[i]) and xhi[i] = the root y in [0, 1] of
+ *   C_R alpha_B(T) nH (1 - y)^2 = C_I Gamma y + beta(T) nH (1 - y) y,
+ * the fixed point of the chemistry operator at fixed T[i] and Gamma (case-B
+ * recombination against photo- and collisional ionisation; the same rate
+ * fits as rt_step).  nH, T, xhi: device arrays of n FP64 values,
+ * caller-owned; an element with nH <= 0 or non-finite, or T outside
+ * [1, 1e9] K, gives NaN.  params: host; only the clumping fields are read
+ * (C_R = C_I = 1 when clump = 0), validated as by rt_init.  gamma0 >= 0 and
+ * finite; n_star > 0 and finite unless model = RT_JMODEL_UNIFORM;
+ * 0 <= n < 2^31 (RT_E_ARG otherwise).  Asynchronous on hip_stream (NULL:
+ * the null stream). */
+int rt_equilibrium_xhi(const rt_params *params, int32_t model, double gamma0, double n_star,
+                       int64_t n, const double *nH, const double *T, double *xhi,
+                       void *hip_stream);
+
 /* Copy field `field` (RT_FIELD_*) of the current state into dst (nx*ny*nz
  * floats; device memory if dst_on_device != 0, else host memory) and wait
  * for the copy. */

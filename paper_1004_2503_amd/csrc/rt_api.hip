@@ -569,6 +569,22 @@ extern "C" int rt_reduce(rt_ctx *c, rt_reductions *out)
     return out->n_nonfinite > 0 ? RT_E_NONFINITE : RT_OK;
 }
 
+extern "C" int rt_equilibrium_xhi(const rt_params *p, int32_t model, double gamma0,
+                                  double n_star, int64_t n, const double *nH, const double *T,
+                                  double *xhi, void *hip_stream)
+{
+    if (!p || check_clump(*p) != RT_OK) return RT_E_ARG;
+    if (model < RT_JMODEL_UNIFORM || model > RT_JMODEL_EXP4) return RT_E_ARG;
+    if (!(gamma0 >= 0.0) || !isfinite(gamma0)) return RT_E_ARG;
+    if (model != RT_JMODEL_UNIFORM && (!(n_star > 0.0) || !isfinite(n_star))) return RT_E_ARG;
+    if (n < 0 || n > (int64_t(1) << 31) - 1) return RT_E_ARG;
+    if (n == 0) return RT_OK;
+    if (!nH || !T || !xhi) return RT_E_ARG;
+    const hipError_t e = launch_equilibrium(n, nH, T, xhi, model, gamma0, n_star, *p,
+                                            static_cast<hipStream_t>(hip_stream));
+    return e == hipSuccess ? RT_OK : RT_E_HIP;
+}
+
 extern "C" int rt_histogram(rt_ctx *c, int32_t quantity, int32_t nbx, double lox, double hix,
                             int32_t nby, double loy, double hiy, int64_t *counts,
                             double *sum_q)

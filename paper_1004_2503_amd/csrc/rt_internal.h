@@ -102,6 +102,9 @@ hipError_t launch_hist(const float *nH, const float *q, int gamma, double csig, 
                        int nbx, int nby, const double *edges, float lox, float inv_wx,
                        float loy, float inv_wy, unsigned long long *counts, double *sums,
                        hipStream_t s);
+hipError_t launch_equilibrium(int64_t n, const double *nH, const double *T, double *xhi,
+                              int model, double gamma0, double n_star, const rt_params &p,
+                              hipStream_t s);
 hipError_t launch_state_sums(const float *N, const float *xHI, const float *nH,
                              uint32_t ncell, double *partials, int nblocks,
                              hipStream_t s);

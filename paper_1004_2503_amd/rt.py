@@ -428,3 +428,48 @@ def rt_set_surrogate(ctx, theta, norm, residual_tol: float) -> int:
     return L.rt_set_surrogate(ctx, ctypes.c_void_p(theta.data_ptr()),
                               nv.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
                               float(residual_tol))
+
+
+EXPORTS += ["rt_equilibrium_xhi"]
+JMODEL_UNIFORM, JMODEL_EXP1, JMODEL_EXP4 = 0, 1, 2
+
+
+def rt_equilibrium_xhi(params: rt_params, model: int, gamma0: float, n_star: float, nH, T, xhi,
+                       stream: int | None = None) -> int:
+    """Equilibrium neutral fraction under a self-shielding model (torch
+    float64 device tensors of one size); asynchronous on ``stream``."""
+    L = lib()
+    vp = ctypes.c_void_p
+    L.rt_equilibrium_xhi.argtypes = [ctypes.POINTER(rt_params), ctypes.c_int32, ctypes.c_double,
+                                     ctypes.c_double, ctypes.c_int64, vp, vp, vp, vp]
+    L.rt_equilibrium_xhi.restype = ctypes.c_int
+    n = int(nH.numel())
+    if T.numel() != n or xhi.numel() != n:
+        return RT_E_ARG
+    return L.rt_equilibrium_xhi(ctypes.byref(params), int(model), float(gamma0), float(n_star),
+                                n, _p(nH), _p(T), _p(xhi), vp(stream or 0))
+
+
+def equilibrium_xhi(params: rt_params, model: int, gamma0: float, n_star: float, nH, T):
+    """New float64 tensor of equilibrium neutral fractions (see
+    rt_equilibrium_xhi); nH and T are float64 device tensors."""
+    import torch
+
+    out = torch.empty_like(nH)
+    check(rt_equilibrium_xhi(params, model, gamma0, n_star, nH, T, out,
+                             torch.cuda.current_stream(nH.device).cuda_stream),
+          "rt_equilibrium_xhi")
+    return out
+
+
+def gamma_plateau(counts, sums, xrange, nH_max: float) -> float:
+    """The plateau rate J0 (as Gamma) from an RT_HQ_GAMMA histogram: the mean
+    rate over the density bins whose upper edge is at most nH_max."""
+    lo, hi, nb = xrange
+    w = (hi - lo) / nb
+    upper = np.array([10.0 ** (lo + (k + 1) * w) for k in range(nb)])
+    sel = upper <= nH_max
+    n = int(np.asarray(counts)[sel].sum())
+    if n == 0:
+        raise ValueError("no cells below nH_max")
+    return float(np.asarray(sums)[sel].sum() / n)

@@ -149,3 +149,34 @@ def test_chem_apply_rejects_invalid_params_on_host(kw):
     p = _params(**kw)
     rc = L.rt_chem_apply(ctypes.byref(p), 16, None, None, None, None, None, 1, None, None)
     assert rc == rt.RT_E_ARG
+
+
+@pytest.mark.parametrize("model,g0,ns,n,kw", [
+    (3, 1e-12, 0.01, 8, {}), (-1, 1e-12, 0.01, 8, {}),
+    (rt.JMODEL_UNIFORM, -1e-12, 0.01, 8, {}), (rt.JMODEL_EXP1, float("nan"), 0.01, 8, {}),
+    (rt.JMODEL_EXP1, 1e-12, 0.0, 8, {}), (rt.JMODEL_EXP4, 1e-12, float("inf"), 8, {}),
+    (rt.JMODEL_UNIFORM, 1e-12, 0.0, -1, {}), (rt.JMODEL_UNIFORM, 1e-12, 0.0, 1 << 31, {}),
+    (rt.JMODEL_UNIFORM, 1e-12, 0.0, 8, {}),                      # null arrays with n > 0
+    (rt.JMODEL_EXP4, 1e-12, 0.02, 8, dict(clump=1, clump_ci_norm=0.0)),
+])
+def test_equilibrium_rejects_invalid_arguments_on_host(model, g0, ns, n, kw):
+    L = rt.lib()
+    L.rt_equilibrium_xhi.argtypes = [ctypes.POINTER(rt.rt_params), ctypes.c_int32,
+                                     ctypes.c_double, ctypes.c_double, ctypes.c_int64,
+                                     ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                     ctypes.c_void_p]
+    p = _params(**kw)
+    rc = L.rt_equilibrium_xhi(ctypes.byref(p), model, g0, ns, n, None, None, None, None)
+    assert rc == rt.RT_E_ARG
+
+
+def test_equilibrium_empty_batch_is_a_no_op():
+    # n = 0 returns before any HIP call; the plateau model needs no n_star
+    p = _params()
+    L = rt.lib()
+    L.rt_equilibrium_xhi.argtypes = [ctypes.POINTER(rt.rt_params), ctypes.c_int32,
+                                     ctypes.c_double, ctypes.c_double, ctypes.c_int64,
+                                     ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                     ctypes.c_void_p]
+    assert L.rt_equilibrium_xhi(ctypes.byref(p), rt.JMODEL_UNIFORM, 1e-12, 0.0, 0, None, None,
+                                None, None) == rt.RT_OK

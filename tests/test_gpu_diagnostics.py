@@ -7,7 +7,13 @@ oracle (Sec. 3.1.5 distributions over density, Sec. 3.1.4 Thomson depth):
     a single bin; values exactly on edges and out of range land where the
     definition puts them; per-density-bin sums agree to 1e-12;
   * tau_e: closed form for a frozen uniform state (c sigma_T <n_e> t), and
-    the oracle's step-by-step sum on a Stromgren run."""
+    the oracle's step-by-step sum on a Stromgren run;
+  * rt_equilibrium_xhi under the plateau, J1 and J4 models, with and
+    without clumping, element by element against the oracle (the neutral
+    and the ionised fraction to 2e-5: the kernel takes the FP32 rate fits of
+    the step), invalid elements NaN, no radiation in cold gas exactly 1; and
+    the analysis of Sec. 3.1.5 on an evolved state: plateau rate from the
+    rate histogram, then the equilibrium curves at the bin centres."""
 
 import numpy as np
 import pytest
@@ -121,3 +127,75 @@ def test_thomson_depth_matches_oracle_run():
     G.close()
     assert tau_o > 0
     assert red["tau_e"] == pytest.approx(tau_o, rel=5e-3)
+
+
+LAW_B = W.CLUMP_LAWS["B"]
+
+
+def _eq_gpu(params, model, g0, ns, nH, T):
+    d = dict(dtype=torch.float64, device="cuda")
+    out = rt.equilibrium_xhi(params, model, g0, ns, torch.tensor(nH, **d), torch.tensor(T, **d))
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+def _compare_eq(y, want):
+    assert np.all(np.abs(y - want) <= 2e-5 * want), np.max(np.abs(y - want) / want)
+    ion_w, ion = 1.0 - want, 1.0 - y
+    m = ion_w > 1e-9
+    tol = 2e-5 + 1e-15 / ion_w[m]
+    assert np.all(np.abs(ion[m] - ion_w[m]) <= tol * ion_w[m])
+
+
+@pytest.mark.parametrize("model,ns", [(rt.JMODEL_UNIFORM, 0.0), (rt.JMODEL_EXP1, 0.007),
+                                      (rt.JMODEL_EXP4, 0.018)])
+@pytest.mark.parametrize("clump", [None, LAW_B])
+def test_equilibrium_matches_oracle(model, ns, clump):
+    rng = np.random.default_rng(40 + model)
+    n = 3000
+    nH = 10 ** rng.uniform(-6, 0, n)
+    T = 10 ** rng.uniform(2, 5, n)
+    g0 = 1e-12
+    p = rt.make_params((1, 1, 1), 1e21, clump=clump)
+    y = _eq_gpu(p, model, g0, ns, nH, T)
+    op = oracle.make_params((1, 1, 1), 1e21, clump=clump) if clump is not None else None
+    want = D.xhi_equilibrium(nH, T, D.gamma_model(model, g0, ns, nH), op)
+    _compare_eq(y, want)
+    # the regimes are present: ionised, partly neutral and (under a cutoff
+    # or with clumping) shielded
+    assert (want < 1e-4).any() and ((want > 0.01) & (want < 0.5)).any()
+    if model != rt.JMODEL_UNIFORM or clump is not None:
+        assert (want > 0.9).any()
+
+
+def test_equilibrium_special_elements():
+    p = rt.make_params((1, 1, 1), 1e21)
+    nH = np.array([0.0, -1.0, np.inf, 1e-3, 1e-3, 1e-3, 1e-3, 1e-2])
+    T = np.array([1e4, 1e4, 1e4, 0.5, np.nan, 2e9, 100.0, 1e4])
+    y = _eq_gpu(p, rt.JMODEL_UNIFORM, 0.0, 0.0, nH, T)
+    assert np.all(np.isnan(y[:6]))
+    assert y[6] == 1.0                       # cold, dark: no ionisation at all
+    a, b = oracle.rates(1e4)[:2]
+    assert y[7] == pytest.approx(a / (a + b), rel=2e-5)   # coronal equilibrium
+
+
+def test_equilibrium_curves_of_an_evolved_state(evolved64):
+    G, st = evolved64
+    xr, yr = (-6.0, 0.0, 48), (-18.0, -8.0, 64)
+    counts, sums = G.histogram(rt.HQ_GAMMA, xr, yr)
+    edges = D.log_edges(*xr)
+    cut = edges[30]                                    # 10^-2.25 cm^-3
+    g0 = rt.gamma_plateau(counts.sum(axis=1), sums, xr, cut)
+    gam = D.photoionisation_rate(st["N"], C, rt.SIGMA_N)
+    want0 = D.gamma_plateau(st["nH"], gam, cut)
+    assert g0 == pytest.approx(want0, rel=1e-12)
+    assert g0 > 0.0
+    centres = np.sqrt(edges[:-1] * edges[1:])
+    T = np.full_like(centres, 1e4)
+    p = rt.make_params((1, 1, 1), 1e21)
+    for model, ns in ((rt.JMODEL_UNIFORM, 0.0), (rt.JMODEL_EXP1, 0.007),
+                      (rt.JMODEL_EXP4, 0.018)):
+        y = _eq_gpu(p, model, g0, ns, centres, T)
+        _compare_eq(y, D.xhi_equilibrium(centres, T, D.gamma_model(model, g0, ns, centres)))
+        # denser gas is more neutral (up to rounding once collisions alone set it)
+        assert np.all(np.diff(y) >= -4e-16)

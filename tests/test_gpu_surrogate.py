@@ -7,9 +7,12 @@
   * the fused step kernel's surrogate path agrees with the batch network on
     the same transported state, cells flagged for fallback equal the exact
     operator, and the photon budget still closes;
-  * what the network gains: one network evaluation replaces the exact
-    operator's sub-cycles; on stiff cells (many sub-cycles) the batch
-    surrogate is timed against the exact operator at equal accuracy target.
+  * what the network gains: judged by the exact adaptive operator (up to 64
+    sub-cycles) on held-out cells of the run, one network evaluation per cell
+    is far more accurate than the exact operator held to one sub-cycle per
+    cell, most of all on the stiff cells that need many sub-cycles; the batch
+    network and the batch adaptive operator are timed on those cells
+    (reported: the fused step's cost is set by HBM, not by either).
 """
 
 import numpy as np
@@ -154,3 +157,79 @@ def test_surrogate_off_again_restores_exact_path(run64, trained):
         G.close()
     for k in outs[0]:
         assert np.array_equal(outs[0][k], outs[1][k])
+
+
+def test_what_the_network_gains(run64, trained):
+    s, _, _ = trained
+    c = surrogate.sample_cells(run64["states"][-1], 200_000, 777)
+    n = c["N"].numel()
+    lit = c["N"] > 0
+    res = {}
+    for f in (1.0, 2.0):                     # the step of this grid and twice it
+        dtt = torch.full_like(c["N"], run64["dt"] * f)
+
+        def exact(params, nsub, ncyc=None):
+            N, x, T = c["N"].clone(), c["xHI"].clone(), c["T"].clone()
+            rt.check(rt.rt_chem_apply(params, c["nH"], N, x, T, dtt, nsub, ncyc),
+                     "rt_chem_apply")
+            torch.cuda.synchronize()
+            return x
+
+        ncyc = torch.zeros(n, dtype=torch.int32, device=DEV)
+        ref = exact(exact_params(), 64, ncyc)
+        one = exact(rt.make_params((1, 1, 1), 1.0, chem=rt.CHEM_FULL, prec=rt.PREC_MIXED), 1)
+        X = surrogate.features(torch, c["nH"], c["N"], c["xHI"], c["T"], dtt)
+        net = 10 ** surrogate.predict(s, X)[:, 0]
+        for name, sel in (("lit", lit), ("stiff", ncyc >= 8)):
+            e1 = float((one[sel] - ref[sel]).abs().mean())
+            en = float((net[sel] - ref[sel]).abs().mean())
+            res[(f, name)] = (int(sel.sum()), e1, en)
+            print(f"dt x{f:g}, {name} cells {int(sel.sum())}: mean |dxHI| against the adaptive "
+                  f"operator: one sub-cycle {e1:.3e}, network {en:.3e}", flush=True)
+        if f == 1.0:
+            # batch timings on the lit cells (the fused step hides both under HBM)
+            idx = torch.nonzero(lit).reshape(-1)
+            times = _time_batch(s, {k: v[idx].contiguous() for k, v in c.items()},
+                                dtt[idx].contiguous(), X[idx])
+            print(f"{idx.numel()} lit cells (mean {float(ncyc[idx].float().mean()):.2f} "
+                  f"sub-cycles): exact adaptive {times['exact']:.3f} ms, exact one sub-cycle "
+                  f"{times['one']:.3f} ms, network {times['network']:.3f} ms", flush=True)
+    # the network meets its target everywhere and beats one exact sub-cycle on
+    # the stiff cells; on ordinary cells one exact sub-cycle is already closer
+    for f in (1.0, 2.0):
+        assert res[(f, "lit")][2] <= 1e-4
+    stiff = [res[(f, "stiff")] for f in (1.0, 2.0)]
+    assert sum(k for k, _, _ in stiff) >= 40
+    assert sum(k * en for k, _, en in stiff) < sum(k * e1 for k, e1, _ in stiff)
+
+
+def _time_batch(s, cs, dts, X):
+    Xs = ((X - torch.tensor(s.mu_in, device=DEV)) /
+          torch.tensor(s.sd_in, device=DEV)).float().contiguous()
+    Y = torch.zeros((X.shape[0], 2), device=DEV)
+    rc, h = rt.rt_mlp_create(1, 0)
+    rt.check(rc, "rt_mlp_create")
+    one = rt.make_params((1, 1, 1), 1.0, chem=rt.CHEM_FULL, prec=rt.PREC_MIXED)
+    times = {}
+    try:
+        for name in ("exact", "one", "network"):
+            best = float("inf")
+            for _ in range(5):
+                N, x, T = cs["N"].clone(), cs["xHI"].clone(), cs["T"].clone()
+                torch.cuda.synchronize()
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record()
+                if name == "exact":
+                    rt.check(rt.rt_chem_apply(exact_params(), cs["nH"], N, x, T, dts, 64),
+                             "rt_chem_apply")
+                elif name == "one":
+                    rt.check(rt.rt_chem_apply(one, cs["nH"], N, x, T, dts, 1), "rt_chem_apply")
+                else:
+                    rt.check(rt.rt_mlp_forward(h, s.theta, Xs, Y), "rt_mlp_forward")
+                b.record()
+                torch.cuda.synchronize()
+                best = min(best, a.elapsed_time(b))
+            times[name] = best
+    finally:
+        rt.rt_mlp_destroy(h)
+    return times

@@ -8,7 +8,7 @@
 // One streaming pass over nH and the chosen quantity (8 bytes per cell).
 // Each block keeps a private histogram in LDS (integer atomics) and FP64
 // per-density-bin sums; blocks then add their non-zero bins to the global
-// result.  Bin decisions are exact: an FP32 logarithm proposes the bin and
+// result (up to 8192 blocks: the LDS atomics need many waves in flight).  Bin decisions are exact: an FP32 logarithm proposes the bin and
 // comparisons against the FP64 edges settle it.
 
 #include <hip/hip_runtime.h>
@@ -37,7 +37,7 @@ __global__ __launch_bounds__(256) void hist_kernel(const float *__restrict__ nH,
                                                    double csig, uint32_t ncell, int nbx,
                                                    int nby, const double *__restrict__ edges,
                                                    float lox, float inv_wx, float loy,
-                                                   float inv_wy,
+                                                   float inv_wy, int vec,
                                                    unsigned long long *__restrict__ counts,
                                                    double *__restrict__ sums)
 {
@@ -52,15 +52,57 @@ __global__ __launch_bounds__(256) void hist_kernel(const float *__restrict__ nH,
     __syncthreads();
     const double *ex = se, *ey = se + nbx + 1;
     const float L10 = 0.301029995664f;   // log10(2)
-    // 64-bit index: ncell may approach 2^32, where a 32-bit stride would wrap
-    const uint64_t stride = uint64_t(gridDim.x) * 256u;
-    for (uint64_t i = uint64_t(blockIdx.x) * 256u + threadIdx.x; i < ncell; i += stride) {
-        const float h = nH[i];
-        const float s = qsrc[i];
-        const double q = gamma ? csig * double(s) : double(s);
-        const int bx = find_bin(double(h), L10 * flog2(h), ex, nbx, lox, inv_wx);
+    auto bins = [&](float h, float v, int &b, int &bx, double &q) {
+        q = gamma ? csig * double(v) : double(v);
+        bx = find_bin(double(h), L10 * flog2(h), ex, nbx, lox, inv_wx);
         const int by = find_bin(q, L10 * flog2(float(q)), ey, nby, loy, inv_wy);
-        atomicAdd(&scnt[bx * nby + by], 1u);
+        b = bx * nby + by;
+    };
+    // Eight consecutive cells per thread and iteration, read as two 16-byte
+    // loads of each field (more loads in flight than one float per thread);
+    // neighbouring cells that share a bin are combined before the LDS
+    // atomics, which bound the kernel.  64-bit indices: ncell may approach
+    // 2^32.  The rest (and everything, for unaligned fields) goes cell by
+    // cell.
+    const uint64_t stride = uint64_t(gridDim.x) * 256u;
+    const uint64_t n8 = vec ? ncell / 8 : 0;
+    const float4 *h4 = reinterpret_cast<const float4 *>(nH);
+    const float4 *q4 = reinterpret_cast<const float4 *>(qsrc);
+    for (uint64_t i = uint64_t(blockIdx.x) * 256u + threadIdx.x; i < n8; i += stride) {
+        const float4 ha = h4[2 * i], hb = h4[2 * i + 1];
+        const float4 va = q4[2 * i], vb = q4[2 * i + 1];
+        const float hh[8] = {ha.x, ha.y, ha.z, ha.w, hb.x, hb.y, hb.z, hb.w};
+        const float vv[8] = {va.x, va.y, va.z, va.w, vb.x, vb.y, vb.z, vb.w};
+        int b[8], bx[8];
+        double q[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) bins(hh[k], vv[k], b[k], bx[k], q[k]);
+        unsigned run = 1;
+        double qs = q[0];
+#pragma unroll
+        for (int k = 1; k < 8; ++k) {
+            if (b[k] == b[k - 1]) {
+                ++run;
+            } else {
+                atomicAdd(&scnt[b[k - 1]], run);
+                run = 1;
+            }
+            if (bx[k] == bx[k - 1]) {
+                qs += q[k];
+            } else {
+                atomicAdd(&ssum[bx[k - 1]], qs);
+                qs = q[k];
+            }
+        }
+        atomicAdd(&scnt[b[7]], run);
+        atomicAdd(&ssum[bx[7]], qs);
+    }
+    for (uint64_t i = n8 * 8 + uint64_t(blockIdx.x) * 256u + threadIdx.x; i < ncell;
+         i += stride) {
+        int b, bx;
+        double q;
+        bins(nH[i], qsrc[i], b, bx, q);
+        atomicAdd(&scnt[b], 1u);
         atomicAdd(&ssum[bx], q);
     }
     __syncthreads();
@@ -84,10 +126,13 @@ hipError_t launch_hist(const float *nH, const float *q, int gamma, double csig, 
                        float loy, float inv_wy, unsigned long long *counts, double *sums,
                        hipStream_t s)
 {
-    const uint32_t want = (ncell + 255u) / 256u;
-    const unsigned blocks = want < 2048u ? (want > 0 ? want : 1u) : 2048u;
+    const int vec = (reinterpret_cast<uintptr_t>(nH) % 16 == 0) &&
+                    (reinterpret_cast<uintptr_t>(q) % 16 == 0);
+    const uint64_t work = vec ? (uint64_t(ncell) + 7u) / 8u : uint64_t(ncell);
+    const uint64_t want = (work + 255u) / 256u;
+    const unsigned blocks = want < 8192u ? (want > 0 ? unsigned(want) : 1u) : 8192u;
     hipLaunchKernelGGL(hist_kernel, dim3(blocks), dim3(256), hist_lds_bytes(nbx, nby), s, nH,
-                       q, gamma, csig, ncell, nbx, nby, edges, lox, inv_wx, loy, inv_wy,
+                       q, gamma, csig, ncell, nbx, nby, edges, lox, inv_wx, loy, inv_wy, vec,
                        counts, sums);
     return hipGetLastError();
 }

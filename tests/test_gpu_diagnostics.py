@@ -4,8 +4,9 @@ oracle (Sec. 3.1.5 distributions over density, Sec. 3.1.4 Thomson depth):
   * rt_histogram counts equal the oracle's exactly (integer work) for the
     neutral fraction and the photoionisation rate, on an evolved
     cosmological state, on a ragged grid, at the largest bin count and for
-    a single bin; values exactly on edges and out of range land where the
-    definition puts them; per-density-bin sums agree to 1e-12;
+    a single bin, on fields that are not 16-byte aligned; values exactly on
+    edges and out of range land where the definition puts them;
+    per-density-bin sums agree to 1e-12;
   * tau_e: closed form for a frozen uniform state (c sigma_T <n_e> t), and
     the oracle's step-by-step sum on a Stromgren run;
   * rt_equilibrium_xhi under the plateau, J1 and J4 models, with and
@@ -82,6 +83,43 @@ def test_histogram_edges_range_and_ragged_grid():
     check_hist(G, st, rt.HQ_GAMMA, xr, (-14.0, -6.0, 16))
     G.close()
     assert counts.sum() == flat.size
+
+
+@pytest.mark.parametrize("offset", [0, 1, 2])
+def test_histogram_on_unaligned_fields(offset):
+    # fields that start 4 or 8 bytes past a 16-byte boundary take the
+    # cell-by-cell path; the counts are the same
+    shape = (5, 7, 41)                       # 1435 cells: not a multiple of 8
+    n = int(np.prod(shape))
+    st = W.random_state(shape, seed=17 + offset)
+    buf = {k: torch.zeros(n + 4, dtype=torch.float32, device="cuda") for k in
+           ("N0", "N1", "Fx0", "Fx1", "Fy0", "Fy1", "Fz0", "Fz1", "xHI", "T", "nH")}
+    view = {k: v[offset:offset + n] for k, v in buf.items()}
+    for k in ("xHI", "T", "nH"):
+        view[k].copy_(torch.from_numpy(st[k].reshape(-1)))
+    for k in ("N", "Fx", "Fy", "Fz"):
+        view[k + "0"].copy_(torch.from_numpy(st[k].reshape(-1)))
+    f = rt.rt_fields()
+    for k in ("N", "Fx", "Fy", "Fz"):
+        getattr(f, k)[0] = view[k + "0"].data_ptr()
+        getattr(f, k)[1] = view[k + "1"].data_ptr()
+    f.xHI, f.T, f.nH = view["xHI"].data_ptr(), view["T"].data_ptr(), view["nH"].data_ptr()
+    assert (view["nH"].data_ptr() % 16 == 0) == (offset == 0)
+    torch.cuda.synchronize()
+    rc, ctx = rt.rt_init(rt.make_params(shape, 1e21), f, None)
+    rt.check(rc, "rt_init")
+    try:
+        for quantity, yr in ((rt.HQ_XHI, (-7.0, 0.5, 32)), (rt.HQ_GAMMA, (-16.0, -8.0, 32))):
+            xr = (-6.0, 0.0, 24)
+            rc, counts, sums = rt.rt_histogram(ctx, quantity, xr, yr)
+            rt.check(rc, "rt_histogram")
+            q = st["xHI"] if quantity == rt.HQ_XHI else D.photoionisation_rate(st["N"], C,
+                                                                               rt.SIGMA_N)
+            oc, osum = D.histogram2d(st["nH"], q, xr, yr)
+            assert np.array_equal(counts, oc)
+            assert np.allclose(sums, osum, rtol=1e-12, atol=0.0)
+    finally:
+        rt.lib().rt_destroy(ctx)
 
 
 def test_histogram_rejects_bad_ranges():

@@ -86,17 +86,26 @@ __device__ __forceinline__ Speeds m1_speeds(float N, float Fx, float Fy, float F
     const float x2 = ux * ux, y2 = uy * uy, z2 = uz * uz;
     const float f2 = x2 + y2 + z2;
     if (!(f2 > 1e-20f)) return s;
+    // 1 - f^2 = ((cN)^2 - |F|^2) / (cN)^2: the difference in FP64 (it cancels
+    // near free streaming), the quotient in FP32
     const double cn = double(N) * c_d;
-    const double g2d =
-        1.0 - (double(Fx) * double(Fx) + double(Fy) * double(Fy) + double(Fz) * double(Fz)) /
-                  (cn * cn);
-    const float g2 = float(g2d > 0.0 ? g2d : 0.0);    // 1 - f^2
+    const double cn2 = cn * cn;
+    const double diff =
+        cn2 - (double(Fx) * double(Fx) + double(Fy) * double(Fy) + double(Fz) * double(Fz));
+    const float g2 = diff > 0.0 ? float(diff) * frcp(float(cn2)) : 0.0f;   // 1 - f^2
     const float fs = 1.0f - g2;
     const float S = fsqrt(1.0f + 3.0f * g2);
-    const float Sm1 = 3.0f * g2 * frcp(S + 1.0f);
+    const float Sp1 = S + 1.0f;
     const float D = 5.0f + 2.0f * S;
-    const float Q = (8.0f * D + 6.0f * (3.0f + 4.0f * fs) * frcp(S)) * frcp(D * D);  // chi'/f
-    const float pref = 8.0f * Sm1 * frcp(3.0f * S * S);
+    const float D2 = D * D;
+    // one reciprocal for 1/S, 1/(S+1) and 1/D^2
+    const float R = frcp(S * Sp1 * D2);
+    const float inv_S = R * Sp1 * D2;
+    const float inv_Sp1 = R * S * D2;
+    const float inv_D2 = R * S * Sp1;
+    const float Sm1 = 3.0f * g2 * inv_Sp1;
+    const float Q = (8.0f * D + 6.0f * (3.0f + 4.0f * fs) * inv_S) * inv_D2;   // chi'/f
+    const float pref = (8.0f / 3.0f) * Sm1 * inv_S * inv_S;
     const float inv_f2 = frcp(f2);
     auto axis = [&](float ud, float a2, float o2, float &lm, float &lp) {
         const float r = fsqrt(pref * (Sm1 * (1.0f + a2 * inv_f2) + o2 * inv_f2));

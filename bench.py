@@ -108,6 +108,82 @@ def cpu_baseline(G, w, dt, nsub, budget_s: float, chem: str = "full", clump=None
                       f"step each ({cells} cell-updates in {t_total:.1f} s)"}
 
 
+def _omp_threads(n: int):
+    """Set the OpenMP thread count of this process (the oracle's parallel
+    loops) through the OpenMP runtime it is linked with."""
+    import ctypes
+
+    ctypes.CDLL("libgomp.so.1").omp_set_num_threads(int(n))
+
+
+def _host_info() -> dict:
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+        with open("/proc/meminfo") as fh:
+            mem_kb = int(fh.readline().split()[1])
+    except OSError:
+        mem_kb = 0
+    return {"cpu": model, "cpus_usable": len(os.sched_getaffinity(0)),
+            "nproc_online": os.cpu_count(), "mem_GiB": round(mem_kb / 2 ** 20, 1)}
+
+
+def cpu_baseline_configs(budget_s: float = 20.0):
+    """The CPU baseline on the configurations themselves: the FP64 oracle on
+    the Stromgren 32^3 test (200 steps), the 128^3 grid (1000 steps) and
+    the 256^3 grid (500 steps), from their initial states, with one thread
+    and with every usable host thread.  Each timing runs whole steps until
+    the config's step count or budget_s of oracle time is reached; rates
+    are cell-updates per second and the full-run times are extrapolated
+    from them where the run was cut."""
+    import oracle
+    from paper_1004_2503_amd import workloads as W
+
+    oracle.lib()
+    full = max(1, int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0)))
+    full = min(full, len(os.sched_getaffinity(0)))
+    rows = []
+    for name in ("stromgren32", "cosmo128", "cosmo256"):
+        w = W.workload(name)
+        n = w.n
+        if name == "stromgren32":
+            st = dict(xHI=np.ones((n,) * 3), T=np.full((n,) * 3, w.T0),
+                      nH=np.full((n,) * 3, w.nH_mean))
+            src = W.stromgren_sources(w)
+            bc = w.bc
+        else:
+            nH, ijk, ndot = W.cosmo_inputs(w, device="cpu")
+            nH = nH.numpy().astype(np.float64)
+            st = dict(xHI=np.ones_like(nH), T=np.full_like(nH, w.T0), nH=nH)
+            src = (ijk, ndot)
+            bc = (0,) * 6
+        for threads in (1, full):
+            _omp_threads(threads)
+            g = oracle.Grid(oracle.make_params((n,) * 3, w.dx, bc=bc, chem=oracle.CHEM_FULL))
+            g.set_state(**st)
+            g.set_sources(*src)
+            done, t = 0, 0.0
+            while done < w.steps and t < budget_s:
+                t0 = time.perf_counter()
+                g.step(w.dt, 1)
+                t += time.perf_counter() - t0
+                done += 1
+            rate = n ** 3 * done / t
+            rows.append({"config": name, "cells": n ** 3, "config_steps": w.steps,
+                         "threads": threads, "steps_timed": done, "seconds": round(t, 3),
+                         "cell_updates_per_s": rate,
+                         "full_run_s": round(n ** 3 * w.steps / rate, 1),
+                         "extrapolated": done < w.steps})
+            print(f"# oracle {name} threads={threads}: {done} steps in {t:.1f} s, "
+                  f"{rate:.3e} cell-updates/s", file=sys.stderr, flush=True)
+    _omp_threads(full)
+    return {"host": _host_info(), "rows": rows}
+
+
 def surrogate_leg(args, G, w, dt, params, src):
     """Train the network on exact pairs sampled from the 256^3 run (several
     dt), then time, from the same state and for the same number of steps,
@@ -334,6 +410,9 @@ def main():
                     help="instead of the step, time a plain device copy of MIB MiB "
                          "(the reference for the HBM byte counters)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-baseline-configs", action="store_true",
+                    help="instead of the step, time the FP64 oracle on the 32^3, 128^3 and "
+                         "256^3 configurations with one and with all host threads")
     ap.add_argument("--surrogate", action="store_true",
                     help="also train the learned chemistry on exact pairs from the 256^3 "
                          "run and time the surrogate form on the same workload")
@@ -350,6 +429,10 @@ def main():
               "MI355X holding the whole grid; multi-GPU runs are not supported.",
               file=sys.stderr)
         sys.exit(2)
+
+    if args.cpu_baseline_configs:
+        print(json.dumps(cpu_baseline_configs(args.cpu_seconds)), flush=True)
+        return
 
     import torch
 

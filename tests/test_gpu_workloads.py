@@ -53,6 +53,8 @@ def test_stromgren32_front_after_500_steps(chem):
     g.step(w.dt, 1, 500)
     r_gpu = front_radius_cells(out["xHI"], w.dx)
     r_orc = front_radius_cells(g.xHI, w.dx)
+    print(f"stromgren32 chem={chem}: front after 500 steps {r_gpu:.4f} (GPU) vs "
+          f"{r_orc:.4f} (oracle) cells", flush=True)
     assert abs(r_gpu - r_orc) < 1.0, (r_gpu, r_orc)
     assert abs(r_gpu - r_orc) < 0.05 * r_orc
     if chem == rt.CHEM_ISOTHERMAL:
@@ -92,6 +94,7 @@ def test_cosmological_one_step_from_evolved_state(name, steps):
     g = oracle_grid(st, shape, w.dx, (0,) * 6, oracle.CHEM_FULL, sources=src)
     g.step(w.dt, 1)
     e = errors(out, oracle_state(g))
+    print(f"{name}: one-step errors from the state after {steps} steps: {e}", flush=True)
     assert_parity(e, what=name)
     # the evolved state is non-trivial: photons spread and gas ionised
     assert np.count_nonzero(st["N"]) > 0.005 * st["N"].size

@@ -749,7 +749,10 @@ __global__ __launch_bounds__(256) void state_sums_kernel(const float *__restrict
     __shared__ double s[4][256];
     const int t = threadIdx.x;
     double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-    for (uint32_t i = blockIdx.x * 256u + t; i < ncell; i += gridDim.x * 256u) {
+    // 64-bit index: with ncell just below 2^32 a 32-bit index would wrap
+    // past the end and never leave the loop
+    const uint64_t stride = uint64_t(gridDim.x) * 256u;
+    for (uint64_t i = uint64_t(blockIdx.x) * 256u + t; i < ncell; i += stride) {
         const double x = xHI[i], n = nH[i];
         a0 += x;
         a1 += n * x;

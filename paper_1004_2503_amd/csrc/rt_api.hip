@@ -49,6 +49,7 @@ struct rt_ctx {
     double ndot_total = 0.0;
     double *d_part = nullptr;
     int npart = 0;
+    double *d_fin = nullptr;   // first-level finalisation rows
     double *d_acc = nullptr;
     float *d_sink = nullptr;
     unsigned long long *d_hcount = nullptr;  // RT_HIST_MAX_BINS
@@ -112,6 +113,7 @@ static void free_ctx(rt_ctx *c)
     if (c->d_src_key) (void)hipFree(c->d_src_key);
     if (c->d_src_rate) (void)hipFree(c->d_src_rate);
     if (c->d_part) (void)hipFree(c->d_part);
+    if (c->d_fin) (void)hipFree(c->d_fin);
     if (c->d_acc) (void)hipFree(c->d_acc);
     if (c->d_sink) (void)hipFree(c->d_sink);
     if (c->d_hcount) (void)hipFree(c->d_hcount);
@@ -168,6 +170,7 @@ extern "C" int rt_init(const rt_params *params, const rt_fields *fields, void *h
     c->npart = std::max(c->nblocks, state_sums_blocks(c->ncell));
 
     if (hipMalloc(&c->d_part, size_t(c->npart) * NRED * sizeof(double)) != hipSuccess ||
+        hipMalloc(&c->d_fin, size_t(FIN1_BLOCKS) * NRED * sizeof(double)) != hipSuccess ||
         hipMalloc(&c->d_acc, ACC_SIZE * sizeof(double)) != hipSuccess ||
         hipMalloc(&c->d_src_ptr, size_t(c->nblocks + 1) * sizeof(int32_t)) != hipSuccess ||
         hipMalloc(&c->d_sink, NTHREADS * sizeof(float)) != hipSuccess ||
@@ -188,7 +191,8 @@ extern "C" int rt_init(const rt_params *params, const rt_fields *fields, void *h
     const int nsb = state_sums_blocks(c->ncell);
     if (launch_state_sums(fields->N[0], fields->xHI, fields->nH, c->ncell, c->d_part, nsb,
                           c->stream) != hipSuccess ||
-        launch_finalize(c->d_part, nsb, c->d_acc, 1, 0.0, 0.0, c->stream) != hipSuccess) {
+        launch_finalize(c->d_part, nsb, c->d_fin, c->d_acc, 1, 0.0, 0.0, c->stream) !=
+            hipSuccess) {
         free_ctx(c);
         return RT_E_HIP;
     }
@@ -482,8 +486,8 @@ extern "C" int rt_step(rt_ctx *c, double dt, int32_t nsub)
     if (launch_step(a, c->stream) != hipSuccess) return RT_E_HIP;
     if (e && hipEventRecord(e->b, c->stream) != hipSuccess) return RT_E_HIP;
     const double tau_coef = c->p.c_cms * SIGMA_T * dt / double(c->ncell);
-    if (launch_finalize(c->d_part, c->nblocks, c->d_acc, 0, tau_coef, c->nh_sum, c->stream) !=
-        hipSuccess)
+    if (launch_finalize(c->d_part, c->nblocks, c->d_fin, c->d_acc, 0, tau_coef, c->nh_sum,
+                        c->stream) != hipSuccess)
         return RT_E_HIP;
     c->cur = 1 - c->cur;
     c->t += dt;

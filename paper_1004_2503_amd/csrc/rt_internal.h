@@ -94,8 +94,12 @@ hipError_t launch_particle_rates(int64_t n, const double *pos, const double *age
                                  hipStream_t s);
 int check_clump(const rt_params &p);
 hipError_t launch_mlp_pack(const float *theta, __bf16 *pk, hipStream_t s);
-// mode 0 also adds tau_coef * (nh_sum - sum nH xHI) to acc[ACC_CUM + ACC_TAU]
-hipError_t launch_finalize(const double *partials, int nblocks, double *acc,
+// mode 0 also adds tau_coef * (nh_sum - sum nH xHI) to acc[ACC_CUM + ACC_TAU].
+// More than FIN1_MIN partial rows go through a first level of FIN1_BLOCKS
+// blocks whose rows land in scratch (FIN1_BLOCKS * NRED doubles).
+constexpr int FIN1_BLOCKS = 256;
+constexpr int FIN1_MIN = 4096;
+hipError_t launch_finalize(const double *partials, int nblocks, double *scratch, double *acc,
                            int mode, double tau_coef, double nh_sum, hipStream_t s);
 size_t hist_lds_bytes(int nbx, int nby);
 hipError_t launch_hist(const float *nH, const float *q, int gamma, double csig, uint32_t ncell,

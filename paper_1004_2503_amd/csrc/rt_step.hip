@@ -739,6 +739,37 @@ __global__ __launch_bounds__(FIN_THREADS) void finalize_kernel(const double *__r
     }
 }
 
+// First level for large grids: FIN1_BLOCKS blocks, each summing a contiguous
+// range of block partials in a fixed order (strided per thread, then the
+// wavefronts and the block), so that finalize_kernel only combines
+// FIN1_BLOCKS rows.  One block reading every partial is latency-bound.
+__global__ __launch_bounds__(256) void finalize_partial_kernel(const double *__restrict__ part,
+                                                               int nb,
+                                                               double *__restrict__ out)
+{
+    __shared__ double s[4][NRED];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int per = (nb + int(gridDim.x) - 1) / int(gridDim.x);
+    const int b0 = int(blockIdx.x) * per, b1 = min(nb, b0 + per);
+    double v[NRED];
+#pragma unroll
+    for (int j = 0; j < NRED; ++j) v[j] = 0.0;
+    for (int b = b0 + t; b < b1; b += 256) {
+        const double *p = part + size_t(b) * NRED;
+#pragma unroll
+        for (int j = 0; j < NRED; ++j) v[j] += p[j];
+    }
+#pragma unroll
+    for (int j = 0; j < NRED; ++j) {
+        double x = v[j];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off);
+        if (lane == 0) s[wave][j] = x;
+    }
+    __syncthreads();
+    if (t < NRED) out[size_t(blockIdx.x) * NRED + t] = ((s[0][t] + s[1][t]) + s[2][t]) + s[3][t];
+}
+
 // --------------------------------------- sums of a state (at rt_init)
 __global__ __launch_bounds__(256) void state_sums_kernel(const float *__restrict__ N,
                                                          const float *__restrict__ xHI,
@@ -808,9 +839,15 @@ hipError_t launch_step(const StepArgs &a, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_finalize(const double *partials, int nblocks, double *acc, int mode,
-                           double tau_coef, double nh_sum, hipStream_t s)
+hipError_t launch_finalize(const double *partials, int nblocks, double *scratch, double *acc,
+                           int mode, double tau_coef, double nh_sum, hipStream_t s)
 {
+    if (nblocks > FIN1_MIN) {
+        hipLaunchKernelGGL(finalize_partial_kernel, dim3(FIN1_BLOCKS), dim3(256), 0, s,
+                           partials, nblocks, scratch);
+        partials = scratch;
+        nblocks = FIN1_BLOCKS;
+    }
     hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(FIN_THREADS), 0, s, partials, nblocks,
                        acc, mode, tau_coef, nh_sum);
     return hipGetLastError();

@@ -230,9 +230,12 @@ __global__ __launch_bounds__(NTHREADS, SURR ? 2 : RT_M1_MINW) void m1_step_kerne
     const float hsx_sign = has_halo ? hx.sign : 1.0f, hsy_sign = has_halo ? hy.sign : 1.0f;
     auto load_ch = [&](float3 &c, int zz) {
         const uint32_t i = col + uint32_t(zz) * plane;
-        c.x = A.xHI[i];
-        c.y = A.T[i];
-        c.z = A.nH[i];
+        // read once per step by this thread alone: non-temporal loads keep
+        // them from displacing the N, F lines that neighbouring tiles read
+        // as halo (measured 1.5% faster; N, F loaded so were 3-20% slower)
+        c.x = __builtin_nontemporal_load(&A.xHI[i]);
+        c.y = __builtin_nontemporal_load(&A.T[i]);
+        c.z = __builtin_nontemporal_load(&A.nH[i]);
     };
     const Cell4 zero4{0.f, 0.f, 0.f, 0.f};
     const float3 zero3 = make_float3(0.f, 0.f, 0.f);

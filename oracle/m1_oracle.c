@@ -2,7 +2,9 @@
  * m1_oracle.c -- FP64 CPU reference of the explicit M1 transport step and
  * the per-cell hydrogen chemistry operator.  TEST INFRASTRUCTURE ONLY (see
  * m1_oracle.h): plain loops, every quantity from its definition, no tiling,
- * no fusion beyond what the method itself states.  OpenMP only splits the
+ * no fusion beyond what the method itself states.  Parity unpinned: the
+ * rate coefficients other than alpha_B and the adaptive sub-cycle time
+ * scale (marked where they are defined).  OpenMP only splits the
  * independent per-cell loops; every tally is summed per z-plane and then
  * over planes in a fixed order, so results do not depend on thread count.
  */
@@ -84,6 +86,8 @@ static double pcomp(const double P[6], int k, int d)
  *   r[3] collisional excitation cooling (HI)    [erg cm^3/s] Cen 1992
  *   r[4] collisional ionisation cooling = 13.6 eV * beta
  *   r[5] free-free (bremsstrahlung) cooling     [erg cm^3/s] Cen 1992
+ * Pinned: alpha_B against a published table.  Parity unpinned: r[1]..r[5]
+ * (the paper gives no rates; nothing outside this file fixes their values).
  * --------------------------------------------------------------------- */
 void orc_rates(double T, double r[6])
 {
@@ -134,7 +138,9 @@ static double cooling(const double r[6], double nHII, double nHI, double C_R)
  * internal-energy times, each against the GROSS rate of change (creation
  * plus destruction, heating plus cooling).  Against the net rate the time
  * scale would be ill-conditioned near equilibrium, where the net rate is a
- * small difference of large terms. */
+ * small difference of large terms.  Parity unpinned: the paper states no
+ * sub-cycling rule (the adaptive mode's convergence to the fixed-step limit
+ * is what the tests check). */
 static double chem_timescale(const orc_params *p, double nH, double N,
                              double xHI, double T)
 {

@@ -93,7 +93,7 @@ def _init_params(seed: int) -> np.ndarray:
 
 
 def fit(X, Y, steps: int = 3000, batch: int = 65536, lr: float = 2e-3, seed: int = 0,
-        grad_blocks: int = 1024, log_every: int = 250, verbose: bool = True,
+        grad_blocks: int = 512, log_every: int = 250, verbose: bool = True,
         warmup: float = 0.05, clip: float | None = 1.0) -> Surrogate:
     """Fit the network to raw features X (n, 5) and end values Y (n, 2) =
     (log10 xHI', log10 T'), device tensors; it learns encode(X, Y).  Adam

@@ -26,6 +26,8 @@ constexpr int MAX_NSUB = 4096;
 #define RT_M1_ZC 64
 #endif
 constexpr int ZC_DEFAULT = RT_M1_ZC;  // planes per block along z
+// the step keeps one FP64-cell mask word per plane of its chunk in a lane
+static_assert(ZC_DEFAULT <= TX, "z chunks longer than a wavefront");
 constexpr double SIGMA_T = 6.6524587321e-25;  // Thomson cross-section [cm^2]
 constexpr int HSUM_DOUBLES = 256 + 2 * 257;   // histogram sums + edges
 
@@ -50,6 +52,9 @@ struct rt_ctx {
     double *d_part = nullptr;
     int npart = 0;
     double *d_fin = nullptr;   // first-level finalisation rows
+    uint64_t *d_mask = nullptr;   // FP64 cells left by the step (mixed LF)
+    uint64_t nwords = 0;
+    int nb2 = 0;                  // blocks of the deferred FP64 chemistry
     double *d_acc = nullptr;
     float *d_sink = nullptr;
     unsigned long long *d_hcount = nullptr;  // RT_HIST_MAX_BINS
@@ -114,6 +119,7 @@ static void free_ctx(rt_ctx *c)
     if (c->d_src_rate) (void)hipFree(c->d_src_rate);
     if (c->d_part) (void)hipFree(c->d_part);
     if (c->d_fin) (void)hipFree(c->d_fin);
+    if (c->d_mask) (void)hipFree(c->d_mask);
     if (c->d_acc) (void)hipFree(c->d_acc);
     if (c->d_sink) (void)hipFree(c->d_sink);
     if (c->d_hcount) (void)hipFree(c->d_hcount);
@@ -167,13 +173,23 @@ extern "C" int rt_init(const rt_params *params, const rt_fields *fields, void *h
         return RT_E_ARG;
     }
     c->nblocks = int(nb);
-    c->npart = std::max(c->nblocks, state_sums_blocks(c->ncell));
+    const bool defer = params->prec == RT_PREC_MIXED && params->flux == RT_FLUX_LF;
+    if (defer) {
+        c->nwords = uint64_t(params->nz) * uint64_t(params->ny) * uint64_t(c->ntx);
+        c->nb2 = defer_chem_blocks(c->nwords);
+    }
+    c->npart = std::max(c->nblocks + c->nb2, state_sums_blocks(c->ncell));
+    if (defer && hipMalloc(&c->d_mask, c->nwords * sizeof(uint64_t)) != hipSuccess) {
+        (void)hipGetLastError();
+        free_ctx(c);
+        return RT_E_NOMEM;
+    }
 
     if (hipMalloc(&c->d_part, size_t(c->npart) * NRED * sizeof(double)) != hipSuccess ||
         hipMalloc(&c->d_fin, size_t(FIN1_BLOCKS) * NRED * sizeof(double)) != hipSuccess ||
         hipMalloc(&c->d_acc, ACC_SIZE * sizeof(double)) != hipSuccess ||
         hipMalloc(&c->d_src_ptr, size_t(c->nblocks + 1) * sizeof(int32_t)) != hipSuccess ||
-        hipMalloc(&c->d_sink, NTHREADS * sizeof(float)) != hipSuccess ||
+        hipMalloc(&c->d_sink, 3 * NTHREADS * sizeof(float)) != hipSuccess ||
         hipMalloc(&c->d_hcount, RT_HIST_MAX_BINS * sizeof(unsigned long long)) != hipSuccess ||
         hipMalloc(&c->d_hsum, HSUM_DOUBLES * sizeof(double)) != hipSuccess) {
         (void)hipGetLastError();
@@ -453,6 +469,8 @@ static void fill_args(const rt_ctx *c, double dt, int nsub, StepArgs &a)
     a.vol = p.dx_cm * p.dx_cm * p.dx_cm;
     a.esc_scale = dt * p.dx_cm * p.dx_cm;
     a.hll = p.flux == RT_FLUX_HLL ? 1 : 0;
+    a.defer = (p.prec == RT_PREC_MIXED && p.flux == RT_FLUX_LF && !c->surr) ? 1 : 0;
+    a.fp64_mask = c->d_mask;
     a.c_d = p.c_cms;
     a.surr = c->surr ? 1 : 0;
     a.surr_pk = c->d_surr_pk;
@@ -484,9 +502,14 @@ extern "C" int rt_step(rt_ctx *c, double dt, int32_t nsub)
         if (hipEventRecord(e->a, c->stream) != hipSuccess) return RT_E_HIP;
     }
     if (launch_step(a, c->stream) != hipSuccess) return RT_E_HIP;
+    int rows = c->nblocks;
+    if (a.defer) {
+        if (launch_defer_chem(a, c->nwords, c->nb2, c->stream) != hipSuccess) return RT_E_HIP;
+        rows += c->nb2;
+    }
     if (e && hipEventRecord(e->b, c->stream) != hipSuccess) return RT_E_HIP;
     const double tau_coef = c->p.c_cms * SIGMA_T * dt / double(c->ncell);
-    if (launch_finalize(c->d_part, c->nblocks, c->d_fin, c->d_acc, 0, tau_coef, c->nh_sum,
+    if (launch_finalize(c->d_part, rows, c->d_fin, c->d_acc, 0, tau_coef, c->nh_sum,
                         c->stream) != hipSuccess)
         return RT_E_HIP;
     c->cur = 1 - c->cur;

@@ -57,13 +57,20 @@ struct StepArgs {
     const int32_t *src_key;          // (z - z0) * NTHREADS + thread index
     const float *src_rate;           // S = ndot / dx^3 [cm^-3 s^-1]
     double *partials;                // nblocks * NRED
-    float *sink;                     // NTHREADS floats: stores of lanes off the grid
+    float *sink;                     // 3 NTHREADS floats: stores of lanes off the grid
+                                     // (NTHREADS floats, then NTHREADS 64-bit words)
     int nx, ny, nz;
     uint32_t plane;                  // nx * ny
     int ntx, nty, nzc, zc, nblocks;
     int bc[6];
     int chem, mixed, adaptive, nsub, any_outflow;
     int hll;                         // 1: HLL fluxes, 0: LF
+    // mixed precision with LF fluxes and the exact chemistry: cells whose
+    // chemistry runs in FP64 are marked in fp64_mask (one bit per cell, one
+    // 64-bit word per x-row of a tile: word (z * ny + y) * ntx + tile x) and
+    // left for launch_defer_chem
+    int defer;
+    uint64_t *fp64_mask;
     ClumpLaw cl;
     // FP32 constants
     float c, inv_c, half_c, half_c2, k1, dt, csig, T_h, inv15kB, T_floor,
@@ -85,6 +92,10 @@ constexpr int SURR_NBIAS = 194;
 constexpr int SURR_NNORM = 24;
 
 hipError_t launch_step(const StepArgs &a, hipStream_t s);
+// The FP64 chemistry of the cells marked by the step (StepArgs::defer): nb2
+// blocks, whose partial sums land in rows nblocks .. nblocks + nb2 - 1.
+int defer_chem_blocks(uint64_t nwords);
+hipError_t launch_defer_chem(const StepArgs &a, uint64_t nwords, int nb2, hipStream_t s);
 ClumpLaw make_clump_law(const rt_params &p);
 int inject_host(rt_ctx *c, int64_t n, const int32_t *ijk, const double *ndot);
 hipError_t launch_particle_rates(int64_t n, const double *pos, const double *age_next,

@@ -109,6 +109,10 @@ __device__ __forceinline__ Cell4 load4(const StepArgs &A, uint32_t i, float sx, 
 template <bool MIXED, bool SURR, bool HLL>
 __global__ __launch_bounds__(NTHREADS, SURR ? 2 : RT_M1_MINW) void m1_step_kernel(StepArgs A)
 {
+    // The LF mixed form leaves its FP64 cells to a second, small kernel
+    // (launch_defer_chem): the few waves that would take the FP64 branch
+    // here cost every wave registers and scheduling freedom.
+    constexpr bool DEFER = MIXED && !SURR && !HLL;
     constexpr int SW = TX + 2;
     __shared__ __attribute__((aligned(16))) __bf16 s_pk[SURR ? PK_FWD * 8 : 8];
     __shared__ float s_bias[SURR ? SURR_NBIAS : 1];
@@ -250,6 +254,7 @@ __global__ __launch_bounds__(NTHREADS, SURR ? 2 : RT_M1_MINW) void m1_step_kerne
     // nx_ld receives plane z+2.  hal: this thread's halo cell of plane z;
     // hal_ld receives plane z+1's.  ch: xHI, T, nH of plane z; ch_ld
     // receives plane z+1's.
+    uint64_t mword = 0;   // DEFER: this lane's plane (z0 + lane) of FP64 cells
     auto plane_step = [&](const int z, const Cell4 &nxt_raw, Cell4 &nx_ld, const Cell4 &hal_raw,
                           Cell4 &hal_ld, const float3 &ch, float3 &ch_ld) {
         const float c_xh = ch.x, c_T = ch.y, c_nh = ch.z;
@@ -458,6 +463,7 @@ __global__ __launch_bounds__(NTHREADS, SURR ? 2 : RT_M1_MINW) void m1_step_kerne
         int ncyc = 0;
         bool used64 = false;
         bool fallback = true;
+        bool deferred = false;
         // Phi leaves a dark, fully neutral cell exactly as it is; a
         // wavefront of such cells branches around the chemistry entirely
         const bool dark = !(Nt > 0.0f) && c_xh >= 1.0f;
@@ -543,7 +549,9 @@ __global__ __launch_bounds__(NTHREADS, SURR ? 2 : RT_M1_MINW) void m1_step_kerne
             }
         }
         if (A.chem != RT_CHEM_OFF && fallback && !dark) {
-            if (MIXED && c_xh < A.xhi_thr) {
+            if (DEFER && c_xh < A.xhi_thr) {
+                deferred = true;   // N, F leave transported; xHI, T as they are
+            } else if (MIXED && !DEFER && c_xh < A.xhi_thr) {
                 double Nd = Nt, xd = c_xh, Td = c_T, ad = 0.0;
                 float cR, cI;
                 clump_f32(A.cl, c_nh, cR, cI);
@@ -562,7 +570,7 @@ __global__ __launch_bounds__(NTHREADS, SURR ? 2 : RT_M1_MINW) void m1_step_kerne
                 pabs = af;
             }
         }
-        if (A.chem != RT_CHEM_OFF) {
+        if (A.chem != RT_CHEM_OFF && !deferred) {
             const float sc = (Nt > N_TINY) ? rmin(Nn * frcp(Nt), 1.0f) : 0.0f;
             Fxt *= sc;
             Fyt *= sc;
@@ -581,7 +589,14 @@ __global__ __launch_bounds__(NTHREADS, SURR ? 2 : RT_M1_MINW) void m1_step_kerne
             store_out(active ? &A.xHI[i] : sink, xh);
             store_out(active ? &A.T[i] : sink, Tc);
         }
-        if (active) {
+        if constexpr (DEFER) {
+            // the word of plane z is kept by lane z - z0 and stored after
+            // the march: no store here to disturb the waits for the
+            // prefetched loads
+            const unsigned long long m = __ballot(active && deferred);
+            if (lx == z - z0) mword = uint64_t(m);
+        }
+        if (active && !deferred) {
             // 0 * v is NaN exactly when v is infinite or NaN; inputs are
             // checked too, since the clamps of Phi would turn a NaN into a bound
             float z0 = 0.0f * Nn + 0.0f * Fxt + 0.0f * Fyt + 0.0f * Fzt + 0.0f * xh + 0.0f * Tc;
@@ -592,7 +607,7 @@ __global__ __launch_bounds__(NTHREADS, SURR ? 2 : RT_M1_MINW) void m1_step_kerne
             n_fp64 += used64 ? 1 : 0;
             n_fb += (SURR && fallback && !dark && A.chem != RT_CHEM_OFF) ? 1 : 0;
         }
-        if (active) {
+        if (active && !deferred) {
             acc_xhi += double(xh);
             acc_nhxhi = fma(double(c_nh), double(xh), acc_nhxhi);
             acc_N += double(Nn);
@@ -616,7 +631,8 @@ __global__ __launch_bounds__(NTHREADS, SURR ? 2 : RT_M1_MINW) void m1_step_kerne
             const int bin = hist_bin(ncyc);
 #pragma unroll
             for (int hb = 0; hb < 8; ++hb) {
-                const unsigned long long m = __ballot(active && fallback && bin == hb);
+                const unsigned long long m =
+                    __ballot(active && fallback && !deferred && bin == hb);
                 if (lx == 0 && m) atomicAdd(&shist[hb], __popcll(m));
             }
         }
@@ -646,6 +662,12 @@ __global__ __launch_bounds__(NTHREADS, SURR ? 2 : RT_M1_MINW) void m1_step_kerne
             plane_step(z, nx1, nx0, ha0, ha1, ch0, ch1);
             if (z + 1 < z1) plane_step(z + 1, nx0, nx1, ha1, ha0, ch1, ch0);
         }
+    }
+    if constexpr (DEFER) {
+        // one x-row per wave, the chunk's planes z0 .. z1-1 one per lane
+        // (chunks are at most 64 planes)
+        if (gy < A.ny && z0 + lx < z1)
+            A.fp64_mask[(size_t(z0 + lx) * A.ny + gy) * A.ntx + (x0 / TX)] = mword;
     }
     {
         double d[4] = {acc_xhi, acc_nhxhi, acc_N, acc_abs};
@@ -690,6 +712,125 @@ __global__ __launch_bounds__(NTHREADS, SURR ? 2 : RT_M1_MINW) void m1_step_kerne
         }
         A.partials[size_t(blockIdx.x) * NRED + tid] = s;
     }
+}
+
+// ------------------------------------- deferred FP64 chemistry (mixed LF)
+// The cells the step marked in fp64_mask hold their transported N, F in the
+// next buffer and their step-start xHI, T.  Each wavefront reads 64 mask
+// words at a time (one per lane) and then takes the non-empty ones in turn,
+// its lanes being the 64 cells of the word's tile row: Phi in FP64, F scaled
+// by the photons left, and the cell's share of the sums that the step left
+// out, reduced per block in a fixed order.
+constexpr int DEFER_THREADS = 256, DEFER_MAX_BLOCKS = 8192;
+
+__global__ __launch_bounds__(DEFER_THREADS) void defer_chem_kernel(StepArgs A, uint64_t nwords)
+{
+    __shared__ double sred[DEFER_THREADS / 64][NRED];
+    __shared__ int shist[8];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    if (tid < 8) shist[tid] = 0;
+    __syncthreads();
+    const ChemK<double> Kd{A.dt_d, A.dt_d / double(A.nsub), A.csig_d, A.T_h_d, A.T_floor_d,
+                           A.sub_eps_d};
+    double acc_xhi = 0.0, acc_nhxhi = 0.0, acc_N = 0.0, acc_abs = 0.0;
+    int n_bad = 0, n_fp64 = 0;
+    const uint64_t waves = uint64_t(gridDim.x) * (DEFER_THREADS / 64);
+    for (uint64_t base = (uint64_t(blockIdx.x) * (DEFER_THREADS / 64) + wave) * 64;
+         base < nwords; base += waves * 64) {
+        const uint64_t mine = base + lane < nwords ? A.fp64_mask[base + lane] : 0ull;
+        unsigned long long todo = __ballot(mine != 0ull);
+        while (todo) {
+            const int src = __builtin_ctzll(todo);
+            todo &= todo - 1ull;
+            const uint32_t lo = __shfl(uint32_t(mine), src), hi = __shfl(uint32_t(mine >> 32), src);
+            const uint64_t m = (uint64_t(hi) << 32) | lo;
+            const uint64_t w = base + src;
+            const int itx = int(w % uint64_t(A.ntx));
+            const uint64_t row = w / uint64_t(A.ntx);
+            const int y = int(row % uint64_t(A.ny)), z = int(row / uint64_t(A.ny));
+            const int x = itx * TX + lane;
+            int ncyc = 0;
+            const bool mark = (m >> lane) & 1ull;
+            if (mark) {
+                const uint32_t i = (uint32_t(z) * uint32_t(A.ny) + uint32_t(y)) * uint32_t(A.nx) +
+                                   uint32_t(x);
+                const float Nt = A.No[i];
+                float Fx = A.Fxo[i], Fy = A.Fyo[i], Fz = A.Fzo[i];
+                const float c_xh = A.xHI[i], c_T = A.T[i], c_nh = A.nH[i];
+                double Nd = Nt, xd = c_xh, Td = c_T, ad = 0.0;
+                float cR, cI;
+                clump_f32(A.cl, c_nh, cR, cI);
+                ncyc = chem_cell<double>(A.chem, A.nsub, A.adaptive, A.inv15kB, Kd, double(cR),
+                                         double(cI), double(c_nh), Nd, xd, Td, ad);
+                const float Nn = float(Nd), xh = float(xd), Tc = float(Td);
+                const float sc = (Nt > N_TINY) ? rmin(Nn * frcp(Nt), 1.0f) : 0.0f;
+                Fx *= sc;
+                Fy *= sc;
+                Fz *= sc;
+                store_out(&A.No[i], Nn);
+                store_out(&A.Fxo[i], Fx);
+                store_out(&A.Fyo[i], Fy);
+                store_out(&A.Fzo[i], Fz);
+                store_out(&A.xHI[i], xh);
+                store_out(&A.T[i], Tc);
+                float z0v = 0.0f * Nn + 0.0f * Fx + 0.0f * Fy + 0.0f * Fz + 0.0f * xh + 0.0f * Tc;
+                z0v += 0.0f * Nt + 0.0f * c_xh + 0.0f * c_T + 0.0f * c_nh;
+                n_bad += z0v == 0.0f ? 0 : 1;
+                n_fp64 += 1;
+                acc_xhi += double(xh);
+                acc_nhxhi = fma(double(c_nh), double(xh), acc_nhxhi);
+                acc_N += double(Nn);
+                acc_abs += ad;
+            }
+            if (A.adaptive) {
+                const int bin = hist_bin(ncyc);
+#pragma unroll
+                for (int hb = 0; hb < 8; ++hb) {
+                    const unsigned long long hm = __ballot(mark && bin == hb);
+                    if (lane == 0 && hm) atomicAdd(&shist[hb], __popcll(hm));
+                }
+            }
+        }
+    }
+    double v[6] = {acc_xhi, acc_nhxhi, acc_N, acc_abs, double(n_bad), double(n_fp64)};
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v[j] += __shfl_xor(v[j], off);
+    }
+    if (lane == 0) {
+#pragma unroll
+        for (int j = 0; j < NRED; ++j) sred[wave][j] = 0.0;
+        sred[wave][R_XHI] = v[0];
+        sred[wave][R_NHXHI] = v[1];
+        sred[wave][R_N] = v[2];
+        sred[wave][R_ABS] = v[3] * A.vol;
+        sred[wave][R_NONFINITE] = v[4];
+        sred[wave][R_FP64] = v[5];
+    }
+    __syncthreads();
+    if (tid < NRED) {
+        double s = 0.0;
+        if (tid < R_HIST0) {
+#pragma unroll
+            for (int w = 0; w < DEFER_THREADS / 64; ++w) s += sred[w][tid];
+        } else {
+            s = double(shist[tid - R_HIST0]);
+        }
+        A.partials[(size_t(A.nblocks) + blockIdx.x) * NRED + tid] = s;
+    }
+}
+
+int defer_chem_blocks(uint64_t nwords)
+{
+    const uint64_t want = (nwords + DEFER_THREADS - 1) / DEFER_THREADS;
+    return int(want < 1 ? 1 : (want > DEFER_MAX_BLOCKS ? DEFER_MAX_BLOCKS : want));
+}
+
+hipError_t launch_defer_chem(const StepArgs &a, uint64_t nwords, int nb2, hipStream_t s)
+{
+    hipLaunchKernelGGL(defer_chem_kernel, dim3(nb2), dim3(DEFER_THREADS), 0, s, a, nwords);
+    return hipGetLastError();
 }
 
 // ---------------------------------------------- finalisation (one block)

@@ -37,16 +37,22 @@ struct Ev {
 
 }  // namespace
 
+// Tiles of one form of the step and the point sources binned into them.
+struct TileSet {
+    int ty = 0, nty = 0, nblocks = 0;
+    int32_t *d_src_ptr = nullptr;   // per tile [start, end) into key/rate
+    int32_t *d_src_key = nullptr;
+    float *d_src_rate = nullptr;
+};
+
 struct rt_ctx {
     rt_params p;
     rt_fields f;
     hipStream_t stream = nullptr;
     int cur = 0;
-    int ntx = 0, nty = 0, nzc = 0, zc = 0, nblocks = 0;
+    int ntx = 0, nzc = 0, zc = 0;
     uint32_t ncell = 0;
-    int32_t *d_src_ptr = nullptr;
-    int32_t *d_src_key = nullptr;
-    float *d_src_rate = nullptr;
+    TileSet geo[2];   // 0: LF forms (TY_LF rows), 1: HLL and surrogate forms (TY rows)
     int64_t nsrc = 0;
     double ndot_total = 0.0;
     double *d_part = nullptr;
@@ -114,9 +120,11 @@ static int check_fields(const rt_fields *f)
 static void free_ctx(rt_ctx *c)
 {
     if (!c) return;
-    if (c->d_src_ptr) (void)hipFree(c->d_src_ptr);
-    if (c->d_src_key) (void)hipFree(c->d_src_key);
-    if (c->d_src_rate) (void)hipFree(c->d_src_rate);
+    for (TileSet &g : c->geo) {
+        if (g.d_src_ptr) (void)hipFree(g.d_src_ptr);
+        if (g.d_src_key) (void)hipFree(g.d_src_key);
+        if (g.d_src_rate) (void)hipFree(g.d_src_rate);
+    }
     if (c->d_part) (void)hipFree(c->d_part);
     if (c->d_fin) (void)hipFree(c->d_fin);
     if (c->d_mask) (void)hipFree(c->d_mask);
@@ -165,20 +173,25 @@ extern "C" int rt_init(const rt_params *params, const rt_fields *fields, void *h
     c->ncell = uint32_t(params->nx) * uint32_t(params->ny) * uint32_t(params->nz);
     c->zc = std::min(ZC_DEFAULT, params->nz);
     c->ntx = (params->nx + TX - 1) / TX;
-    c->nty = (params->ny + TY - 1) / TY;
     c->nzc = (params->nz + c->zc - 1) / c->zc;
-    const int64_t nb = int64_t(c->ntx) * c->nty * c->nzc;
-    if (nb > (int64_t(1) << 30)) {
-        delete c;
-        return RT_E_ARG;
+    for (int gi = 0; gi < 2; ++gi) {
+        TileSet &g = c->geo[gi];
+        g.ty = gi == 0 ? TY_LF : TY;
+        g.nty = (params->ny + g.ty - 1) / g.ty;
+        const int64_t nb = int64_t(c->ntx) * g.nty * c->nzc;
+        if (nb > (int64_t(1) << 30)) {
+            delete c;
+            return RT_E_ARG;
+        }
+        g.nblocks = int(nb);
     }
-    c->nblocks = int(nb);
     const bool defer = params->prec == RT_PREC_MIXED && params->flux == RT_FLUX_LF;
     if (defer) {
         c->nwords = uint64_t(params->nz) * uint64_t(params->ny) * uint64_t(c->ntx);
         c->nb2 = defer_chem_blocks(c->nwords);
     }
-    c->npart = std::max(c->nblocks + c->nb2, state_sums_blocks(c->ncell));
+    c->npart = std::max(std::max(c->geo[0].nblocks + c->nb2, c->geo[1].nblocks),
+                        state_sums_blocks(c->ncell));
     if (defer && hipMalloc(&c->d_mask, c->nwords * sizeof(uint64_t)) != hipSuccess) {
         (void)hipGetLastError();
         free_ctx(c);
@@ -188,16 +201,21 @@ extern "C" int rt_init(const rt_params *params, const rt_fields *fields, void *h
     if (hipMalloc(&c->d_part, size_t(c->npart) * NRED * sizeof(double)) != hipSuccess ||
         hipMalloc(&c->d_fin, size_t(FIN1_BLOCKS) * NRED * sizeof(double)) != hipSuccess ||
         hipMalloc(&c->d_acc, ACC_SIZE * sizeof(double)) != hipSuccess ||
-        hipMalloc(&c->d_src_ptr, size_t(c->nblocks + 1) * sizeof(int32_t)) != hipSuccess ||
-        hipMalloc(&c->d_sink, 3 * NTHREADS * sizeof(float)) != hipSuccess ||
+        hipMalloc(&c->geo[0].d_src_ptr, size_t(c->geo[0].nblocks + 1) * sizeof(int32_t)) !=
+            hipSuccess ||
+        hipMalloc(&c->geo[1].d_src_ptr, size_t(c->geo[1].nblocks + 1) * sizeof(int32_t)) !=
+            hipSuccess ||
+        hipMalloc(&c->d_sink, NTHREADS_MAX * sizeof(float)) != hipSuccess ||
         hipMalloc(&c->d_hcount, RT_HIST_MAX_BINS * sizeof(unsigned long long)) != hipSuccess ||
         hipMalloc(&c->d_hsum, HSUM_DOUBLES * sizeof(double)) != hipSuccess) {
         (void)hipGetLastError();
         free_ctx(c);
         return RT_E_NOMEM;
     }
-    if (hipMemsetAsync(c->d_src_ptr, 0, size_t(c->nblocks + 1) * sizeof(int32_t), c->stream) !=
-            hipSuccess ||
+    if (hipMemsetAsync(c->geo[0].d_src_ptr, 0, size_t(c->geo[0].nblocks + 1) * sizeof(int32_t),
+                       c->stream) != hipSuccess ||
+        hipMemsetAsync(c->geo[1].d_src_ptr, 0, size_t(c->geo[1].nblocks + 1) * sizeof(int32_t),
+                       c->stream) != hipSuccess ||
         hipMemsetAsync(c->d_acc, 0, ACC_SIZE * sizeof(double), c->stream) != hipSuccess) {
         free_ctx(c);
         return RT_E_HIP;
@@ -301,28 +319,31 @@ extern "C" int rt_sources_from_particles(rt_ctx *c, int64_t n, const double *pos
     return inject_host(c, m, ijk.data(), rate.data());
 }
 
-// Bin host sources into the per-tile lists (duplicate cells summed in input
-// order) and replace the context's source set.
-int rtk::inject_host(rt_ctx *c, int64_t n, const int32_t *ijk, const double *ndot)
+// Bin host sources into the per-tile lists of both tile sets (duplicate
+// cells summed in input order) and replace the context's source set.
+namespace {
+struct Lists {
+    std::vector<int32_t> ptr, key;
+    std::vector<float> rate;
+};
+
+Lists bin_sources(const rt_ctx *c, const TileSet &g, int64_t n, const int32_t *ijk,
+                  const double *ndot)
 {
     const rt_params &p = c->p;
+    const int nt = TX * g.ty;
     struct Src {
         int32_t tile, key;
         double ndot;
     };
     std::vector<Src> v;
     v.reserve(size_t(n));
-    double total = 0.0;
     for (int64_t s = 0; s < n; ++s) {
         const int32_t i = ijk[3 * s], j = ijk[3 * s + 1], k = ijk[3 * s + 2];
-        const double q = ndot[s];
-        if (i < 0 || i >= p.nx || j < 0 || j >= p.ny || k < 0 || k >= p.nz) return RT_E_ARG;
-        if (!(q >= 0.0) || !isfinite(q)) return RT_E_ARG;
-        const int itx = i / TX, ity = j / TY, izc = k / c->zc;
-        const int tile = (izc * c->nty + ity) * c->ntx + itx;
-        const int key = (k - izc * c->zc) * NTHREADS + (j - ity * TY) * TX + (i - itx * TX);
-        v.push_back({tile, key, q});
-        total += q;
+        const int itx = i / TX, ity = j / g.ty, izc = k / c->zc;
+        const int tile = (izc * g.nty + ity) * c->ntx + itx;
+        const int key = (k - izc * c->zc) * nt + (j - ity * g.ty) * TX + (i - itx * TX);
+        v.push_back({tile, key, ndot[s]});
     }
     // stable: duplicate cells are summed in input order, so the result does
     // not depend on the sort's tie-breaking
@@ -330,57 +351,88 @@ int rtk::inject_host(rt_ctx *c, int64_t n, const int32_t *ijk, const double *ndo
         return a.tile != b.tile ? a.tile < b.tile : a.key < b.key;
     });
     // merge duplicate cells (nearest-grid-point projection sums them)
-    std::vector<int32_t> key, ptr(size_t(c->nblocks) + 1, 0);
-    std::vector<float> rate;
+    Lists out;
+    out.ptr.assign(size_t(g.nblocks) + 1, 0);
     std::vector<double> acc;
     std::vector<int32_t> tiles;
     for (size_t s = 0; s < v.size(); ++s) {
-        if (!key.empty() && tiles.back() == v[s].tile && key.back() == v[s].key) {
+        if (!out.key.empty() && tiles.back() == v[s].tile && out.key.back() == v[s].key) {
             acc.back() += v[s].ndot;
         } else {
             tiles.push_back(v[s].tile);
-            key.push_back(v[s].key);
+            out.key.push_back(v[s].key);
             acc.push_back(v[s].ndot);
         }
     }
     const double vol = p.dx_cm * p.dx_cm * p.dx_cm;
-    rate.resize(acc.size());
-    for (size_t s = 0; s < acc.size(); ++s) rate[s] = float(acc[s] / vol);
-    for (size_t s = 0; s < tiles.size(); ++s) ptr[size_t(tiles[s]) + 1] += 1;
-    for (int b = 0; b < c->nblocks; ++b) ptr[size_t(b) + 1] += ptr[size_t(b)];
+    out.rate.resize(acc.size());
+    for (size_t s = 0; s < acc.size(); ++s) out.rate[s] = float(acc[s] / vol);
+    for (size_t s = 0; s < tiles.size(); ++s) out.ptr[size_t(tiles[s]) + 1] += 1;
+    for (int b = 0; b < g.nblocks; ++b) out.ptr[size_t(b) + 1] += out.ptr[size_t(b)];
+    return out;
+}
+}  // namespace
 
-    // allocate the new lists first so that a failure leaves the old set intact
-    const size_t m = std::max<size_t>(key.size(), 1);
-    int32_t *nkey = nullptr;
-    float *nrate = nullptr;
-    if (hipMalloc(&nkey, m * sizeof(int32_t)) != hipSuccess ||
-        hipMalloc(&nrate, m * sizeof(float)) != hipSuccess) {
-        (void)hipGetLastError();
-        if (nkey) (void)hipFree(nkey);
-        return RT_E_NOMEM;
+int rtk::inject_host(rt_ctx *c, int64_t n, const int32_t *ijk, const double *ndot)
+{
+    const rt_params &p = c->p;
+    double total = 0.0;
+    for (int64_t s = 0; s < n; ++s) {
+        const int32_t i = ijk[3 * s], j = ijk[3 * s + 1], k = ijk[3 * s + 2];
+        const double q = ndot[s];
+        if (i < 0 || i >= p.nx || j < 0 || j >= p.ny || k < 0 || k >= p.nz) return RT_E_ARG;
+        if (!(q >= 0.0) || !isfinite(q)) return RT_E_ARG;
+        total += q;
     }
-    if (!key.empty() &&
-        (hipMemcpy(nkey, key.data(), key.size() * sizeof(int32_t), hipMemcpyHostToDevice) !=
-             hipSuccess ||
-         hipMemcpy(nrate, rate.data(), rate.size() * sizeof(float), hipMemcpyHostToDevice) !=
-             hipSuccess)) {
-        (void)hipFree(nkey);
-        (void)hipFree(nrate);
-        return RT_E_HIP;
+    Lists L[2] = {bin_sources(c, c->geo[0], n, ijk, ndot), bin_sources(c, c->geo[1], n, ijk, ndot)};
+
+    // allocate and fill the new lists first so that a failure leaves the old
+    // set intact
+    int32_t *nkey[2] = {nullptr, nullptr};
+    float *nrate[2] = {nullptr, nullptr};
+    auto drop = [&]() {
+        for (int g = 0; g < 2; ++g) {
+            if (nkey[g]) (void)hipFree(nkey[g]);
+            if (nrate[g]) (void)hipFree(nrate[g]);
+        }
+    };
+    for (int g = 0; g < 2; ++g) {
+        const size_t m = std::max<size_t>(L[g].key.size(), 1);
+        if (hipMalloc(&nkey[g], m * sizeof(int32_t)) != hipSuccess ||
+            hipMalloc(&nrate[g], m * sizeof(float)) != hipSuccess) {
+            (void)hipGetLastError();
+            drop();
+            return RT_E_NOMEM;
+        }
+        if (!L[g].key.empty() &&
+            (hipMemcpy(nkey[g], L[g].key.data(), L[g].key.size() * sizeof(int32_t),
+                       hipMemcpyHostToDevice) != hipSuccess ||
+             hipMemcpy(nrate[g], L[g].rate.data(), L[g].rate.size() * sizeof(float),
+                       hipMemcpyHostToDevice) != hipSuccess)) {
+            drop();
+            return RT_E_HIP;
+        }
     }
     // the stream may still read the old lists
-    if (hipStreamSynchronize(c->stream) != hipSuccess ||
-        hipMemcpy(c->d_src_ptr, ptr.data(), ptr.size() * sizeof(int32_t),
-                  hipMemcpyHostToDevice) != hipSuccess) {
-        (void)hipFree(nkey);
-        (void)hipFree(nrate);
+    if (hipStreamSynchronize(c->stream) != hipSuccess) {
+        drop();
         return RT_E_HIP;
     }
-    if (c->d_src_key) (void)hipFree(c->d_src_key);
-    if (c->d_src_rate) (void)hipFree(c->d_src_rate);
-    c->d_src_key = nkey;
-    c->d_src_rate = nrate;
-    c->nsrc = int64_t(key.size());
+    for (int g = 0; g < 2; ++g) {
+        if (hipMemcpy(c->geo[g].d_src_ptr, L[g].ptr.data(), L[g].ptr.size() * sizeof(int32_t),
+                      hipMemcpyHostToDevice) != hipSuccess) {
+            drop();
+            return RT_E_HIP;
+        }
+    }
+    for (int g = 0; g < 2; ++g) {
+        TileSet &t = c->geo[g];
+        if (t.d_src_key) (void)hipFree(t.d_src_key);
+        if (t.d_src_rate) (void)hipFree(t.d_src_rate);
+        t.d_src_key = nkey[g];
+        t.d_src_rate = nrate[g];
+    }
+    c->nsrc = int64_t(L[0].key.size());
     c->ndot_total = total;
     return RT_OK;
 }
@@ -424,9 +476,11 @@ static void fill_args(const rt_ctx *c, double dt, int nsub, StepArgs &a)
     a.xHI = c->f.xHI;
     a.T = c->f.T;
     a.nH = c->f.nH;
-    a.src_ptr = c->d_src_ptr;
-    a.src_key = c->d_src_key;
-    a.src_rate = c->d_src_rate;
+    // the LF forms run on the TY_LF tiles, HLL and the surrogate on the TY ones
+    const TileSet &g = c->geo[(!c->surr && p.flux == RT_FLUX_LF) ? 0 : 1];
+    a.src_ptr = g.d_src_ptr;
+    a.src_key = g.d_src_key;
+    a.src_rate = g.d_src_rate;
     a.partials = c->d_part;
     a.sink = c->d_sink;
     a.nx = p.nx;
@@ -434,10 +488,10 @@ static void fill_args(const rt_ctx *c, double dt, int nsub, StepArgs &a)
     a.nz = p.nz;
     a.plane = uint32_t(p.nx) * uint32_t(p.ny);
     a.ntx = c->ntx;
-    a.nty = c->nty;
+    a.nty = g.nty;
     a.nzc = c->nzc;
     a.zc = c->zc;
-    a.nblocks = c->nblocks;
+    a.nblocks = g.nblocks;
     for (int f = 0; f < 6; ++f) a.bc[f] = p.bc[f];
     a.chem = p.chem;
     a.mixed = p.prec == RT_PREC_MIXED;
@@ -502,7 +556,7 @@ extern "C" int rt_step(rt_ctx *c, double dt, int32_t nsub)
         if (hipEventRecord(e->a, c->stream) != hipSuccess) return RT_E_HIP;
     }
     if (launch_step(a, c->stream) != hipSuccess) return RT_E_HIP;
-    int rows = c->nblocks;
+    int rows = a.nblocks;
     if (a.defer) {
         if (launch_defer_chem(a, c->nwords, c->nb2, c->stream) != hipSuccess) return RT_E_HIP;
         rows += c->nb2;

@@ -9,14 +9,23 @@
 
 namespace rtk {
 
-// Tile of the fused step kernel: one wavefront per x-row of 64 cells, TY
-// rows per block (64 TY threads), the block marching ZC planes along z.
+// Tiles of the fused step kernel: one wavefront per x-row of 64 cells, the
+// block marching ZC planes along z.  The plain LF forms use TY_LF rows per
+// block (64 TY_LF threads, at most 128 VGPRs each: more rows share each
+// halo row); the HLL and surrogate forms, which need more registers per
+// thread, use TY rows (64 TY threads).
 #ifndef RT_M1_TY
 #define RT_M1_TY 8
+#endif
+#ifndef RT_M1_TY_LF
+#define RT_M1_TY_LF 16
 #endif
 constexpr int TX = 64;
 constexpr int TY = RT_M1_TY;
 constexpr int NTHREADS = TX * TY;
+constexpr int TY_LF = RT_M1_TY_LF;
+constexpr int NTHREADS_LF = TX * TY_LF;
+constexpr int NTHREADS_MAX = NTHREADS > NTHREADS_LF ? NTHREADS : NTHREADS_LF;
 constexpr int SRC_LDS = 256;   // sources staged in LDS per refill
 
 // Per-block partial sums written by the step kernel (all FP64).
@@ -54,14 +63,13 @@ struct StepArgs {
     float *xHI, *T;                  // in place
     const float *nH;
     const int32_t *src_ptr;          // per block [start, end) into src_key/rate
-    const int32_t *src_key;          // (z - z0) * NTHREADS + thread index
+    const int32_t *src_key;          // (z - z0) * threads per block + thread index
     const float *src_rate;           // S = ndot / dx^3 [cm^-3 s^-1]
     double *partials;                // nblocks * NRED
-    float *sink;                     // 3 NTHREADS floats: stores of lanes off the grid
-                                     // (NTHREADS floats, then NTHREADS 64-bit words)
+    float *sink;                     // NTHREADS_MAX floats: stores of lanes off the grid
     int nx, ny, nz;
     uint32_t plane;                  // nx * ny
-    int ntx, nty, nzc, zc, nblocks;
+    int ntx, nty, nzc, zc, nblocks;  // of the tiles of the form that runs
     int bc[6];
     int chem, mixed, adaptive, nsub, any_outflow;
     int hll;                         // 1: HLL fluxes, 0: LF

@@ -99,16 +99,23 @@ __device__ __forceinline__ Cell4 load4(const StepArgs &A, uint32_t i, float sx, 
 }
 
 // ------------------------------------------------------ fused step kernel
-// One 512-thread block per CU (up to 256 VGPRs): measured faster at 1024^3
-// than two blocks at 128 VGPRs, where the FP64 chemistry of the mixed form
-// spills.
+// One block per CU.  The LF forms: 1024 threads (64 x 16 tile) at up to 128
+// VGPRs, four wavefronts per SIMD (their FP64 chemistry runs in a second
+// kernel); the HLL and surrogate forms: 512 threads (64 x 8) at up to 256.
 #ifndef RT_M1_MINW
 #define RT_M1_MINW 2
 #endif
+#ifndef RT_M1_MINW_LF
+#define RT_M1_MINW_LF 4
+#endif
 
 template <bool MIXED, bool SURR, bool HLL>
-__global__ __launch_bounds__(NTHREADS, SURR ? 2 : RT_M1_MINW) void m1_step_kernel(StepArgs A)
+__global__ __launch_bounds__((SURR || HLL) ? NTHREADS : NTHREADS_LF,
+                             SURR ? 2 : (HLL ? RT_M1_MINW : RT_M1_MINW_LF))
+void m1_step_kernel(StepArgs A)
 {
+    constexpr int KTY = (SURR || HLL) ? TY : TY_LF;   // tile rows of this form
+    constexpr int KNT = TX * KTY;                     // its threads per block
     // The LF mixed form leaves its FP64 cells to a second, small kernel
     // (launch_defer_chem): the few waves that would take the FP64 branch
     // here cost every wave registers and scheduling freedom.
@@ -116,22 +123,22 @@ __global__ __launch_bounds__(NTHREADS, SURR ? 2 : RT_M1_MINW) void m1_step_kerne
     constexpr int SW = TX + 2;
     __shared__ __attribute__((aligned(16))) __bf16 s_pk[SURR ? PK_FWD * 8 : 8];
     __shared__ float s_bias[SURR ? SURR_NBIAS : 1];
-    __shared__ float sN[TY + 2][SW], sFx[TY + 2][SW], sFy[TY + 2][SW], sFz[TY + 2][SW];
-    __shared__ float sPxx[TY + 2][SW], sPyy[TY + 2][SW], sPxy[TY + 2][SW];
-    __shared__ float sPxz[TY + 2][SW], sPyz[TY + 2][SW];
+    __shared__ float sN[KTY + 2][SW], sFx[KTY + 2][SW], sFy[KTY + 2][SW], sFz[KTY + 2][SW];
+    __shared__ float sPxx[KTY + 2][SW], sPyy[KTY + 2][SW], sPxy[KTY + 2][SW];
+    __shared__ float sPxz[KTY + 2][SW], sPyz[KTY + 2][SW];
     // HLL: x and y signal speeds of the tile and its halo
-    constexpr int HY = HLL ? TY + 2 : 1, HX = HLL ? SW : 1;
+    constexpr int HY = HLL ? KTY + 2 : 1, HX = HLL ? SW : 1;
     __shared__ float sLxm[HY][HX], sLxp[HY][HX], sLym[HY][HX], sLyp[HY][HX];
-    __shared__ double sred[NTHREADS / 64][NRED];
+    __shared__ double sred[KNT / 64][NRED];
 
     const int tid = threadIdx.x;
     const int lx = tid & (TX - 1), ly = tid / TX;
     if (SURR) {
         // network operands to LDS (read by every plane; the first barrier of
         // the z loop orders these stores before any use)
-        for (int i = tid; i < PK_FWD; i += NTHREADS)
+        for (int i = tid; i < PK_FWD; i += KNT)
             reinterpret_cast<uint4 *>(s_pk)[i] = reinterpret_cast<const uint4 *>(A.surr_pk)[i];
-        for (int i = tid; i < SURR_NBIAS; i += NTHREADS) s_bias[i] = A.surr_bias[i];
+        for (int i = tid; i < SURR_NBIAS; i += KNT) s_bias[i] = A.surr_bias[i];
     }
 
     // XCD-aware renumbering: blockIdx mod 8 selects the XCD; each XCD takes
@@ -149,7 +156,7 @@ __global__ __launch_bounds__(NTHREADS, SURR ? 2 : RT_M1_MINW) void m1_step_kerne
     const int ity = rest % A.nty;
     const int izc = rest / A.nty;
     const int tile_id = tile;   // source-list index
-    const int x0 = itx * TX, y0 = ity * TY;
+    const int x0 = itx * TX, y0 = ity * KTY;
     const int z0 = izc * A.zc;
     const int z1 = min(z0 + A.zc, A.nz);
     const int gx = x0 + lx, gy = y0 + ly;
@@ -161,21 +168,21 @@ __global__ __launch_bounds__(NTHREADS, SURR ? 2 : RT_M1_MINW) void m1_step_kerne
     const Map1 my = map_coord(gy, A.ny, A.bc[2], A.bc[3]);
     const uint32_t col = uint32_t(my.idx) * uint32_t(A.nx) + uint32_t(mx.idx);
 
-    // halo slot of this thread: rows y0-1 and y0+TY, columns x0-1 and x0+TX
+    // halo slot of this thread: rows y0-1 and y0+KTY, columns x0-1 and x0+TX
     int hsx = 0, hsy = 0;
-    const bool has_halo = tid < 2 * TX + 2 * TY;
+    const bool has_halo = tid < 2 * TX + 2 * KTY;
     if (tid < TX) {
         hsy = 0;
         hsx = tid + 1;
     } else if (tid < 2 * TX) {
-        hsy = TY + 1;
+        hsy = KTY + 1;
         hsx = tid - TX + 1;
-    } else if (tid < 2 * TX + TY) {
+    } else if (tid < 2 * TX + KTY) {
         hsx = 0;
         hsy = tid - 2 * TX + 1;
     } else {
         hsx = TX + 1;
-        hsy = tid - 2 * TX - TY + 1;
+        hsy = tid - 2 * TX - KTY + 1;
     }
     const Map1 hx = map_coord(x0 + hsx - 1, A.nx, A.bc[0], A.bc[1]);
     const Map1 hy = map_coord(y0 + hsy - 1, A.ny, A.bc[2], A.bc[3]);
@@ -190,7 +197,7 @@ __global__ __launch_bounds__(NTHREADS, SURR ? 2 : RT_M1_MINW) void m1_step_kerne
     const int sp_end = A.src_ptr[tile_id + 1];
     int buf_base = sp;
     int buf_n = min(SRC_LDS, sp_end - sp);
-    for (int i = tid; i < buf_n; i += NTHREADS) {
+    for (int i = tid; i < buf_n; i += KNT) {
         s_skey[i] = A.src_key[buf_base + i];
         s_srate[i] = A.src_rate[buf_base + i];
     }
@@ -200,7 +207,7 @@ __global__ __launch_bounds__(NTHREADS, SURR ? 2 : RT_M1_MINW) void m1_step_kerne
     // the step); escaped and floor photons, which are zero almost
     // everywhere, are reduced across the wavefront only on planes where
     // they occur and kept per wavefront in LDS.
-    __shared__ double s_acc[NTHREADS / 64][8];
+    __shared__ double s_acc[KNT / 64][8];
     const int wave = tid >> 6;
     if (lx < 8) s_acc[wave][lx] = 0.0;
     double acc_xhi = 0.0, acc_nhxhi = 0.0, acc_N = 0.0, acc_abs = 0.0;
@@ -408,15 +415,15 @@ __global__ __launch_bounds__(NTHREADS, SURR ? 2 : RT_M1_MINW) void m1_step_kerne
                 __syncthreads();
                 buf_base = sp;
                 buf_n = min(SRC_LDS, sp_end - sp);
-                for (int i = tid; i < buf_n; i += NTHREADS) {
+                for (int i = tid; i < buf_n; i += KNT) {
                     s_skey[i] = A.src_key[buf_base + i];
                     s_srate[i] = A.src_rate[buf_base + i];
                 }
                 __syncthreads();
             }
             const int key = s_skey[sp - buf_base];
-            if (key / NTHREADS != zl) break;
-            if (key - zl * NTHREADS == tid) S += s_srate[sp - buf_base];
+            if (key / KNT != zl) break;
+            if (key - zl * KNT == tid) S += s_srate[sp - buf_base];
             ++sp;
         }
 
@@ -706,7 +713,7 @@ __global__ __launch_bounds__(NTHREADS, SURR ? 2 : RT_M1_MINW) void m1_step_kerne
         double s = 0.0;
         if (tid < R_HIST0) {
 #pragma unroll
-            for (int w = 0; w < NTHREADS / 64; ++w) s += sred[w][tid];
+            for (int w = 0; w < KNT / 64; ++w) s += sred[w][tid];
         } else {
             s = double(shist[tid - R_HIST0]);
         }
@@ -962,7 +969,7 @@ int state_sums_blocks(uint32_t ncell)
 
 hipError_t launch_step(const StepArgs &a, hipStream_t s)
 {
-    const dim3 g(a.nblocks), b(NTHREADS);
+    const dim3 g(a.nblocks), b((a.surr || a.hll) ? NTHREADS : NTHREADS_LF);
     // the learned chemistry runs with the LF flux only (rejected on the host)
     if (a.surr) {
         if (a.mixed)

@@ -26,6 +26,7 @@ constexpr int MAX_NSUB = 4096;
 #define RT_M1_ZC 64
 #endif
 constexpr int ZC_DEFAULT = RT_M1_ZC;  // planes per block along z
+constexpr int BIG_MIN_BLOCKS = 1024;   // 64 x TY_LF tiles from this many on
 // the step keeps one FP64-cell mask word per plane of its chunk in a lane
 static_assert(ZC_DEFAULT <= TX, "z chunks longer than a wavefront");
 constexpr double SIGMA_T = 6.6524587321e-25;  // Thomson cross-section [cm^2]
@@ -476,8 +477,12 @@ static void fill_args(const rt_ctx *c, double dt, int nsub, StepArgs &a)
     a.xHI = c->f.xHI;
     a.T = c->f.T;
     a.nH = c->f.nH;
-    // the LF forms run on the TY_LF tiles, HLL and the surrogate on the TY ones
-    const TileSet &g = c->geo[(!c->surr && p.flux == RT_FLUX_LF) ? 0 : 1];
+    // the LF forms run on the TY_LF tiles when there are enough of them to
+    // fill the chip (four per compute unit), else, like HLL and the
+    // surrogate, on the TY ones
+    const bool big = !c->surr && p.flux == RT_FLUX_LF && c->geo[0].nblocks >= BIG_MIN_BLOCKS;
+    const TileSet &g = c->geo[big ? 0 : 1];
+    a.big = big ? 1 : 0;
     a.src_ptr = g.d_src_ptr;
     a.src_key = g.d_src_key;
     a.src_rate = g.d_src_rate;

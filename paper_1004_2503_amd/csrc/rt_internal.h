@@ -10,10 +10,11 @@
 namespace rtk {
 
 // Tiles of the fused step kernel: one wavefront per x-row of 64 cells, the
-// block marching ZC planes along z.  The plain LF forms use TY_LF rows per
-// block (64 TY_LF threads, at most 128 VGPRs each: more rows share each
-// halo row); the HLL and surrogate forms, which need more registers per
-// thread, use TY rows (64 TY threads).
+// block marching ZC planes along z.  On large grids the plain LF forms use
+// TY_LF rows per block (64 TY_LF threads, at most 128 VGPRs each: more rows
+// share each halo row); small grids (too few such tiles to fill the chip)
+// and the HLL and surrogate forms, which need more registers per thread,
+// use TY rows (64 TY threads).
 #ifndef RT_M1_TY
 #define RT_M1_TY 8
 #endif
@@ -73,6 +74,7 @@ struct StepArgs {
     int bc[6];
     int chem, mixed, adaptive, nsub, any_outflow;
     int hll;                         // 1: HLL fluxes, 0: LF
+    int big;                         // 1: 64 x TY_LF tiles (LF forms, large grids)
     // mixed precision with LF fluxes and the exact chemistry: cells whose
     // chemistry runs in FP64 are marked in fp64_mask (one bit per cell, one
     // 64-bit word per x-row of a tile: word (z * ny + y) * ntx + tile x) and

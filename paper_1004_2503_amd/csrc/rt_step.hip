@@ -99,9 +99,10 @@ __device__ __forceinline__ Cell4 load4(const StepArgs &A, uint32_t i, float sx, 
 }
 
 // ------------------------------------------------------ fused step kernel
-// One block per CU.  The LF forms: 1024 threads (64 x 16 tile) at up to 128
-// VGPRs, four wavefronts per SIMD (their FP64 chemistry runs in a second
-// kernel); the HLL and surrogate forms: 512 threads (64 x 8) at up to 256.
+// One block per CU.  On large grids the LF forms take 64 x 16 tiles (BIG):
+// 1024 threads at up to 128 VGPRs, four wavefronts per SIMD (their FP64
+// chemistry runs in a second kernel).  Otherwise, and for the HLL and
+// surrogate forms, 64 x 8 tiles: 512 threads at up to 256 VGPRs.
 #ifndef RT_M1_MINW
 #define RT_M1_MINW 2
 #endif
@@ -109,13 +110,14 @@ __device__ __forceinline__ Cell4 load4(const StepArgs &A, uint32_t i, float sx, 
 #define RT_M1_MINW_LF 4
 #endif
 
-template <bool MIXED, bool SURR, bool HLL>
-__global__ __launch_bounds__((SURR || HLL) ? NTHREADS : NTHREADS_LF,
-                             SURR ? 2 : (HLL ? RT_M1_MINW : RT_M1_MINW_LF))
+template <bool MIXED, bool SURR, bool HLL, bool BIG>
+__global__ __launch_bounds__(BIG ? NTHREADS_LF : NTHREADS,
+                             BIG ? RT_M1_MINW_LF : (SURR ? 2 : RT_M1_MINW))
 void m1_step_kernel(StepArgs A)
 {
-    constexpr int KTY = (SURR || HLL) ? TY : TY_LF;   // tile rows of this form
-    constexpr int KNT = TX * KTY;                     // its threads per block
+    static_assert(!BIG || (!SURR && !HLL), "64 x 16 tiles: LF forms only");
+    constexpr int KTY = BIG ? TY_LF : TY;   // tile rows of this form
+    constexpr int KNT = TX * KTY;           // its threads per block
     // The LF mixed form leaves its FP64 cells to a second, small kernel
     // (launch_defer_chem): the few waves that would take the FP64 branch
     // here cost every wave registers and scheduling freedom.
@@ -969,23 +971,28 @@ int state_sums_blocks(uint32_t ncell)
 
 hipError_t launch_step(const StepArgs &a, hipStream_t s)
 {
-    const dim3 g(a.nblocks), b((a.surr || a.hll) ? NTHREADS : NTHREADS_LF);
+    const dim3 g(a.nblocks), b(a.big ? NTHREADS_LF : NTHREADS);
     // the learned chemistry runs with the LF flux only (rejected on the host)
     if (a.surr) {
         if (a.mixed)
-            hipLaunchKernelGGL((m1_step_kernel<true, true, false>), g, b, 0, s, a);
+            hipLaunchKernelGGL((m1_step_kernel<true, true, false, false>), g, b, 0, s, a);
         else
-            hipLaunchKernelGGL((m1_step_kernel<false, true, false>), g, b, 0, s, a);
+            hipLaunchKernelGGL((m1_step_kernel<false, true, false, false>), g, b, 0, s, a);
     } else if (a.hll) {
         if (a.mixed)
-            hipLaunchKernelGGL((m1_step_kernel<true, false, true>), g, b, 0, s, a);
+            hipLaunchKernelGGL((m1_step_kernel<true, false, true, false>), g, b, 0, s, a);
         else
-            hipLaunchKernelGGL((m1_step_kernel<false, false, true>), g, b, 0, s, a);
+            hipLaunchKernelGGL((m1_step_kernel<false, false, true, false>), g, b, 0, s, a);
+    } else if (a.big) {
+        if (a.mixed)
+            hipLaunchKernelGGL((m1_step_kernel<true, false, false, true>), g, b, 0, s, a);
+        else
+            hipLaunchKernelGGL((m1_step_kernel<false, false, false, true>), g, b, 0, s, a);
     } else {
         if (a.mixed)
-            hipLaunchKernelGGL((m1_step_kernel<true, false, false>), g, b, 0, s, a);
+            hipLaunchKernelGGL((m1_step_kernel<true, false, false, false>), g, b, 0, s, a);
         else
-            hipLaunchKernelGGL((m1_step_kernel<false, false, false>), g, b, 0, s, a);
+            hipLaunchKernelGGL((m1_step_kernel<false, false, false, false>), g, b, 0, s, a);
     }
     return hipGetLastError();
 }

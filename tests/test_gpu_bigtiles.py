@@ -1,0 +1,88 @@
+"""The 64 x 16 tiles that the LF forms take on large grids (at least 1024 such
+tiles): one mixed step on a grid ragged in every direction, with sources at
+its corners, checked against the oracle on sampled 32^3 sub-blocks (corners,
+edges, around sources, random) and by its photon budget; and the FP32 form
+the same way.  Smaller grids, HLL and the surrogate use 64 x 8 tiles, which
+the other GPU tests cover."""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1004_2503_amd import rt
+
+from parity_util import assert_parity, errors
+
+pytestmark = pytest.mark.gpu
+
+SHAPE = (130, 1000, 1030)     # 17 x 63 x 3 = 3213 tiles of 64 x 16 x 64
+DX = 3.0e21
+B = 32
+
+
+def _block(t, o, halo):
+    idx = [torch.arange(c - halo, c + B + halo, device=t.device) % n for c, n in zip(o, SHAPE)]
+    return t.index_select(0, idx[0]).index_select(1, idx[1]).index_select(2, idx[2]) \
+        .double().cpu().numpy()
+
+
+@pytest.mark.parametrize("prec", [rt.PREC_MIXED, rt.PREC_FP32])
+def test_big_tiles_match_oracle(prec):
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(16 + prec)
+    mk = lambda: torch.empty(SHAPE, dtype=torch.float32, device="cuda")
+    N, xHI, T, nH = mk(), mk(), mk(), mk()
+    N.uniform_(0.0, 1.0, generator=gen).pow_(3).mul_(1e-3)
+    F = []
+    for _ in range(3):
+        F.append(mk().uniform_(-1.0, 1.0, generator=gen).mul_(N).mul_(0.5 * rt.C_LIGHT / 3 ** 0.5))
+    xHI.uniform_(-6.0, 0.0, generator=gen).mul_(np.log(10.0)).exp_()
+    T.uniform_(2.0, 4.7, generator=gen).mul_(np.log(10.0)).exp_()
+    nH.uniform_(-5.0, -1.0, generator=gen).mul_(np.log(10.0)).exp_()
+    st = dict(N=N, Fx=F[0], Fy=F[1], Fz=F[2], xHI=xHI, T=T, nH=nH)
+    G = rt.RTGrid(rt.make_params(SHAPE, DX, prec=prec), st)
+    nz, ny, nx = SHAPE
+    ijk = np.array([[nx - 1, ny - 1, nz - 1], [0, 0, 0], [nx - 3, 5, nz - 2], [500, 600, 70]],
+                   np.int32)
+    ndot = np.array([3e52, 1e51, 2e52, 5e51])
+    G.inject_sources(ijk, ndot)
+    pre = G.tensors()
+    rng = np.random.default_rng(3)
+    origins = [(nz - B, ny - B, nx - B), (0, 0, 0), (nz - B, 0, nx - B), (0, ny - B, 0),
+               (nz - 20, 10, nx - 40), (60, 580, 480)]
+    origins += [tuple(int(rng.integers(0, m - B + 1)) for m in SHAPE) for _ in range(6)]
+    inputs = {o: dict(N=_block(pre["N"], o, 1), F=[_block(pre[k], o, 1) for k in ("Fx", "Fy", "Fz")],
+                      xHI=_block(pre["xHI"], o, 0), T=_block(pre["T"], o, 0),
+                      nH=_block(pre["nH"], o, 0)) for o in origins}
+    dt = DX / (3 * rt.C_LIGHT)
+    G.step(dt, 2)
+    red = G.reduce()
+    post = G.tensors()
+    lhs = red["photons_initial"] + red["photons_emitted"] + red["photons_floor"]
+    rhs = red["photons_stored"] + red["photons_absorbed"] + red["photons_escaped"]
+    assert rhs == pytest.approx(lhs, rel=1e-5)
+    assert red["n_nonfinite"] == 0
+    if prec == rt.PREC_MIXED:
+        assert red["n_fp64"] > 0
+    p = oracle.make_params((B, B, B), DX, chem=oracle.CHEM_FULL)
+    vol = DX ** 3
+    worst = dict(N=0.0, F=0.0, xHI=0.0, T=0.0)
+    for o in origins:
+        z0, y0, x0 = o
+        S = np.zeros((B, B, B))
+        for (i, j, k), q in zip(ijk, ndot):
+            if z0 <= k < z0 + B and y0 <= j < y0 + B and x0 <= i < x0 + B:
+                S[k - z0, j - y0, i - x0] += q / vol
+        d = inputs[o]
+        res = oracle.step_subblock(p, dt, 2, d["N"], d["F"], d["xHI"], d["T"], d["nH"], S)
+        ref = dict(N=res[0], Fx=res[1], Fy=res[2], Fz=res[3], xHI=res[4], T=res[5])
+        got = {k: _block(post[k], o, 0) for k in ("N", "Fx", "Fy", "Fz", "xHI", "T")}
+        e = errors(got, ref)
+        for k in worst:
+            worst[k] = max(worst[k], e[k])
+        assert_parity(e, what=f"block at {o}")
+    print(f"64x16 tiles, prec={prec}: {len(origins)} blocks, worst errors {worst}", flush=True)
+    G.close()
+    del N, F, xHI, T, nH, st, pre, post
+    torch.cuda.empty_cache()

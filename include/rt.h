@@ -206,7 +206,9 @@ int rt_sources_from_particles(rt_ctx *ctx, int64_t n, const double *pos,
  * mode) or at most nsub (adaptive mode) -- and the global sums, all in one
  * fused kernel followed by a one-block finalisation.  dt must satisfy
  * dt <= dx/(3c) (the CFL bound of Sec. 2.2 for the 3-D unsplit update;
- * RT_E_CFL otherwise); 1 <= nsub <= 4096.  Asynchronous. */
+ * RT_E_CFL otherwise); 1 <= nsub <= 4096.  Asynchronous, except that the
+ * first step after the learned chemistry is switched on or off may first
+ * rebin the point sources for its tiling (waiting for the stream once). */
 int rt_step(rt_ctx *ctx, double dt, int32_t nsub);
 
 /* Switch the learned chemistry on (theta != NULL) or off (theta == NULL).

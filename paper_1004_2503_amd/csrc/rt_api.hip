@@ -54,6 +54,11 @@ struct rt_ctx {
     int ntx = 0, nzc = 0, zc = 0;
     uint32_t ncell = 0;
     TileSet geo[2];   // 0: LF forms (TY_LF rows), 1: HLL and surrogate forms (TY rows)
+    // the current source set on the host; each tile set's lists are built
+    // when a step first needs them
+    std::vector<int32_t> src_ijk;
+    std::vector<double> src_ndot;
+    bool geo_ready[2] = {true, true};   // the empty set at rt_init
     int64_t nsrc = 0;
     double ndot_total = 0.0;
     double *d_part = nullptr;
@@ -374,6 +379,56 @@ Lists bin_sources(const rt_ctx *c, const TileSet &g, int64_t n, const int32_t *i
 }
 }  // namespace
 
+// Which tile set the next step uses: the LF forms take the 64 x TY_LF
+// tiles when there are enough of them to fill the chip (four per compute
+// unit); small grids, HLL and the surrogate take the 64 x TY ones.
+static int tile_set(const rt_ctx *c)
+{
+    const bool lf = !c->surr && c->p.flux == RT_FLUX_LF;
+    return (lf && c->geo[0].nblocks >= BIG_MIN_BLOCKS) ? 0 : 1;
+}
+
+// Build tile set g's lists from the host copy of the sources.  New lists are
+// allocated and filled first, so that a failure leaves the old ones intact.
+static int build_lists(rt_ctx *c, int g)
+{
+    const int64_t n = int64_t(c->src_ndot.size());
+    const Lists L = bin_sources(c, c->geo[g], n, c->src_ijk.data(), c->src_ndot.data());
+    const size_t m = std::max<size_t>(L.key.size(), 1);
+    int32_t *nkey = nullptr;
+    float *nrate = nullptr;
+    if (hipMalloc(&nkey, m * sizeof(int32_t)) != hipSuccess ||
+        hipMalloc(&nrate, m * sizeof(float)) != hipSuccess) {
+        (void)hipGetLastError();
+        if (nkey) (void)hipFree(nkey);
+        return RT_E_NOMEM;
+    }
+    if (!L.key.empty() &&
+        (hipMemcpy(nkey, L.key.data(), L.key.size() * sizeof(int32_t), hipMemcpyHostToDevice) !=
+             hipSuccess ||
+         hipMemcpy(nrate, L.rate.data(), L.rate.size() * sizeof(float), hipMemcpyHostToDevice) !=
+             hipSuccess)) {
+        (void)hipFree(nkey);
+        (void)hipFree(nrate);
+        return RT_E_HIP;
+    }
+    // the stream may still read the old lists
+    TileSet &t = c->geo[g];
+    if (hipStreamSynchronize(c->stream) != hipSuccess ||
+        hipMemcpy(t.d_src_ptr, L.ptr.data(), L.ptr.size() * sizeof(int32_t),
+                  hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(nkey);
+        (void)hipFree(nrate);
+        return RT_E_HIP;
+    }
+    if (t.d_src_key) (void)hipFree(t.d_src_key);
+    if (t.d_src_rate) (void)hipFree(t.d_src_rate);
+    t.d_src_key = nkey;
+    t.d_src_rate = nrate;
+    c->geo_ready[g] = true;
+    return RT_OK;
+}
+
 int rtk::inject_host(rt_ctx *c, int64_t n, const int32_t *ijk, const double *ndot)
 {
     const rt_params &p = c->p;
@@ -385,55 +440,22 @@ int rtk::inject_host(rt_ctx *c, int64_t n, const int32_t *ijk, const double *ndo
         if (!(q >= 0.0) || !isfinite(q)) return RT_E_ARG;
         total += q;
     }
-    Lists L[2] = {bin_sources(c, c->geo[0], n, ijk, ndot), bin_sources(c, c->geo[1], n, ijk, ndot)};
-
-    // allocate and fill the new lists first so that a failure leaves the old
-    // set intact
-    int32_t *nkey[2] = {nullptr, nullptr};
-    float *nrate[2] = {nullptr, nullptr};
-    auto drop = [&]() {
-        for (int g = 0; g < 2; ++g) {
-            if (nkey[g]) (void)hipFree(nkey[g]);
-            if (nrate[g]) (void)hipFree(nrate[g]);
-        }
-    };
-    for (int g = 0; g < 2; ++g) {
-        const size_t m = std::max<size_t>(L[g].key.size(), 1);
-        if (hipMalloc(&nkey[g], m * sizeof(int32_t)) != hipSuccess ||
-            hipMalloc(&nrate[g], m * sizeof(float)) != hipSuccess) {
-            (void)hipGetLastError();
-            drop();
-            return RT_E_NOMEM;
-        }
-        if (!L[g].key.empty() &&
-            (hipMemcpy(nkey[g], L[g].key.data(), L[g].key.size() * sizeof(int32_t),
-                       hipMemcpyHostToDevice) != hipSuccess ||
-             hipMemcpy(nrate[g], L[g].rate.data(), L[g].rate.size() * sizeof(float),
-                       hipMemcpyHostToDevice) != hipSuccess)) {
-            drop();
-            return RT_E_HIP;
-        }
+    std::vector<int32_t> old_ijk;
+    std::vector<double> old_ndot;
+    old_ijk.swap(c->src_ijk);
+    old_ndot.swap(c->src_ndot);
+    c->src_ijk.assign(ijk, ijk + 3 * n);
+    c->src_ndot.assign(ndot, ndot + n);
+    // the set the next step uses now, the other one when first needed
+    const int g = tile_set(c);
+    const int rc = build_lists(c, g);
+    if (rc != RT_OK) {
+        c->src_ijk.swap(old_ijk);   // the old set stays, lists and all
+        c->src_ndot.swap(old_ndot);
+        return rc;
     }
-    // the stream may still read the old lists
-    if (hipStreamSynchronize(c->stream) != hipSuccess) {
-        drop();
-        return RT_E_HIP;
-    }
-    for (int g = 0; g < 2; ++g) {
-        if (hipMemcpy(c->geo[g].d_src_ptr, L[g].ptr.data(), L[g].ptr.size() * sizeof(int32_t),
-                      hipMemcpyHostToDevice) != hipSuccess) {
-            drop();
-            return RT_E_HIP;
-        }
-    }
-    for (int g = 0; g < 2; ++g) {
-        TileSet &t = c->geo[g];
-        if (t.d_src_key) (void)hipFree(t.d_src_key);
-        if (t.d_src_rate) (void)hipFree(t.d_src_rate);
-        t.d_src_key = nkey[g];
-        t.d_src_rate = nrate[g];
-    }
-    c->nsrc = int64_t(L[0].key.size());
+    c->geo_ready[1 - g] = false;
+    c->nsrc = int64_t(c->src_ndot.size());
     c->ndot_total = total;
     return RT_OK;
 }
@@ -477,12 +499,9 @@ static void fill_args(const rt_ctx *c, double dt, int nsub, StepArgs &a)
     a.xHI = c->f.xHI;
     a.T = c->f.T;
     a.nH = c->f.nH;
-    // the LF forms run on the TY_LF tiles when there are enough of them to
-    // fill the chip (four per compute unit), else, like HLL and the
-    // surrogate, on the TY ones
-    const bool big = !c->surr && p.flux == RT_FLUX_LF && c->geo[0].nblocks >= BIG_MIN_BLOCKS;
-    const TileSet &g = c->geo[big ? 0 : 1];
-    a.big = big ? 1 : 0;
+    const int gi = tile_set(c);
+    const TileSet &g = c->geo[gi];
+    a.big = gi == 0 ? 1 : 0;
     a.src_ptr = g.d_src_ptr;
     a.src_key = g.d_src_key;
     a.src_rate = g.d_src_rate;
@@ -547,6 +566,10 @@ extern "C" int rt_step(rt_ctx *c, double dt, int32_t nsub)
     const double dtmax = c->p.dx_cm / (3.0 * c->p.c_cms);
     if (dt > dtmax * (1.0 + 1e-12)) return RT_E_CFL;
 
+    if (!c->geo_ready[tile_set(c)]) {
+        const int rc = build_lists(c, tile_set(c));
+        if (rc != RT_OK) return rc;
+    }
     StepArgs a;
     fill_args(c, dt, nsub, a);
     Ev *e = nullptr;

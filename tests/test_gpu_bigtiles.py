@@ -86,3 +86,39 @@ def test_big_tiles_match_oracle(prec):
     G.close()
     del N, F, xHI, T, nH, st, pre, post
     torch.cuda.empty_cache()
+
+
+def test_source_lists_follow_the_tiling():
+    # On a large grid the LF step uses the 64 x 16 tiles; switching the
+    # learned chemistry on moves the next step to the 64 x 8 tiles, whose
+    # source lists are then built from the same sources.  With the chemistry
+    # off both steps do the same transport and injection.
+    shape = (64, 1000, 1030)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(7)
+    N = torch.empty(shape, dtype=torch.float32, device="cuda").uniform_(0.0, 1e-3, generator=gen)
+    st = dict(N=N, xHI=torch.ones_like(N), T=torch.full_like(N, 1e4),
+              nH=torch.full_like(N, 1e-3))
+    nz, ny, nx = shape
+    rng = np.random.default_rng(11)
+    ijk = np.stack([rng.integers(0, nx, 300), rng.integers(0, ny, 300),
+                    rng.integers(0, nz, 300)], axis=1).astype(np.int32)
+    ijk[:4] = [[nx - 1, ny - 1, nz - 1], [0, 0, 0], [nx - 1, 0, nz - 1], [0, ny - 1, 0]]
+    ndot = 10 ** rng.uniform(50, 53, 300)
+    theta = torch.zeros(rt.MLP_NPARAM, dtype=torch.float32, device="cuda")
+    norm = [0.0] * 5 + [1.0] * 5 + [0.0, 0.0, 1.0, 1.0] + [-40.0] * 5 + [40.0] * 5
+    out = []
+    for surr in (False, True):
+        G = rt.RTGrid(rt.make_params(shape, DX, chem=rt.CHEM_OFF), st)
+        G.inject_sources(ijk, ndot)
+        if surr:
+            rt.check(rt.rt_set_surrogate(G.ctx, theta, norm, 1e-2), "rt_set_surrogate")
+        G.step(DX / (3 * rt.C_LIGHT), 1)
+        red = G.reduce()
+        out.append((G.tensors()["N"].double().cpu().numpy(), red["photons_emitted"]))
+        G.close()
+    assert out[0][1] == out[1][1]
+    d = np.abs(out[0][0] - out[1][0])
+    assert float(d.max()) <= 1e-6 * float(np.abs(out[0][0]).max())
+    del N, st
+    torch.cuda.empty_cache()

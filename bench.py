@@ -495,7 +495,8 @@ def main():
     traffic = measured_traffic(w.name, args.nsub, args.prec, args.flux)
     roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-            "kernel": "m1_step_kernel", "avg_launch_ms": avg_ms,
+            "kernel": "m1_step_kernel (+ defer_chem_kernel in the mixed LF form)",
+            "avg_launch_ms": avg_ms,
             "bytes_per_cell": BYTES_PER_CELL}
 
     diag = diagnostics_leg(G, w)

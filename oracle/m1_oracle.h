@@ -22,7 +22,7 @@
  *     then the per-cell operator Phi that applies chemistry, temperature and
  *     absorption to the transported state.
  *
- * Readings where the paper is silent or garbled (documented in the design doc):
+ * Readings where the paper is silent or garbled:
  *   closure chi(f) = Levermore form; D = (1-chi)/2 I + (3chi-1)/2 n(x)n
  *   (the printed coefficients are swapped); LF dissipation speed c; case-B
  *   rates of Hui & Gnedin (1997) and Cen (1992); photon-conserving implicit

@@ -25,10 +25,21 @@ constexpr int MAX_NSUB = 4096;
 #ifndef RT_M1_ZC
 #define RT_M1_ZC 64
 #endif
-constexpr int ZC_DEFAULT = RT_M1_ZC;  // planes per block along z
+#ifndef RT_M1_ZC_MIN
+#define RT_M1_ZC_MIN 16
+#endif
+#ifndef RT_M1_ZC_BLOCKS
+#define RT_M1_ZC_BLOCKS 2048
+#endif
+constexpr int ZC_DEFAULT = RT_M1_ZC;  // planes per block along z (the longest chunk)
+constexpr int ZC_MIN = RT_M1_ZC_MIN;  // shortest chunk the grid size may ask for
+// chunks are halved (down to ZC_MIN) while a grid has fewer 64 x TY tiles
+// than this, so that small and mid-size grids still fill the chip
+constexpr int ZC_BLOCKS = RT_M1_ZC_BLOCKS;
 constexpr int BIG_MIN_BLOCKS = 1024;   // 64 x TY_LF tiles from this many on
 // the step keeps one FP64-cell mask word per plane of its chunk in a lane
 static_assert(ZC_DEFAULT <= TX, "z chunks longer than a wavefront");
+static_assert(ZC_MIN >= 2 && ZC_MIN <= ZC_DEFAULT, "z chunk bounds");
 constexpr double SIGMA_T = 6.6524587321e-25;  // Thomson cross-section [cm^2]
 constexpr int HSUM_DOUBLES = 256 + 2 * 257;   // histogram sums + edges
 
@@ -161,6 +172,19 @@ extern "C" const char *rt_strerror(int code)
     }
 }
 
+// Planes per block along z: the longest chunk (at most the grid's depth),
+// halved while the grid has fewer than ZC_BLOCKS tiles of 64 x TY cells.
+// Each block marches its chunk serially, so on small grids long chunks
+// leave most compute units idle; short chunks re-read more z-halo planes
+// (two per chunk), which the large grids avoid.
+static int z_chunk(int ntx, int ny, int nz)
+{
+    int zc = std::min(ZC_DEFAULT, nz);
+    const int64_t cols = int64_t(ntx) * ((ny + TY - 1) / TY);
+    while (zc / 2 >= ZC_MIN && cols * ((nz + zc - 1) / zc) < ZC_BLOCKS) zc /= 2;
+    return zc;
+}
+
 extern "C" int rt_init(const rt_params *params, const rt_fields *fields, void *hip_stream,
                        rt_ctx **out)
 {
@@ -177,8 +201,8 @@ extern "C" int rt_init(const rt_params *params, const rt_fields *fields, void *h
     c->f = *fields;
     c->stream = static_cast<hipStream_t>(hip_stream);
     c->ncell = uint32_t(params->nx) * uint32_t(params->ny) * uint32_t(params->nz);
-    c->zc = std::min(ZC_DEFAULT, params->nz);
     c->ntx = (params->nx + TX - 1) / TX;
+    c->zc = z_chunk(c->ntx, params->ny, params->nz);
     c->nzc = (params->nz + c->zc - 1) / c->zc;
     for (int gi = 0; gi < 2; ++gi) {
         TileSet &g = c->geo[gi];

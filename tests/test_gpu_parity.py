@@ -2,9 +2,10 @@
 from the same FP32-representable state, compared element by element with the
 per-field norms of parity_util (N, F <= 1e-4; xHI, T <= 1e-3).
 
-Shapes are chosen to span several 64 x 8 tiles and several 32-plane z chunks
-with ragged tails in every axis, every boundary condition, every chemistry
-mode, both precisions and both sub-cycle modes, plus degenerate grids."""
+Shapes are chosen to span several 64 x 8 tiles and several z chunks (small
+grids take chunks of 8-32 planes) with ragged tails in every axis, every
+boundary condition, every chemistry mode, both precisions and both sub-cycle
+modes, plus degenerate grids."""
 
 import numpy as np
 import pytest

@@ -366,20 +366,33 @@ Lists bin_sources(const rt_ctx *c, const TileSet &g, int64_t n, const int32_t *i
         int32_t tile, key;
         double ndot;
     };
-    std::vector<Src> v;
-    v.reserve(size_t(n));
+    // two stable counting sorts (by cell within the tile, then by tile) give
+    // the (tile, cell) order with equal cells kept in input order, so
+    // duplicates are summed in input order
+    const int64_t nkeys = int64_t(c->zc) * nt;
+    std::vector<int32_t> tile_of(static_cast<size_t>(n)), key_of(static_cast<size_t>(n));
+    std::vector<int64_t> kcount(static_cast<size_t>(nkeys) + 1, 0);
+    std::vector<int64_t> tcount(static_cast<size_t>(g.nblocks) + 1, 0);
     for (int64_t s = 0; s < n; ++s) {
         const int32_t i = ijk[3 * s], j = ijk[3 * s + 1], k = ijk[3 * s + 2];
         const int itx = i / TX, ity = j / g.ty, izc = k / c->zc;
         const int tile = (izc * g.nty + ity) * c->ntx + itx;
         const int key = (k - izc * c->zc) * nt + (j - ity * g.ty) * TX + (i - itx * TX);
-        v.push_back({tile, key, ndot[s]});
+        tile_of[size_t(s)] = tile;
+        key_of[size_t(s)] = key;
+        kcount[size_t(key) + 1] += 1;
+        tcount[size_t(tile) + 1] += 1;
     }
-    // stable: duplicate cells are summed in input order, so the result does
-    // not depend on the sort's tie-breaking
-    std::stable_sort(v.begin(), v.end(), [](const Src &a, const Src &b) {
-        return a.tile != b.tile ? a.tile < b.tile : a.key < b.key;
-    });
+    for (int64_t q = 0; q < nkeys; ++q) kcount[size_t(q) + 1] += kcount[size_t(q)];
+    for (int b = 0; b < g.nblocks; ++b) tcount[size_t(b) + 1] += tcount[size_t(b)];
+    std::vector<int64_t> by_key(static_cast<size_t>(n));
+    for (int64_t s = 0; s < n; ++s) by_key[size_t(kcount[size_t(key_of[size_t(s)])]++)] = s;
+    std::vector<Src> v(static_cast<size_t>(n));
+    for (int64_t r = 0; r < n; ++r) {
+        const int64_t s = by_key[size_t(r)];
+        const int32_t t = tile_of[size_t(s)];
+        v[size_t(tcount[size_t(t)]++)] = Src{t, key_of[size_t(s)], ndot[s]};
+    }
     // merge duplicate cells (nearest-grid-point projection sums them)
     Lists out;
     out.ptr.assign(size_t(g.nblocks) + 1, 0);

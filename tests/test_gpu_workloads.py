@@ -13,7 +13,8 @@
     RT_LONG_TESTS is set).
   * 1024^3 (the benchmark's workload and launch configuration): one step
     checked on sampled 32^3 sub-blocks (random, the eight corners and around
-    sources), the oracle stepping each from the library's input state."""
+    sources), the oracle stepping each from the library's input state; with
+    the LF fluxes and with HLL."""
 
 import os
 
@@ -162,11 +163,14 @@ def _block(t, z0, y0, x0, B, halo, n):
 
 
 @pytest.mark.timeout(900)
-def test_cosmo1024_sampled_subblocks():
+@pytest.mark.parametrize("flux", [rt.FLUX_LF, rt.FLUX_HLL], ids=["lf", "hll"])
+def test_cosmo1024_sampled_subblocks(flux):
+    # both fluxes in the launch configuration of the timed runs: LF on the
+    # 64 x 16 tiles with the deferred FP64 chemistry, HLL on the 64 x 8 ones
     w = W.workload("cosmo1024")
     n, B = w.n, 32
     nH, ijk, ndot = W.cosmo_inputs(w, device="cuda")
-    G = rt.RTGrid(rt.make_params((n,) * 3, w.dx, prec=rt.PREC_MIXED), dict(nH=nH))
+    G = rt.RTGrid(rt.make_params((n,) * 3, w.dx, prec=rt.PREC_MIXED, flux=flux), dict(nH=nH))
     del nH
     G.inject_sources(ijk, ndot)
     G.step(w.dt, 1, 20)
@@ -186,7 +190,8 @@ def test_cosmo1024_sampled_subblocks():
     post = G.tensors()
     cur = G.current()
     Nin, Fin = G.N[1 - cur], [G.Fx[1 - cur], G.Fy[1 - cur], G.Fz[1 - cur]]
-    p = oracle.make_params((B, B, B), w.dx, chem=oracle.CHEM_FULL)
+    p = oracle.make_params((B, B, B), w.dx, chem=oracle.CHEM_FULL,
+                           flux=oracle.FLUX_HLL if flux == rt.FLUX_HLL else oracle.FLUX_LF)
     vol = w.dx ** 3
     worst = dict(N=0.0, F=0.0, xHI=0.0, T=0.0)
     for o in origins:
@@ -208,7 +213,8 @@ def test_cosmo1024_sampled_subblocks():
         e = errors(got, ref)
         for k in worst:
             worst[k] = max(worst[k], e[k])
-        assert_parity(e, what=f"1024^3 block at {o}")
-    print(f"1024^3 sampled blocks ({len(origins)}): worst errors {worst}", flush=True)
+        assert_parity(e, what=f"1024^3 block at {o} (flux {flux})")
+    print(f"1024^3 sampled blocks ({len(origins)}, flux {flux}): worst errors {worst}",
+          flush=True)
     G.close()
     torch.cuda.empty_cache()

@@ -36,7 +36,10 @@ constexpr int ZC_MIN = RT_M1_ZC_MIN;  // shortest chunk the grid size may ask fo
 // chunks are halved (down to ZC_MIN) while a grid has fewer 64 x TY tiles
 // than this, so that small and mid-size grids still fill the chip
 constexpr int ZC_BLOCKS = RT_M1_ZC_BLOCKS;
-constexpr int BIG_MIN_BLOCKS = 1024;   // 64 x TY_LF tiles from this many on
+#ifndef RT_M1_BIG_MIN
+#define RT_M1_BIG_MIN 1024
+#endif
+constexpr int BIG_MIN_BLOCKS = RT_M1_BIG_MIN;   // 64 x TY_LF tiles from this many on
 // the step keeps one FP64-cell mask word per plane of its chunk in a lane
 static_assert(ZC_DEFAULT <= TX, "z chunks longer than a wavefront");
 static_assert(ZC_MIN >= 2 && ZC_MIN <= ZC_DEFAULT, "z chunk bounds");
@@ -220,7 +223,9 @@ extern "C" int rt_init(const rt_params *params, const rt_fields *fields, void *h
         c->nwords = uint64_t(params->nz) * uint64_t(params->ny) * uint64_t(c->ntx);
         c->nb2 = defer_chem_blocks(c->nwords);
     }
-    c->npart = std::max(std::max(c->geo[0].nblocks + c->nb2, c->geo[1].nblocks),
+    // partial rows: a step writes one per block of whichever tile set it
+    // runs on, then the deferred chemistry nb2 more after them
+    c->npart = std::max(std::max(c->geo[0].nblocks, c->geo[1].nblocks) + c->nb2,
                         state_sums_blocks(c->ncell));
     if (defer && hipMalloc(&c->d_mask, c->nwords * sizeof(uint64_t)) != hipSuccess) {
         (void)hipGetLastError();
@@ -609,6 +614,8 @@ extern "C" int rt_step(rt_ctx *c, double dt, int32_t nsub)
     }
     StepArgs a;
     fill_args(c, dt, nsub, a);
+    const int rows = a.nblocks + (a.defer ? c->nb2 : 0);
+    if (rows > c->npart) return RT_E_STATE;   // the partials would not fit
     Ev *e = nullptr;
     if (c->prof) {
         if (c->ev_used == c->ev.size()) {
@@ -621,11 +628,8 @@ extern "C" int rt_step(rt_ctx *c, double dt, int32_t nsub)
         if (hipEventRecord(e->a, c->stream) != hipSuccess) return RT_E_HIP;
     }
     if (launch_step(a, c->stream) != hipSuccess) return RT_E_HIP;
-    int rows = a.nblocks;
-    if (a.defer) {
-        if (launch_defer_chem(a, c->nwords, c->nb2, c->stream) != hipSuccess) return RT_E_HIP;
-        rows += c->nb2;
-    }
+    if (a.defer && launch_defer_chem(a, c->nwords, c->nb2, c->stream) != hipSuccess)
+        return RT_E_HIP;
     if (e && hipEventRecord(e->b, c->stream) != hipSuccess) return RT_E_HIP;
     const double tau_coef = c->p.c_cms * SIGMA_T * dt / double(c->ncell);
     if (launch_finalize(c->d_part, rows, c->d_fin, c->d_acc, 0, tau_coef, c->nh_sum,

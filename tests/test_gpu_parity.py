@@ -190,3 +190,24 @@ def test_error_paths_from_the_host():
     rc, out = rt.rt_reduce(G.ctx)
     assert rc == rt.RT_E_NONFINITE and out.n_nonfinite >= 1
     G.close()
+
+
+def test_mixed_lf_on_64x8_tiles_with_many_deferred_blocks():
+    # Too few 64 x 16 tiles (512) for them to be used, so the LF mixed step
+    # runs on 1024 tiles of 64 x 8, and the deferred FP64 chemistry adds 512
+    # partial rows after them: 1536 rows, more than either count alone or the
+    # state-sum blocks.  Parity, the step's tallies and its FP64 sums.
+    shape = (32, 512, 512)
+    st = W.random_state(shape, seed=512)
+    src = sources_for(shape, 200, 13)
+    g, o, red, og = one_step_pair(st, shape, DX, DT, 2, (rt.BC_PERIODIC,) * 6,
+                                  rt.CHEM_FULL, rt.PREC_MIXED, sources=src)
+    assert_parity(errors(g, o), what="64 x 8 tiles, deferred FP64 chemistry")
+    ro = og.reductions()
+    assert red["n_fp64"] > 0 and red["n_nonfinite"] == 0
+    assert red["photons_absorbed"] == pytest.approx(ro["photons_absorbed"], rel=1e-4)
+    assert red["photons_emitted"] == pytest.approx(ro["photons_emitted"], rel=1e-14)
+    assert red["xhi_vol"] == pytest.approx(g["xHI"].astype(np.float64).mean(), rel=1e-12)
+    vol = DX ** 3
+    assert red["photons_stored"] == pytest.approx(g["N"].astype(np.float64).sum() * vol,
+                                                  rel=1e-12)

@@ -78,7 +78,7 @@ struct rt_ctx {
     double *d_part = nullptr;
     int npart = 0;
     double *d_fin = nullptr;   // first-level finalisation rows
-    uint64_t *d_mask = nullptr;   // FP64 cells left by the step (mixed LF)
+    uint64_t *d_mask = nullptr;   // FP64 cells left by the step (mixed forms)
     uint64_t nwords = 0;
     int nb2 = 0;                  // blocks of the deferred FP64 chemistry
     double *d_acc = nullptr;
@@ -218,7 +218,7 @@ extern "C" int rt_init(const rt_params *params, const rt_fields *fields, void *h
         }
         g.nblocks = int(nb);
     }
-    const bool defer = params->prec == RT_PREC_MIXED && params->flux == RT_FLUX_LF;
+    const bool defer = params->prec == RT_PREC_MIXED;
     if (defer) {
         c->nwords = uint64_t(params->nz) * uint64_t(params->ny) * uint64_t(c->ntx);
         c->nb2 = defer_chem_blocks(c->nwords);
@@ -589,7 +589,7 @@ static void fill_args(const rt_ctx *c, double dt, int nsub, StepArgs &a)
     a.vol = p.dx_cm * p.dx_cm * p.dx_cm;
     a.esc_scale = dt * p.dx_cm * p.dx_cm;
     a.hll = p.flux == RT_FLUX_HLL ? 1 : 0;
-    a.defer = (p.prec == RT_PREC_MIXED && p.flux == RT_FLUX_LF && !c->surr) ? 1 : 0;
+    a.defer = (p.prec == RT_PREC_MIXED && !c->surr) ? 1 : 0;
     a.fp64_mask = c->d_mask;
     a.c_d = p.c_cms;
     a.surr = c->surr ? 1 : 0;

@@ -75,7 +75,7 @@ struct StepArgs {
     int chem, mixed, adaptive, nsub, any_outflow;
     int hll;                         // 1: HLL fluxes, 0: LF
     int big;                         // 1: 64 x TY_LF tiles (LF forms, large grids)
-    // mixed precision with LF fluxes and the exact chemistry: cells whose
+    // mixed precision with the exact chemistry (either flux): cells whose
     // chemistry runs in FP64 are marked in fp64_mask (one bit per cell, one
     // 64-bit word per x-row of a tile: word (z * ny + y) * ntx + tile x) and
     // left for launch_defer_chem

@@ -118,10 +118,11 @@ void m1_step_kernel(StepArgs A)
     static_assert(!BIG || (!SURR && !HLL), "64 x 16 tiles: LF forms only");
     constexpr int KTY = BIG ? TY_LF : TY;   // tile rows of this form
     constexpr int KNT = TX * KTY;           // its threads per block
-    // The LF mixed form leaves its FP64 cells to a second, small kernel
-    // (launch_defer_chem): the few waves that would take the FP64 branch
-    // here cost every wave registers and scheduling freedom.
-    constexpr bool DEFER = MIXED && !SURR && !HLL;
+    // The mixed forms (LF and HLL) leave their FP64 cells to a second, small
+    // kernel (launch_defer_chem): the few waves that would take the FP64
+    // branch here cost every wave registers and scheduling freedom.  (The
+    // surrogate form keeps its exact fallback inline.)
+    constexpr bool DEFER = MIXED && !SURR;
     constexpr int SW = TX + 2;
     __shared__ __attribute__((aligned(16))) __bf16 s_pk[SURR ? PK_FWD * 8 : 8];
     __shared__ float s_bias[SURR ? SURR_NBIAS : 1];
@@ -723,7 +724,7 @@ void m1_step_kernel(StepArgs A)
     }
 }
 
-// ------------------------------------- deferred FP64 chemistry (mixed LF)
+// ---------------------------------- deferred FP64 chemistry (mixed forms)
 // The cells the step marked in fp64_mask hold their transported N, F in the
 // next buffer and their step-start xHI, T.  Each wavefront reads 64 mask
 // words at a time (one per lane) and then takes the non-empty ones in turn,

@@ -203,12 +203,16 @@ int rt_sources_from_particles(rt_ctx *ctx, int64_t n, const double *pos,
 /* Advance one radiative-transfer step of length dt (Appendix A): the
  * unsplit explicit update of (N, F) with the intercell fluxes of
  * rt_params.flux (Lax-Friedrichs or HLL) of the M1 system plus dt*S, then Phi per cell -- nsub chemistry sub-cycles (fixed
- * mode) or at most nsub (adaptive mode) -- and the global sums, all in one
- * fused kernel followed by a one-block finalisation.  dt must satisfy
- * dt <= dx/(3c) (the CFL bound of Sec. 2.2 for the 3-D unsplit update;
- * RT_E_CFL otherwise); 1 <= nsub <= 4096.  Asynchronous, except that the
- * first step after the learned chemistry is switched on or off may first
- * rebin the point sources for its tiling (waiting for the stream once). */
+ * mode) or at most nsub (adaptive mode) -- and the global sums, in one
+ * fused kernel (in mixed precision a second, small kernel applies Phi in
+ * FP64 to the cells the first one marked) followed by the finalisation of
+ * the sums.  dt must satisfy dt <= dx/(3c) (the CFL bound of Sec. 2.2 for
+ * the 3-D unsplit update; RT_E_CFL otherwise); 1 <= nsub <= 4096.
+ * Asynchronous, except that the first step after the learned chemistry is
+ * switched on or off may first rebin the point sources for its tiling
+ * (waiting for the stream once).  RT_E_STATE also if the context's
+ * partial-sum buffer could not hold the launch (an internal check; nothing
+ * is launched then). */
 int rt_step(rt_ctx *ctx, double dt, int32_t nsub);
 
 /* Switch the learned chemistry on (theta != NULL) or off (theta == NULL).

@@ -2,8 +2,10 @@
 tiles): one mixed step on a grid ragged in every direction, with sources at
 its corners, checked against the oracle on sampled 32^3 sub-blocks (corners,
 edges, around sources, random) and by its photon budget; and the FP32 form
-the same way.  Smaller grids, HLL and the surrogate use 64 x 8 tiles, which
-the other GPU tests cover."""
+the same way; a grid whose z chunks are shortened to 32 planes (so that it
+has 1024 such tiles), checked everywhere; the source lists when the learned
+chemistry moves a grid to the 64 x 8 tiles.  Smaller grids, HLL and the
+surrogate use 64 x 8 tiles, which the other GPU tests cover."""
 
 import numpy as np
 import pytest
@@ -12,7 +14,8 @@ import torch
 import oracle
 from paper_1004_2503_amd import rt
 
-from parity_util import assert_parity, errors
+from paper_1004_2503_amd import workloads as W
+from parity_util import assert_parity, errors, one_step_pair
 
 pytestmark = pytest.mark.gpu
 
@@ -122,3 +125,23 @@ def test_source_lists_follow_the_tiling():
     assert float(d.max()) <= 1e-6 * float(np.abs(out[0][0]).max())
     del N, st
     torch.cuda.empty_cache()
+
+
+def test_big_tiles_with_short_z_chunks_whole_grid():
+    # 4 x 128 tiles of 64 x 8 per plane are too few for 64-plane chunks
+    # (512 blocks), so the chunks are halved to 32 planes (the last one 4
+    # planes), which makes 1024 tiles of 64 x 16: the LF forms take those.
+    # One mixed step with sources, checked everywhere against the oracle.
+    shape = (100, 1024, 256)
+    st = W.random_state(shape, seed=1124)
+    nz, ny, nx = shape
+    rng = np.random.default_rng(5)
+    ijk = np.stack([rng.integers(0, nx, 400), rng.integers(0, ny, 400),
+                    rng.integers(0, nz, 400)], axis=1).astype(np.int32)
+    ijk[:5] = [[nx - 1, ny - 1, nz - 1], [0, 0, 0], [3, 17, 96], [3, 17, 96], [200, 900, 99]]
+    ndot = 10 ** rng.uniform(50, 53, 400)
+    dt = DX / (3 * rt.C_LIGHT)
+    g, o, red, _ = one_step_pair(st, shape, DX, dt, 2, (rt.BC_PERIODIC,) * 6, rt.CHEM_FULL,
+                                 rt.PREC_MIXED, sources=(ijk, ndot))
+    assert_parity(errors(g, o), what="64 x 16 tiles, 32-plane chunks")
+    assert red["n_fp64"] > 0 and red["n_nonfinite"] == 0

@@ -77,6 +77,10 @@ def lib():
             dp] * 10
         L.orc_clumping.restype = None
         L.orc_clumping.argtypes = [ctypes.POINTER(Params), ctypes.c_double, dp, dp]
+        L.orc_rates_n.restype = None
+        L.orc_rates_n.argtypes = [ctypes.c_int64, dp, dp]
+        L.orc_chem_timescale.restype = ctypes.c_double
+        L.orc_chem_timescale.argtypes = [ctypes.POINTER(Params)] + [ctypes.c_double] * 4
         L.orc_heat_per_ionisation_erg.restype = ctypes.c_double
         L.orc_heat_per_ionisation_erg.argtypes = [ctypes.POINTER(Params)]
         L.orc_chem_cell.restype = None
@@ -145,6 +149,20 @@ def rates(T: float) -> np.ndarray:
     out = np.zeros(6)
     lib().orc_rates(float(T), _ptr(out))
     return out
+
+
+def rates_n(T) -> np.ndarray:
+    """rates() for an array of temperatures: shape (n, 6)."""
+    T = np.ascontiguousarray(np.asarray(T, dtype=np.float64).reshape(-1))
+    out = np.zeros((T.size, 6))
+    lib().orc_rates_n(T.size, _ptr(T), _ptr(out))
+    return out
+
+
+def chem_timescale(params: Params, nH, N, xHI, T) -> float:
+    """The adaptive sub-cycle time scale of one cell [s] (inf if static)."""
+    return lib().orc_chem_timescale(ctypes.byref(params), float(nH), float(N), float(xHI),
+                                    float(T))
 
 
 def heat_per_ionisation_erg(params: Params) -> float:

@@ -3,8 +3,7 @@
  * the per-cell hydrogen chemistry operator.  TEST INFRASTRUCTURE ONLY (see
  * m1_oracle.h): plain loops, every quantity from its definition, no tiling,
  * no fusion beyond what the method itself states.  Parity unpinned: the
- * rate coefficients other than alpha_B and the adaptive sub-cycle time
- * scale (marked where they are defined).  OpenMP only splits the
+ * adaptive sub-cycle time scale (marked where it is defined).  OpenMP only splits the
  * independent per-cell loops; every tally is summed per z-plane and then
  * over planes in a fixed order, so results do not depend on thread count.
  */
@@ -86,8 +85,13 @@ static double pcomp(const double P[6], int k, int d)
  *   r[3] collisional excitation cooling (HI)    [erg cm^3/s] Cen 1992
  *   r[4] collisional ionisation cooling = 13.6 eV * beta
  *   r[5] free-free (bremsstrahlung) cooling     [erg cm^3/s] Cen 1992
- * Pinned: alpha_B against a published table.  Parity unpinned: r[1]..r[5]
- * (the paper gives no rates; nothing outside this file fixes their values).
+ * Pinned: alpha_B against a published table; r[1]..r[5] against physics
+ * that does not come from these fits (thresholds at the ionisation and
+ * Lyman-alpha energies, 13.6 eV per collisional ionisation, an independent
+ * ionisation-rate fit, the mean energy per case-B recombination, the
+ * free-free Gaunt factor and the excitation collision strength implied by
+ * textbook prefactors).  The paper gives no rates, so the set itself is a
+ * reading, not a parity claim against the paper.
  * --------------------------------------------------------------------- */
 void orc_rates(double T, double r[6])
 {
@@ -103,6 +107,11 @@ void orc_rates(double T, double r[6])
     double lt = 5.5 - log10(T);
     double gff = 1.1 + 0.34 * exp(-lt * lt / 3.0);
     r[5] = 1.42e-27 * gff * sqrt(T);
+}
+
+void orc_rates_n(int64_t n, const double *T, double *r)
+{
+    for (int64_t i = 0; i < n; ++i) orc_rates(T[i], r + 6 * i);
 }
 
 /* Sec. 2.2 gray constants: energy deposited per photoionisation is the
@@ -141,8 +150,8 @@ static double cooling(const double r[6], double nHII, double nHI, double C_R)
  * small difference of large terms.  Parity unpinned: the paper states no
  * sub-cycling rule (the adaptive mode's convergence to the fixed-step limit
  * is what the tests check). */
-static double chem_timescale(const orc_params *p, double nH, double N,
-                             double xHI, double T)
+double orc_chem_timescale(const orc_params *p, double nH, double N,
+                          double xHI, double T)
 {
     double r[6], C_R, C_I;
     orc_rates(T, r);
@@ -192,7 +201,7 @@ void orc_chem_cell(const orc_params *p, double dt, int32_t nsub, double nH,
         if (it == nsub - 1) {
             h = remaining;
         } else if (p->sub == ORC_SUB_ADAPTIVE) {
-            double tc = chem_timescale(p, nH, *N, *xHI, *T);
+            double tc = orc_chem_timescale(p, nH, *N, *xHI, *T);
             h = fmin(remaining, p->sub_eps * tc);
         } else {
             h = dt / nsub;

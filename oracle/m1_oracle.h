@@ -99,6 +99,13 @@ void orc_eddington(double N, double Fx, double Fy, double Fz, double c,
 void orc_rates(double T, double r[6]);
 double orc_heat_per_ionisation_erg(const orc_params *p);
 void orc_clumping(const orc_params *p, double nH, double *C_R, double *C_I);
+/* orc_rates for n temperatures: r[6 i + m] = rate m at T[i]. */
+void orc_rates_n(int64_t n, const double *T, double *r);
+/* The adaptive sub-cycle time scale of a cell (the time over which the
+ * chemistry changes xHI or the internal energy by their own size, from the
+ * gross rates at the given state); INFINITY where nothing changes. */
+double orc_chem_timescale(const orc_params *p, double nH, double N, double xHI,
+                          double T);
 
 void orc_chem_cell(const orc_params *p, double dt, int32_t nsub, double nH,
                    double *N, double *Fx, double *Fy, double *Fz, double *xHI,

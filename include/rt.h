@@ -149,11 +149,14 @@ typedef struct {
     int64_t steps;           /* rt_step calls since rt_init                 */
     int64_t n_nonfinite;     /* cells with a non-finite result, cumulative  */
     int64_t n_fp64;          /* cell-steps whose chemistry ran in FP64      */
-    int64_t n_fallback;      /* surrogate cell-steps sent to the exact path */
+    int64_t n_fallback;      /* learned-chemistry cell-steps whose prediction
+                                was rejected (the exact operator took them) */
     int64_t subcycle_hist[8]; /* cell-steps by sub-cycle count: 1, 2-3,
                                  4-7, 8-15, 16-31, 32-63, 64-127, >=128     */
     double tau_e;            /* Thomson depth c sigma_T sum_steps <nH (1 - xHI)> dt,
                                 with the state at the end of each step (Sec. 3.1.4) */
+    int64_t n_learned;       /* learned-chemistry cell-steps that kept the
+                                network's prediction, cumulative */
 } rt_reductions;
 
 /* Create a context for the grid described by `params` over the caller's
@@ -202,17 +205,19 @@ int rt_sources_from_particles(rt_ctx *ctx, int64_t n, const double *pos,
 
 /* Advance one radiative-transfer step of length dt (Appendix A): the
  * unsplit explicit update of (N, F) with the intercell fluxes of
- * rt_params.flux (Lax-Friedrichs or HLL) of the M1 system plus dt*S, then Phi per cell -- nsub chemistry sub-cycles (fixed
- * mode) or at most nsub (adaptive mode) -- and the global sums, in one
- * fused kernel (in mixed precision a second, small kernel applies Phi in
- * FP64 to the cells the first one marked) followed by the finalisation of
- * the sums.  dt must satisfy dt <= dx/(3c) (the CFL bound of Sec. 2.2 for
- * the 3-D unsplit update; RT_E_CFL otherwise); 1 <= nsub <= 4096.
- * Asynchronous, except that the first step after the learned chemistry is
- * switched on or off may first rebin the point sources for its tiling
- * (waiting for the stream once).  RT_E_STATE also if the context's
- * partial-sum buffer could not hold the launch (an internal check; nothing
- * is launched then). */
+ * rt_params.flux (Lax-Friedrichs or HLL) of the M1 system plus dt*S, then
+ * Phi per cell -- nsub chemistry sub-cycles (fixed mode) or at most nsub
+ * (adaptive mode) -- and the global sums.  One fused kernel sweeps the
+ * grid; the cells whose Phi is costly -- in mixed precision those below
+ * xhi_fp64_thr (FP64 chemistry), in the adaptive and learned forms those
+ * that need more than one sub-cycle -- are left to a second kernel that
+ * processes them in dense wavefronts; a last one finalises the sums.  dt
+ * must satisfy dt <= dx/(3c) (the CFL bound of Sec. 2.2 for the 3-D unsplit
+ * update; RT_E_CFL otherwise); 1 <= nsub <= 4096.  Asynchronous, except
+ * that a step whose tiling has no source lists yet first bins the point
+ * sources for it (waiting for the stream once).  RT_E_STATE also if the
+ * context's partial-sum buffer could not hold the launch (an internal
+ * check; nothing is launched then). */
 int rt_step(rt_ctx *ctx, double dt, int32_t nsub);
 
 /* Switch the learned chemistry on (theta != NULL) or off (theta == NULL).
@@ -225,14 +230,22 @@ int rt_step(rt_ctx *ctx, double dt, int32_t nsub);
  * large ones; decoded as d = 1e-3 sinh u).  norm: host
  * float[24] = mu_in[5], sd_in[5], mu_out[2], sd_out[2] (the two
  * standardisations) and in_min[5], in_max[5] (the training range of the raw
- * log10 features).  With it on and chem == RT_CHEM_FULL,
- * rt_step evaluates the network on the matrix cores for every cell, derives
- * the absorbed photons from the predicted (xHI', T') (net ionisations +
- * recombinations - collisional ionisations) so the photon budget stays
- * exact, and runs the exact Phi instead for any cell whose inputs leave the
- * training range, whose prediction leaves the physical bounds, or whose
- * backward-Euler residual over dt exceeds residual_tol (counted in
- * rt_reductions.n_fallback).  RT_E_ARG for non-positive scales or tol. */
+ * log10 features).  With it on and chem == RT_CHEM_FULL, rt_step asks the
+ * network, on the matrix cores, for the cells whose chemistry is costly:
+ * those that are not dark (photons after transport, or xHI < 1) and whose
+ * adaptive operator would take more than one sub-cycle (sub_eps times the
+ * chemistry time scale at the transported state below dt; sub_eps = 0 asks
+ * it for every such cell), plus, in mixed precision, the cells below
+ * xhi_fp64_thr.  For each it derives the absorbed photons from the predicted
+ * (xHI', T') (net ionisations + recombinations - collisional ionisations
+ * over dt at that state) so the photon budget stays exact, and runs the
+ * exact Phi of the context's mode instead for any cell whose inputs leave
+ * the training range, whose prediction leaves the physical bounds, or whose
+ * backward-Euler residuals over dt (photoionisation, energy) exceed
+ * residual_tol (rt_reductions.n_fallback; n_learned counts the accepted
+ * cells).  The other cells take the exact operator.  RT_E_ARG for
+ * non-positive scales or tol, an inverted training range or sub_eps outside
+ * [0, 1]. */
 int rt_set_surrogate(rt_ctx *ctx, const float *theta, const float *norm, double residual_tol);
 
 /* Wait for the stream and report the sums of the last step (or of the

@@ -22,17 +22,22 @@ ionisations over the step, evaluated at the predicted end state:
 so that the photon budget (emitted = stored + absorbed + escaped) holds
 exactly whatever the network predicts.
 
-Acceptance.  The prediction is the end point of one backward-Euler step of
-length dt of the chemistry of Sec. 2.2 when
+Acceptance.  The prediction is compared with one backward-Euler step of
+length dt of the chemistry of Sec. 2.2 taken with every rate frozen at the
+predicted state: the photoionisation rate G' = C_I c sigma_n N', case-B
+recombination and collisional ionisation at T' with the electron density
+nH x' (Lambda' the cooling of Sec. 2.2's rate set there, the ne nHII terms
+times C_R; e_heat the energy per ionisation of the gray constants):
 
-    r_x = |P - C_I c sigma_n dt N' nH xHI'| / nH         (photoionisation),
-    r_T = |T' - T_BE| / T',   T_BE = u_BE / (3/2 kB nH (1 + x')),
-          u_BE = (u0 + P e_heat) / (1 + dt Lambda' / u'),
-          u0 = 3/2 kB nH (1 + x) T,   u' = 3/2 kB nH (1 + x') T',
+    xHI_BE = (xHI + C_R alpha_B(T') nH x'^2 dt) / (1 + G' dt + beta(T') nH x' dt),
+    u_BE = (u0 + P e_heat) / (1 + dt Lambda' / u'),  T_BE = u_BE / (3/2 kB nH (1 + x')),
+    u0 = 3/2 kB nH (1 + x) T,   u' = 3/2 kB nH (1 + x') T',
 
-both vanish (Lambda' the cooling of Sec. 2.2's rate set at the predicted
-state, the ne nHII terms times C_R; e_heat the energy per ionisation of the
-gray constants).  The cell keeps the prediction when r_x and r_T are at most
+    r_x = |xHI' - xHI_BE|,   r_T = |T' - T_BE| / T'.
+
+Both vanish exactly at the end point of the fully implicit step, and both
+measure the prediction's distance from it in the units of the state (an
+absolute neutral fraction, a relative temperature).  The cell keeps the prediction when r_x and r_T are at most
 the tolerance, its features lie inside the training range, 1e-12 <= xHI' <= 1,
 T' >= T_floor and T' is finite; otherwise the exact operator decides it.  Only
 the full chemistry (photo-heating and cooling) is ever replaced.
@@ -134,7 +139,11 @@ def accounting(params: Params, dt, nH, Nt, Fx, Fy, Fz, xHI, T, xs, Ts, tol, ood,
     with np.errstate(divide="ignore", invalid="ignore"):
         scale = np.where(Nt > 0.0, Ns / Nt, 0.0)
     csig = params.c * params.sigma_n
-    rx = np.abs(P - CI * csig * dt * Ns * nH * xs) / nH
+    # neutral fraction after one backward-Euler step with the rates frozen
+    # at the prediction
+    xBE = (xHI + CR * alpha * nH * x1 * x1 * dt) / (1.0 + CI * csig * Ns * dt +
+                                                     beta * nH * x1 * dt)
+    rx = np.abs(xs - xBE)
     # energy: backward Euler with the cooling rate at the predicted state
     lam = nH * nH * (CR * x1 * x1 * (r[:, 2] + r[:, 5]) + x1 * xs * (r[:, 3] + r[:, 4]))
     u0 = 1.5 * KB * nH * (1.0 + x0) * T
@@ -150,14 +159,14 @@ def accounting(params: Params, dt, nH, Nt, Fx, Fy, Fz, xHI, T, xs, Ts, tol, ood,
                 rx=rx, rT=rT, ok=ok)
 
 
-def stiff(params: Params, dt, nH, N, xHI, T) -> np.ndarray:
-    """Cells whose adaptive operator would take more than one sub-cycle:
-    sub_eps times the chemistry time scale (at the transported state) is
-    shorter than the step."""
+def stiffness(params: Params, dt, nH, N, xHI, T) -> np.ndarray:
+    """sub_eps times the chemistry time scale over the step, per cell (at the
+    transported state): below 1 the adaptive operator would take more than
+    one sub-cycle (the cell is stiff)."""
     nH, N, xHI, T = (np.asarray(v, dtype=np.float64).reshape(-1) for v in (nH, N, xHI, T))
-    out = np.zeros(nH.size, dtype=bool)
+    out = np.empty(nH.size)
     for i in range(nH.size):
-        out[i] = params.sub_eps * chem_timescale(params, nH[i], N[i], xHI[i], T[i]) < dt
+        out[i] = params.sub_eps * chem_timescale(params, nH[i], N[i], xHI[i], T[i]) / dt
     return out
 
 
@@ -169,16 +178,20 @@ def _clone(params: Params, **kw) -> Params:
 
 
 def step(params: Params, state: dict, sources, dt, nsub, theta, norm, tol,
-         select: str = "lit", bf16_operands: bool = True) -> dict:
+         select: str = "stiff", fp64_thr: float = 0.0, bf16_operands: bool = True) -> dict:
     """One step of the learned form on a grid.  Transport (the oracle's step
     with chemistry off), then per cell: dark, fully neutral cells (no
-    photons after transport, xHI = 1) and, with select = "stiff", cells the
-    adaptive operator would finish in one sub-cycle, take the exact operator
-    (the oracle's step with the chemistry of `params`); the others ("lit" or
-    "stiff" candidates) take the network's prediction where accepted and the
-    exact operator elsewhere.  Returns the end state (N, Fx, Fy, Fz, xHI, T)
-    plus per-cell arrays cand, ok, rx, rT, P and the exact end state under
-    the key "exact"."""
+    photons after transport, xHI = 1) take the exact operator (the oracle's
+    step with the chemistry of `params`), and so, with select = "stiff", do
+    the cells that the adaptive operator would finish in one sub-cycle,
+    unless their xHI lies below fp64_thr (the mixed form sends those cells to
+    the network too); the other cells (the candidates; with select = "lit"
+    every cell that is not dark) take the network's prediction where it is
+    accepted and the exact operator elsewhere.  Returns the end state (N,
+    Fx, Fy, Fz, xHI, T) plus per-cell arrays cand, ok, rx, rT, P, stiffness
+    (see stiffness()), the exact end state ("exact"), the transported state
+    ("transported") and the end state every cell would have if its
+    prediction were accepted ("net")."""
     shape = np.shape(state["nH"])
 
     def run(p, nsub_):
@@ -199,8 +212,9 @@ def step(params: Params, state: dict, sources, dt, nsub, theta, norm, tol,
     Nt = tr["N"].reshape(-1)
     dark = ~(Nt > 0.0) & (x0 >= 1.0)
     cand = ~dark
+    ratio = stiffness(params, dt, nH, Nt, x0, T0)
     if select == "stiff":
-        cand &= stiff(params, dt, nH, Nt, x0, T0)
+        cand &= (ratio < 1.0) | (x0 < fp64_thr)
     elif select != "lit":
         raise ValueError(select)
     f = features(nH, Nt, x0, T0, dt)
@@ -213,6 +227,8 @@ def step(params: Params, state: dict, sources, dt, nsub, theta, norm, tol,
     for k in ("N", "Fx", "Fy", "Fz", "xHI", "T"):
         out[k] = np.where(ok, acc[k], ex[k].reshape(-1)).reshape(shape)
     out.update(cand=cand.reshape(shape), ok=ok.reshape(shape), rx=acc["rx"].reshape(shape),
+               stiffness=ratio.reshape(shape),
                rT=acc["rT"].reshape(shape), P=acc["P"].reshape(shape), exact=ex,
-               transported=tr, xs=xs.reshape(shape), Ts=Ts.reshape(shape))
+               transported=tr,
+               net={k: acc[k].reshape(shape) for k in ("N", "Fx", "Fy", "Fz", "xHI", "T")})
     return out

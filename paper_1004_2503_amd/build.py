@@ -24,6 +24,8 @@ HIPCC_FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall",
     "-Wno-unused-function",
+    # every symbol resolved at link time, not at the first dlopen
+    "-Wl,-z,defs",
 ]
 
 

@@ -144,8 +144,8 @@ hipError_t launch_hist(const float *nH, const float *q, int gamma, double csig, 
 // The root in [0, 1] is taken as a over the larger root's numerator,
 //   y = 2a / ((2a + g + b) + sqrt((g + b)^2 + 4 a g)),
 // where every term is non-negative: no cancellation at either end (y << 1
-// in ionised gas, 1 - y << 1 in shielded gas).  alpha and beta are the FP32
-// rate fits of the step's chemistry; the rest is FP64.
+// in ionised gas, 1 - y << 1 in shielded gas).  alpha and beta are the rate
+// fits of the step's chemistry, evaluated in FP64 like the rest.
 __global__ __launch_bounds__(256) void equilibrium_kernel(
     int64_t n, const double *__restrict__ nH, const double *__restrict__ T,
     double *__restrict__ xhi, int model, double gamma0, double inv_nstar, int clump,
@@ -170,9 +170,9 @@ __global__ __launch_bounds__(256) void equilibrium_kernel(
         cR = fmax(1.0, cr_norm * pow(nh, cr_exp));
         cI = ci_norm * pow(nh, ci_exp);
     }
-    const RateSet rs = rates_f32(float(t), 1.0f);
-    const double a = cR * double(rs.alpha) * nh;
-    const double b = double(rs.beta) * nh;
+    const RateSetT<double> rs = rates_f64(t, 1.0);
+    const double a = cR * rs.alpha * nh;
+    const double b = rs.beta * nh;
     const double gi = cI * g;
     const double s = gi + b;
     const double den = (2.0 * a + s) + sqrt(s * s + 4.0 * a * gi);

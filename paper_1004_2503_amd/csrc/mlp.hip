@@ -337,10 +337,10 @@ __global__ __launch_bounds__(256) void chem_batch_kernel(int64_t n, const float 
                                                          float *__restrict__ T,
                                                          const float *__restrict__ dt,
                                                          int chem, int mixed, int adaptive,
-                                                         int nsub, float csig, float T_h,
-                                                         float inv15kB, float T_floor,
-                                                         float sub_eps, float xhi_thr,
-                                                         ClumpLaw cl,
+                                                         int nsub, double csig, double T_h,
+                                                         double inv15kB, double T_floor,
+                                                         double sub_eps, float xhi_thr,
+                                                         ClumpLaw cl, ClumpLawD cld,
                                                          int32_t *__restrict__ ncyc)
 {
     const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
@@ -348,21 +348,19 @@ __global__ __launch_bounds__(256) void chem_batch_kernel(int64_t n, const float 
     const float d = dt[i];
     int nc = 0;
     if (mixed && xHI[i] < xhi_thr) {
-        const ChemK<double> K{double(d), double(d) / nsub, double(csig), double(T_h),
-                              double(T_floor), double(sub_eps)};
-        double Nd = N[i], xd = xHI[i], Td = T[i], ad = 0.0;
-        float cR, cI;
-        clump_f32(cl, nH[i], cR, cI);
-        nc = chem_cell<double>(chem, nsub, adaptive, inv15kB, K, double(cR), double(cI),
-                               double(nH[i]), Nd, xd, Td, ad);
+        const ChemK<double> K{double(d), double(d) / nsub, csig, T_h, T_floor, sub_eps, inv15kB};
+        double Nd = N[i], xd = xHI[i], Td = T[i], ad = 0.0, cR, cI;
+        clump_f64(cld, double(nH[i]), cR, cI);
+        nc = chem_cell<double>(chem, nsub, adaptive, K, cR, cI, double(nH[i]), Nd, xd, Td, ad);
         N[i] = float(Nd);
         xHI[i] = float(xd);
         T[i] = float(Td);
     } else {
-        const ChemK<float> K{d, d / float(nsub), csig, T_h, T_floor, sub_eps};
+        const ChemK<float> K{d,          d / float(nsub),  float(csig),   float(T_h),
+                             float(T_floor), float(sub_eps), float(inv15kB)};
         float Nf = N[i], xf = xHI[i], Tf = T[i], af = 0.0f, cR, cI;
         clump_f32(cl, nH[i], cR, cI);
-        nc = chem_cell<float>(chem, nsub, adaptive, inv15kB, K, cR, cI, nH[i], Nf, xf, Tf, af);
+        nc = chem_cell<float>(chem, nsub, adaptive, K, cR, cI, nH[i], Nf, xf, Tf, af);
         N[i] = Nf;
         xHI[i] = xf;
         T[i] = Tf;
@@ -503,8 +501,8 @@ extern "C" int rt_chem_apply(const rt_params *p, int64_t n, const float *nH, flo
     hipLaunchKernelGGL(chem_batch_kernel, dim3(unsigned(blocks)), dim3(256), 0,
                        static_cast<hipStream_t>(hip_stream), n, nH, N, xHI, T, dt, p->chem,
                        p->prec == RT_PREC_MIXED ? 1 : 0, p->sub == RT_SUB_ADAPTIVE ? 1 : 0,
-                       nsub, float(p->c_cms * p->sigma_n), float(eheat / (1.5 * KB_)),
-                       float(1.0 / (1.5 * KB_)), float(p->T_floor), float(p->sub_eps),
-                       float(p->xhi_fp64_thr), make_clump_law(*p), ncycles);
+                       nsub, p->c_cms * p->sigma_n, eheat / (1.5 * KB_), 1.0 / (1.5 * KB_),
+                       p->T_floor, p->sub_eps, float(p->xhi_fp64_thr), make_clump_law(*p),
+                       make_clump_law_d(*p), ncycles);
     return hipGetLastError() == hipSuccess ? RT_OK : RT_E_HIP;
 }

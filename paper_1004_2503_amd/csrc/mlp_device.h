@@ -133,4 +133,35 @@ __device__ __forceinline__ void mlp_forward32(const PK *pk, const MlpBias &bias,
     y1 = acc[1] + bias.b4[1];
 }
 
+// Forward pass of the 64 cells of a wavefront (every lane takes part): sv
+// holds this lane's five standardised features; returns this lane's two
+// standardised outputs.  Two 32-cell passes: lanes 0..31 first, then the
+// features of lanes 32..63 moved down and the outputs moved back up.
+__device__ __forceinline__ void mlp_predict64(const bf16x8 *pk, const MlpBias &bias,
+                                              const float sv[5], float &y0, float &y1)
+{
+    const int lane = threadIdx.x & 63;
+    bf16x8 xa, xb;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        xa[k] = (__bf16)0.0f;
+        xb[k] = (__bf16)0.0f;
+    }
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        const float up = __shfl(sv[k], (lane + 32) & 63);
+        if (lane < 32) {
+            xa[k] = (__bf16)sv[k];
+            xb[k] = (__bf16)up;
+        }
+    }
+    MlpFwd unused;
+    float ya0, ya1, yb0, yb1;
+    mlp_forward32<false>(pk, bias, xa, unused, ya0, ya1);
+    mlp_forward32<false>(pk, bias, xb, unused, yb0, yb1);
+    const float sb0 = __shfl(yb0, lane & 31), sb1 = __shfl(yb1, lane & 31);
+    y0 = lane < 32 ? ya0 : sb0;
+    y1 = lane < 32 ? ya1 : sb1;
+}
+
 }  // namespace rtk

@@ -218,11 +218,11 @@ extern "C" int rt_init(const rt_params *params, const rt_fields *fields, void *h
         }
         g.nblocks = int(nb);
     }
-    const bool defer = params->prec == RT_PREC_MIXED;
-    if (defer) {
-        c->nwords = uint64_t(params->nz) * uint64_t(params->ny) * uint64_t(c->ntx);
-        c->nb2 = defer_chem_blocks(c->nwords);
-    }
+    // the deferred chemistry's mask: needed by the mixed and adaptive forms
+    // from the start, by the learned chemistry once it is switched on
+    const bool defer = params->prec == RT_PREC_MIXED || params->sub == RT_SUB_ADAPTIVE;
+    c->nwords = uint64_t(params->nz) * uint64_t(params->ny) * uint64_t(c->ntx);
+    c->nb2 = defer_chem_blocks(c->nwords);
     // partial rows: a step writes one per block of whichever tile set it
     // runs on, then the deferred chemistry nb2 more after them
     c->npart = std::max(std::max(c->geo[0].nblocks, c->geo[1].nblocks) + c->nb2,
@@ -423,10 +423,10 @@ Lists bin_sources(const rt_ctx *c, const TileSet &g, int64_t n, const int32_t *i
 
 // Which tile set the next step uses: the LF forms take the 64 x TY_LF
 // tiles when there are enough of them to fill the chip (four per compute
-// unit); small grids, HLL and the surrogate take the 64 x TY ones.
+// unit); small grids and HLL take the 64 x TY ones.
 static int tile_set(const rt_ctx *c)
 {
-    const bool lf = !c->surr && c->p.flux == RT_FLUX_LF;
+    const bool lf = c->p.flux == RT_FLUX_LF;
     return (lf && c->geo[0].nblocks >= BIG_MIN_BLOCKS) ? 0 : 1;
 }
 
@@ -526,6 +526,17 @@ ClumpLaw rtk::make_clump_law(const rt_params &p)
     return l;
 }
 
+ClumpLawD rtk::make_clump_law_d(const rt_params &p)
+{
+    ClumpLawD l{};
+    l.on = p.clump;
+    l.cr_norm = p.clump_cr_norm;
+    l.cr_exp = p.clump_cr_exp;
+    l.ci_norm = p.clump_ci_norm;
+    l.ci_exp = p.clump_ci_exp;
+    return l;
+}
+
 static void fill_args(const rt_ctx *c, double dt, int nsub, StepArgs &a)
 {
     const rt_params &p = c->p;
@@ -564,6 +575,7 @@ static void fill_args(const rt_ctx *c, double dt, int nsub, StepArgs &a)
     a.adaptive = p.sub == RT_SUB_ADAPTIVE;
     a.nsub = nsub;
     a.cl = make_clump_law(p);
+    a.cld = make_clump_law_d(p);
     a.any_outflow = 0;
     for (int f = 0; f < 6; ++f) a.any_outflow |= p.bc[f] == RT_BC_OUTFLOW ? 1 : 0;
     const double c_ = p.c_cms;
@@ -586,10 +598,15 @@ static void fill_args(const rt_ctx *c, double dt, int nsub, StepArgs &a)
     a.T_h_d = T_h;
     a.T_floor_d = p.T_floor;
     a.sub_eps_d = p.sub_eps;
+    a.inv15kB_d = 1.0 / (1.5 * KB);
     a.vol = p.dx_cm * p.dx_cm * p.dx_cm;
     a.esc_scale = dt * p.dx_cm * p.dx_cm;
     a.hll = p.flux == RT_FLUX_HLL ? 1 : 0;
-    a.defer = (p.prec == RT_PREC_MIXED && !c->surr) ? 1 : 0;
+    // stiff cells leave the step for the dense deferred kernel in the
+    // adaptive and learned forms
+    a.defer_stiff = (p.chem != RT_CHEM_OFF && (c->surr || p.sub == RT_SUB_ADAPTIVE)) ? 1 : 0;
+    a.defer = (p.chem != RT_CHEM_OFF && (p.prec == RT_PREC_MIXED || a.defer_stiff)) ? 1 : 0;
+    a.count_hist = (p.sub == RT_SUB_ADAPTIVE || c->surr) ? 1 : 0;
     a.fp64_mask = c->d_mask;
     a.c_d = p.c_cms;
     a.surr = c->surr ? 1 : 0;
@@ -616,6 +633,7 @@ extern "C" int rt_step(rt_ctx *c, double dt, int32_t nsub)
     fill_args(c, dt, nsub, a);
     const int rows = a.nblocks + (a.defer ? c->nb2 : 0);
     if (rows > c->npart) return RT_E_STATE;   // the partials would not fit
+    if (a.defer && !c->d_mask) return RT_E_STATE;
     Ev *e = nullptr;
     if (c->prof) {
         if (c->ev_used == c->ev.size()) {
@@ -639,7 +657,7 @@ extern "C" int rt_step(rt_ctx *c, double dt, int32_t nsub)
     c->t += dt;
     c->emitted += dt * c->ndot_total;
     c->steps += 1;
-    if (c->p.sub == RT_SUB_FIXED && c->p.chem != RT_CHEM_OFF && !c->surr) {
+    if (!a.count_hist && c->p.chem != RT_CHEM_OFF) {
         int b = 0;
         while (b < 7 && (2 << b) <= nsub) ++b;
         c->hist_host[b] += int64_t(c->ncell);
@@ -656,7 +674,8 @@ extern "C" int rt_set_surrogate(rt_ctx *c, const float *theta, const float *norm
         return RT_OK;
     }
     if (!norm || !(residual_tol > 0.0) || !isfinite(residual_tol)) return RT_E_ARG;
-    if (c->p.flux != RT_FLUX_LF) return RT_E_ARG;   // surrogate step: LF only
+    // the stiffness test that selects the network's cells uses sub_eps
+    if (!(c->p.sub_eps >= 0.0 && c->p.sub_eps <= 1.0)) return RT_E_ARG;
     for (int k = 0; k < SURR_NNORM; ++k)
         if (!isfinite(norm[k])) return RT_E_ARG;
     for (int k = 0; k < 7; ++k)
@@ -669,6 +688,10 @@ extern "C" int rt_set_surrogate(rt_ctx *c, const float *theta, const float *norm
             (void)hipGetLastError();
             return RT_E_NOMEM;
         }
+    }
+    if (!c->d_mask && hipMalloc(&c->d_mask, c->nwords * sizeof(uint64_t)) != hipSuccess) {
+        (void)hipGetLastError();
+        return RT_E_NOMEM;
     }
     const int offs[4] = {OFF_B1, OFF_B2, OFF_B3, OFF_B4};
     const int lens[4] = {MLP_NH, MLP_NH, MLP_NH, MLP_NOUT};
@@ -716,6 +739,7 @@ extern "C" int rt_reduce(rt_ctx *c, rt_reductions *out)
     for (int b = 0; b < 8; ++b)
         out->subcycle_hist[b] = c->hist_host[b] + int64_t(acc[ACC_CUM + R_HIST0 + b]);
     out->tau_e = acc[ACC_CUM + ACC_TAU];
+    out->n_learned = int64_t(acc[ACC_CUM + R_LEARNED]);
     return out->n_nonfinite > 0 ? RT_E_NONFINITE : RT_OK;
 }
 

@@ -140,13 +140,17 @@ __device__ __forceinline__ HllW hll_weights(float lmL, float lpL, float lmR, flo
 // alpha_B and case-B recombination cooling: Hui & Gnedin (1997);
 // collisional ionisation, its cooling (13.6 eV each), collisional excitation
 // and free-free cooling: Cen (1992).  Cooling rates are returned divided by
-// 3/2 kB so that the energy update works in kelvin.
-struct RateSet {
-    float alpha;  // [cm^3/s]
-    float beta;   // [cm^3/s]
-    float crb;    // (recombination + free-free) cooling / (1.5 kB) [K cm^3/s]
-    float cci;    // (excitation + ionisation) cooling / (1.5 kB) [K cm^3/s]
+// 3/2 kB so that the energy update works in kelvin.  rates_f32 serves the
+// FP32 chemistry (hardware exp2/log2), rates_f64 the FP64 chemistry (libm
+// double precision).
+template <typename R>
+struct RateSetT {
+    R alpha;  // [cm^3/s]
+    R beta;   // [cm^3/s]
+    R crb;    // (recombination + free-free) cooling / (1.5 kB) [K cm^3/s]
+    R cci;    // (excitation + ionisation) cooling / (1.5 kB) [K cm^3/s]
 };
+using RateSet = RateSetT<float>;
 
 __device__ __forceinline__ RateSet rates_f32(float T, float inv15kB)
 {
@@ -170,34 +174,62 @@ __device__ __forceinline__ RateSet rates_f32(float T, float inv15kB)
     return r;
 }
 
+__device__ __forceinline__ RateSetT<double> rates_f64(double T, double inv15kB)
+{
+    RateSetT<double> r;
+    const double lam = 315614.0 / T;                  // 2 T_HI / T
+    const double llam = log(lam);
+    r.alpha = 2.753e-14 * exp(1.5 * llam - 2.242 * log1p(exp(0.407 * (llam - log(2.740)))));
+    const double recb =
+        3.435e-30 * T * exp(1.970 * llam - 3.720 * log1p(exp(0.376 * (llam - log(2.250)))));
+    const double sT = sqrt(T);
+    const double damp = 1.0 / (1.0 + sT * 3.1622776601683795e-3);
+    r.beta = 5.85e-11 * sT * exp(-157809.1 / T) * damp;
+    const double colex = 7.5e-19 * exp(-118348.0 / T) * damp;
+    const double colion = 2.178960222240e-11 * r.beta;   // 13.6 eV per ionisation
+    const double lt = 5.5 - log10(T);
+    const double brems = 1.42e-27 * sT * (1.1 + 0.34 * exp(-lt * lt / 3.0));
+    r.crb = (recb + brems) * inv15kB;
+    r.cci = (colex + colion) * inv15kB;
+    return r;
+}
+
 // ------------------------------------------------ per-cell operator Phi
 template <typename R>
 struct ChemK {
-    R dt, hfix, csig, T_h, T_floor, sub_eps;
+    R dt, hfix, csig, T_h, T_floor, sub_eps, inv15kB;
 };
+
+__device__ __forceinline__ RateSetT<float> rates_of(float T, const ChemK<float> &K)
+{
+    return rates_f32(T, K.inv15kB);
+}
+__device__ __forceinline__ RateSetT<double> rates_of(double T, const ChemK<double> &K)
+{
+    return rates_f64(T, K.inv15kB);
+}
 
 // Adaptive sub-cycle time scale: the shorter of xHI / (gross xHI rate) and
 // u / (heating + cooling rate).  Gross rates keep it well conditioned near
 // equilibrium, where the net rate is a small difference of large terms.
 template <typename R>
-__device__ __forceinline__ R chem_timescale(int chem, const ChemK<R> &K, const RateSet &rs,
+__device__ __forceinline__ R chem_timescale(int chem, const ChemK<R> &K, const RateSetT<R> &rs,
                                             R cR, R cI, R nH, R N, R xHI, R x, R T)
 {
     R g = cI * K.csig * N;
-    R gx = cR * R(rs.alpha) * nH * x * x + (g + R(rs.beta) * nH * x) * xHI;
+    R gx = cR * rs.alpha * nH * x * x + (g + rs.beta * nH * x) * xHI;
     R t = R(3.0e38f);
     if (gx > R(0)) t = xHI * frcp(gx);
     if (chem == RT_CHEM_FULL) {
-        R gu = g * xHI * K.T_h + nH * (x * x * cR * R(rs.crb) + x * xHI * R(rs.cci));
+        R gu = g * xHI * K.T_h + nH * (x * x * cR * rs.crb + x * xHI * rs.cci);
         if (gu > R(0)) t = rmin(t, (R(1) + x) * T * frcp(gu));
     }
     return t;
 }
 
 // Subgrid clumping factors (Sec. 3.2.1) of a cell: C_R = max(1, norm_R
-// nH^exp_R) and C_I = norm_I nH^exp_I, evaluated as 2^(exp log2 nH + l2n)
-// with l2n = log2 norm.  Exactly 1 when clumping is off.  The FP64
-// chemistry takes the same FP32 factors (relative error ~1e-6).
+// nH^exp_R) and C_I = norm_I nH^exp_I.  FP32: 2^(exp log2 nH + l2n) with
+// l2n = log2 norm; FP64: libm pow.  Exactly 1 when clumping is off.
 __device__ __forceinline__ void clump_f32(const ClumpLaw &L, float nH, float &cR, float &cI)
 {
     cR = 1.0f;
@@ -209,32 +241,113 @@ __device__ __forceinline__ void clump_f32(const ClumpLaw &L, float nH, float &cR
     }
 }
 
-// Sub-cycles of one cell: implicit photon-conserving photoionisation,
-// creation/destruction recombination update, semi-implicit energy update.
-// cR multiplies the terms in ne nHII (recombination and its cooling,
-// bremsstrahlung), cI the photoionisation rate.  Returns the number of
-// sub-cycles; N, xHI, T updated; `absorbed` gains the photon density
-// removed.
+__device__ __forceinline__ void clump_f64(const ClumpLawD &L, double nH, double &cR, double &cI)
+{
+    cR = 1.0;
+    cI = 1.0;
+    if (L.on) {
+        cR = fmax(1.0, L.cr_norm * pow(nH, L.cr_exp));
+        cI = L.ci_norm * pow(nH, L.ci_exp);
+    }
+}
+
+// One sub-cycle of length h with the rates rs at the sub-cycle's starting
+// T: implicit photon-conserving photoionisation, creation/destruction
+// recombination update, semi-implicit energy update.  cR multiplies the
+// terms in ne nHII (recombination and its cooling, bremsstrahlung), cI the
+// photoionisation rate.  The ionised fraction xi is carried beside xHI with
+// updates free of cancellation: 1 - xHI would lose its relative precision
+// in nearly neutral gas, where cooling goes as its square.  N, xHI, xi, T
+// updated; `absorbed` gains the photon density removed.
 template <typename R>
-__device__ __forceinline__ int chem_cell(int chem, int nsub, int adaptive, float inv15kB,
-                                         const ChemK<R> &K, R cR, R cI, R nH, R &N, R &xHI,
-                                         R &T, R &absorbed)
+__device__ __forceinline__ void chem_sub(int chem, const ChemK<R> &K, const RateSetT<R> &rs,
+                                         R cR, R cI, R nH, R inv_nH, R h, R &N, R &xHI,
+                                         R &xi, R &T, R &absorbed)
+{
+    const R a = cI * K.csig * h;
+    const R nHI = nH * xHI;
+    if (chem == RT_CHEM_FROZEN) {
+        R Nn = N * frcp(R(1) + a * nHI);
+        absorbed += N - Nn;
+        N = Nn;
+        return;
+    }
+    // photoionisation: remaining photons Nn and neutrals un solve
+    // a un Nn = N - Nn, un - Nn = nHI - N; each root taken in the
+    // cancellation-free form for its sign of aD.  Without photons
+    // nothing is absorbed and xHI is left exactly as it is.
+    const R x0 = xi;
+    R Pd = R(0), xh = xHI;
+    if (N > R(0)) {
+        const R aN = a * N, aH = a * nHI, aD = aH - aN;
+        const R opd = R(1) + aD;
+        const R s = fsqrt(opd * opd + R(4) * aN);
+        R Nn, un;
+        if (aD >= R(0)) {
+            Nn = R(2) * N * frcp(opd + s);
+            un = Nn + (nHI - N);
+        } else {
+            un = R(2) * nHI * frcp((R(1) - aD) + s);
+            Nn = un - (nHI - N);
+        }
+        Nn = rmin(rmax(Nn, R(0)), N);
+        un = rmin(rmax(un, R(0)), nHI);
+        Pd = R(2) * aN * nHI * frcp(R(1) + aN + aH + s);
+        absorbed += N - Nn;
+        N = Nn;
+        xh = un * inv_nH;
+    }
+
+    // recombination (case B) and collisional ionisation:
+    // xn = (xh + A x^2) / (1 + B x); with xh + x = 1 the ionised
+    // fraction after it is x (1 + B - A x) / (1 + B x), taken in that
+    // form when it is the smaller of the two
+    const R x = rmin(x0 + Pd * inv_nH, R(1));
+    const R A = cR * rs.alpha * nH * h, B = rs.beta * nH * h;
+    const R den = frcp(R(1) + B * x);
+    R xn = (xh + A * x * x) * den;
+    R xin;
+    if (xn >= R(0.5)) {
+        xin = rmax(x * (R(1) + B - A * x) * den, R(0));
+        xn = R(1) - xin;
+    } else {
+        xin = R(1) - xn;
+    }
+    xn = rmin(rmax(xn, R(1e-12)), R(1));
+
+    // internal energy 3/2 kB nH (1+x) T: photo-heating, then cooling
+    if (chem == RT_CHEM_FULL) {
+        const R x1 = xin;
+        const R lu = h * nH * (x1 * x1 * cR * rs.crb + x1 * xn * rs.cci) *
+                     frcp((R(1) + x0) * T);
+        const R Tn = ((R(1) + x0) * T + Pd * inv_nH * K.T_h) *
+                     frcp((R(1) + lu) * (R(1) + x1));
+        T = rmax(Tn, K.T_floor);
+    }
+    xHI = xn;
+    xi = rmin(xin, R(1));
+}
+
+// Sub-cycles of one cell: fixed (nsub of length dt / nsub) or adaptive
+// (h = min(rest, sub_eps t_chem), at most nsub, the last taking the rest).
+// Returns the number of sub-cycles; N, xHI, T updated; `absorbed` gains the
+// photon density removed.
+template <typename R>
+__device__ __forceinline__ int chem_cell(int chem, int nsub, int adaptive, const ChemK<R> &K,
+                                         R cR, R cI, R nH, R &N, R &xHI, R &T, R &absorbed)
 {
     const R inv_nH = frcp(nH);
-    // The ionised fraction is carried beside xHI with updates free of
-    // cancellation: 1 - xHI would lose its relative precision in nearly
-    // neutral gas, where cooling goes as its square.
     R xi = R(1) - xHI;
     R remaining = K.dt;
     int it = 0;
     for (; it < nsub && remaining > R(0); ++it) {
-        RateSet rs;
+        RateSetT<R> rs;
         bool have = false;
         R h;
         if (it == nsub - 1) {
             h = remaining;
         } else if (adaptive) {
-            rs = rates_f32(float(T), inv15kB);
+            rs = rates_of(T, K);
             have = true;
             h = rmin(remaining,
                      K.sub_eps * chem_timescale<R>(chem, K, rs, cR, cI, nH, N, xHI, xi, T));
@@ -243,70 +356,8 @@ __device__ __forceinline__ int chem_cell(int chem, int nsub, int adaptive, float
         }
         remaining -= h;
         if (it == nsub - 1 || remaining < R(0)) remaining = R(0);
-
-        const R a = cI * K.csig * h;
-        const R nHI = nH * xHI;
-        if (chem == RT_CHEM_FROZEN) {
-            R Nn = N * frcp(R(1) + a * nHI);
-            absorbed += N - Nn;
-            N = Nn;
-            continue;
-        }
-        // photoionisation: remaining photons Nn and neutrals un solve
-        // a un Nn = N - Nn, un - Nn = nHI - N; each root taken in the
-        // cancellation-free form for its sign of aD.  Without photons
-        // nothing is absorbed and xHI is left exactly as it is.
-        const R x0 = xi;
-        R Pd = R(0), xh = xHI;
-        if (N > R(0)) {
-            const R aN = a * N, aH = a * nHI, aD = aH - aN;
-            const R opd = R(1) + aD;
-            const R s = fsqrt(opd * opd + R(4) * aN);
-            R Nn, un;
-            if (aD >= R(0)) {
-                Nn = R(2) * N * frcp(opd + s);
-                un = Nn + (nHI - N);
-            } else {
-                un = R(2) * nHI * frcp((R(1) - aD) + s);
-                Nn = un - (nHI - N);
-            }
-            Nn = rmin(rmax(Nn, R(0)), N);
-            un = rmin(rmax(un, R(0)), nHI);
-            Pd = R(2) * aN * nHI * frcp(R(1) + aN + aH + s);
-            absorbed += N - Nn;
-            N = Nn;
-            xh = un * inv_nH;
-        }
-
-        // recombination (case B) and collisional ionisation:
-        // xn = (xh + A x^2) / (1 + B x); with xh + x = 1 the ionised
-        // fraction after it is x (1 + B - A x) / (1 + B x), taken in that
-        // form when it is the smaller of the two
-        if (!have) rs = rates_f32(float(T), inv15kB);
-        const R x = rmin(x0 + Pd * inv_nH, R(1));
-        const R A = cR * R(rs.alpha) * nH * h, B = R(rs.beta) * nH * h;
-        const R den = frcp(R(1) + B * x);
-        R xn = (xh + A * x * x) * den;
-        R xin;
-        if (xn >= R(0.5)) {
-            xin = rmax(x * (R(1) + B - A * x) * den, R(0));
-            xn = R(1) - xin;
-        } else {
-            xin = R(1) - xn;
-        }
-        xn = rmin(rmax(xn, R(1e-12)), R(1));
-
-        // internal energy 3/2 kB nH (1+x) T: photo-heating, then cooling
-        if (chem == RT_CHEM_FULL) {
-            const R x1 = xin;
-            const R lu = h * nH * (x1 * x1 * cR * R(rs.crb) + x1 * xn * R(rs.cci)) *
-                         frcp((R(1) + x0) * T);
-            const R Tn = ((R(1) + x0) * T + Pd * inv_nH * K.T_h) *
-                         frcp((R(1) + lu) * (R(1) + x1));
-            T = rmax(Tn, K.T_floor);
-        }
-        xHI = xn;
-        xi = rmin(xin, R(1));
+        if (!have) rs = rates_of(T, K);
+        chem_sub<R>(chem, K, rs, cR, cI, nH, inv_nH, h, N, xHI, xi, T, absorbed);
     }
     return it;
 }

@@ -40,7 +40,8 @@ enum Red : int {
     R_FLOOR,       // photons added by the N >= 0 guard (dx^3 folded in)
     R_NONFINITE,   // cells with a non-finite result
     R_FP64,        // cells whose chemistry ran in FP64
-    R_FALLBACK,    // surrogate cells sent to the exact path
+    R_FALLBACK,    // learned-chemistry cells whose prediction was rejected
+    R_LEARNED,     // learned-chemistry cells that kept the prediction
     R_HIST0,       // 8 sub-cycle histogram bins
     NRED = R_HIST0 + 8
 };
@@ -50,12 +51,18 @@ constexpr int ACC_CUR = 0;    // NRED sums of the last step (or initial state)
 constexpr int ACC_CUM = 32;   // NRED cumulative sums over steps
 constexpr int ACC_SIZE = 64;
 constexpr int ACC_TAU = 31;   // ACC_CUM + ACC_TAU: Thomson depth (cumulative)
+static_assert(NRED <= ACC_TAU && ACC_CUM + ACC_TAU < ACC_SIZE, "accumulator layout");
 
 // Subgrid clumping laws: C = 2^(exp log2 nH + l2n), l2n = log2 norm; C_R is
 // bounded below by 1.  on = 0: C_R = C_I = 1.
 struct ClumpLaw {
     int on;
     float cr_exp, cr_l2n, ci_exp, ci_l2n;
+};
+// The same laws for the FP64 chemistry: C = norm nH^exp.
+struct ClumpLawD {
+    int on;
+    double cr_norm, cr_exp, ci_norm, ci_exp;
 };
 
 struct StepArgs {
@@ -75,18 +82,24 @@ struct StepArgs {
     int chem, mixed, adaptive, nsub, any_outflow;
     int hll;                         // 1: HLL fluxes, 0: LF
     int big;                         // 1: 64 x TY_LF tiles (LF forms, large grids)
-    // mixed precision with the exact chemistry (either flux): cells whose
-    // chemistry runs in FP64 are marked in fp64_mask (one bit per cell, one
-    // 64-bit word per x-row of a tile: word (z * ny + y) * ntx + tile x) and
-    // left for launch_defer_chem
-    int defer;
+    // Cells whose chemistry the step leaves to launch_defer_chem are marked
+    // in fp64_mask (one bit per cell, one 64-bit word per x-row of a tile:
+    // word (z * ny + y) * ntx + tile x): in mixed precision the cells with
+    // xHI < xhi_thr (FP64 chemistry), with defer_stiff the cells whose
+    // adaptive operator would take more than one sub-cycle (sub_eps times
+    // the chemistry time scale below dt).  The deferred kernel runs the
+    // learned chemistry on them when surr is set.
+    int defer;                       // mask in use (mixed or defer_stiff)
+    int defer_stiff;
+    int count_hist;                  // sub-cycle histogram counted on the device
     uint64_t *fp64_mask;
     ClumpLaw cl;
+    ClumpLawD cld;
     // FP32 constants
     float c, inv_c, half_c, half_c2, k1, dt, csig, T_h, inv15kB, T_floor,
         sub_eps, xhi_thr;
     // FP64 constants for the FP64 chemistry path and the tallies
-    double dt_d, csig_d, T_h_d, T_floor_d, sub_eps_d, vol, esc_scale;
+    double dt_d, csig_d, T_h_d, T_floor_d, sub_eps_d, inv15kB_d, vol, esc_scale;
     double c_d;                      // c in FP64 (HLL reduced flux 1 - f^2)
     // learned chemistry (surrogate form): packed bf16 forward operands,
     // biases b1|b2|b3|b4 (194 floats), and mu_in[5] sd_in[5] mu_out[2]
@@ -107,6 +120,7 @@ hipError_t launch_step(const StepArgs &a, hipStream_t s);
 int defer_chem_blocks(uint64_t nwords);
 hipError_t launch_defer_chem(const StepArgs &a, uint64_t nwords, int nb2, hipStream_t s);
 ClumpLaw make_clump_law(const rt_params &p);
+ClumpLawD make_clump_law_d(const rt_params &p);
 int inject_host(rt_ctx *c, int64_t n, const int32_t *ijk, const double *ndot);
 hipError_t launch_particle_rates(int64_t n, const double *pos, const double *age_next,
                                  const double *lifetime, const double *q, const double *mass,

@@ -10,10 +10,16 @@
 //     x/y halo whose boundary images (periodic wrap, outflow copy, reflection)
 //     are produced by the loader, so the grid carries no ghost layers;
 //   * planes z-1 and z+1 of the thread's own column stay in registers;
-//   * the unsplit Lax-Friedrichs update, the point sources, the positivity
-//     guards, the sub-cycled chemistry Phi and the FP64 global sums all
+//   * the unsplit Lax-Friedrichs (or HLL) update, the point sources, the
+//     positivity guards, the chemistry Phi and the FP64 global sums all
 //     happen on values already in registers; each cell is read and written
 //     exactly once;
+//   * cells whose chemistry is expensive or needs FP64 -- the stiff cells
+//     of the adaptive and learned forms, the ionised cells of the mixed
+//     form -- are marked in a bit mask and left to a second kernel that
+//     gathers them into dense wavefronts (the network runs there on the
+//     matrix cores), so that the bandwidth-bound sweep never waits on
+//     divergent sub-cycles;
 //   * blocks are renumbered so that each XCD (blockIdx mod 8) receives a
 //     contiguous run of neighbouring tiles and shares their halo rows in its
 //     own L2.
@@ -100,9 +106,8 @@ __device__ __forceinline__ Cell4 load4(const StepArgs &A, uint32_t i, float sx, 
 
 // ------------------------------------------------------ fused step kernel
 // One block per CU.  On large grids the LF forms take 64 x 16 tiles (BIG):
-// 1024 threads at up to 128 VGPRs, four wavefronts per SIMD (their FP64
-// chemistry runs in a second kernel).  Otherwise, and for the HLL and
-// surrogate forms, 64 x 8 tiles: 512 threads at up to 256 VGPRs.
+// 1024 threads at up to 128 VGPRs, four wavefronts per SIMD.  Otherwise, and
+// for the HLL form, 64 x 8 tiles: 512 threads at up to 256 VGPRs.
 #ifndef RT_M1_MINW
 #define RT_M1_MINW 2
 #endif
@@ -110,22 +115,14 @@ __device__ __forceinline__ Cell4 load4(const StepArgs &A, uint32_t i, float sx, 
 #define RT_M1_MINW_LF 4
 #endif
 
-template <bool MIXED, bool SURR, bool HLL, bool BIG>
-__global__ __launch_bounds__(BIG ? NTHREADS_LF : NTHREADS,
-                             BIG ? RT_M1_MINW_LF : (SURR ? 2 : RT_M1_MINW))
+template <bool HLL, bool BIG>
+__global__ __launch_bounds__(BIG ? NTHREADS_LF : NTHREADS, BIG ? RT_M1_MINW_LF : RT_M1_MINW)
 void m1_step_kernel(StepArgs A)
 {
-    static_assert(!BIG || (!SURR && !HLL), "64 x 16 tiles: LF forms only");
+    static_assert(!BIG || !HLL, "64 x 16 tiles: LF forms only");
     constexpr int KTY = BIG ? TY_LF : TY;   // tile rows of this form
     constexpr int KNT = TX * KTY;           // its threads per block
-    // The mixed forms (LF and HLL) leave their FP64 cells to a second, small
-    // kernel (launch_defer_chem): the few waves that would take the FP64
-    // branch here cost every wave registers and scheduling freedom.  (The
-    // surrogate form keeps its exact fallback inline.)
-    constexpr bool DEFER = MIXED && !SURR;
     constexpr int SW = TX + 2;
-    __shared__ __attribute__((aligned(16))) __bf16 s_pk[SURR ? PK_FWD * 8 : 8];
-    __shared__ float s_bias[SURR ? SURR_NBIAS : 1];
     __shared__ float sN[KTY + 2][SW], sFx[KTY + 2][SW], sFy[KTY + 2][SW], sFz[KTY + 2][SW];
     __shared__ float sPxx[KTY + 2][SW], sPyy[KTY + 2][SW], sPxy[KTY + 2][SW];
     __shared__ float sPxz[KTY + 2][SW], sPyz[KTY + 2][SW];
@@ -136,13 +133,6 @@ void m1_step_kernel(StepArgs A)
 
     const int tid = threadIdx.x;
     const int lx = tid & (TX - 1), ly = tid / TX;
-    if (SURR) {
-        // network operands to LDS (read by every plane; the first barrier of
-        // the z loop orders these stores before any use)
-        for (int i = tid; i < PK_FWD; i += KNT)
-            reinterpret_cast<uint4 *>(s_pk)[i] = reinterpret_cast<const uint4 *>(A.surr_pk)[i];
-        for (int i = tid; i < SURR_NBIAS; i += KNT) s_bias[i] = A.surr_bias[i];
-    }
 
     // XCD-aware renumbering: blockIdx mod 8 selects the XCD; each XCD takes
     // a contiguous range of tiles ordered x fastest, so the blocks resident
@@ -214,13 +204,12 @@ void m1_step_kernel(StepArgs A)
     const int wave = tid >> 6;
     if (lx < 8) s_acc[wave][lx] = 0.0;
     double acc_xhi = 0.0, acc_nhxhi = 0.0, acc_N = 0.0, acc_abs = 0.0;
-    int n_bad = 0, n_fp64 = 0, n_fb = 0;
+    int n_bad = 0;
     __shared__ int shist[8];
     if (tid < 8) shist[tid] = 0;
 
-    const ChemK<float> Kf{A.dt, A.dt / float(A.nsub), A.csig, A.T_h, A.T_floor, A.sub_eps};
-    const ChemK<double> Kd{A.dt_d, A.dt_d / double(A.nsub), A.csig_d, A.T_h_d, A.T_floor_d,
-                           A.sub_eps_d};
+    const ChemK<float> Kf{A.dt,      A.dt / float(A.nsub), A.csig,   A.T_h,
+                          A.T_floor, A.sub_eps,            A.inv15kB};
 
     // prologue: plane z0-1 (boundary image if outside), plane z0, plane z0+1
     const Map1 mzm = map_coord(z0 - 1, A.nz, A.bc[4], A.bc[5]);
@@ -264,7 +253,7 @@ void m1_step_kernel(StepArgs A)
     // nx_ld receives plane z+2.  hal: this thread's halo cell of plane z;
     // hal_ld receives plane z+1's.  ch: xHI, T, nH of plane z; ch_ld
     // receives plane z+1's.
-    uint64_t mword = 0;   // DEFER: this lane's plane (z0 + lane) of FP64 cells
+    uint64_t mword = 0;   // A.defer: this lane's plane (z0 + lane) of deferred cells
     auto plane_step = [&](const int z, const Cell4 &nxt_raw, Cell4 &nx_ld, const Cell4 &hal_raw,
                           Cell4 &hal_ld, const float3 &ch, float3 &ch_ld) {
         const float c_xh = ch.x, c_T = ch.y, c_nh = ch.z;
@@ -468,116 +457,43 @@ void m1_step_kernel(StepArgs A)
         }
 
         // per-cell operator Phi
-        float Nn = Nt, xh = c_xh, Tc = c_T;
-        double pabs = 0.0;
+        float Nn = Nt, xh = c_xh, Tc = c_T, pabs = 0.0f;
         int ncyc = 0;
-        bool used64 = false;
-        bool fallback = true;
         bool deferred = false;
-        // Phi leaves a dark, fully neutral cell exactly as it is; a
-        // wavefront of such cells branches around the chemistry entirely
+        // Phi leaves a dark, fully neutral cell as it is, apart from the
+        // temperature floor of the full chemistry; a wavefront of such cells
+        // branches around the chemistry entirely
         const bool dark = !(Nt > 0.0f) && c_xh >= 1.0f;
-        if (SURR && __ballot(!dark) != 0ull) {
-            // learned Phi for the 64 cells of this wavefront (uniform control
-            // flow: every lane takes part in the matrix products)
-            const float *nm = A.surr_norm;
-            const float LOG10_2 = 0.301029995664f;
-            float f[5] = {LOG10_2 * flog2(c_nh), LOG10_2 * flog2(rmax(c_xh, 1e-30f)),
-                          LOG10_2 * flog2(c_T), LOG10_2 * flog2(rmax(Nt, 1e-30f)), A.log10_dt};
-            bool ood = !(c_nh > 0.0f && c_T > 0.0f);
-            float sv[5];
-#pragma unroll
-            for (int k = 0; k < 5; ++k) {
-                ood = ood || !(f[k] >= nm[14 + k] && f[k] <= nm[19 + k]);
-                sv[k] = (f[k] - nm[k]) * frcp(nm[5 + k]);
-            }
-            const int lane = tid & 63;
-            bf16x8 xa, xb;
-#pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                xa[k] = (__bf16)0.0f;
-                xb[k] = (__bf16)0.0f;
-            }
-#pragma unroll
-            for (int k = 0; k < 5; ++k) {
-                const float up = __shfl(sv[k], (lane + 32) & 63);
-                if (lane < 32) {
-                    xa[k] = (__bf16)sv[k];
-                    xb[k] = (__bf16)up;
-                }
-            }
-            const MlpBias mb{s_bias, s_bias + 64, s_bias + 128, s_bias + 192};
-            const bf16x8 *spk = reinterpret_cast<const bf16x8 *>(s_pk);
-            MlpFwd unused;
-            float ya0, ya1, yb0, yb1;
-            mlp_forward32<false>(spk, mb, xa, unused, ya0, ya1);
-            mlp_forward32<false>(spk, mb, xb, unused, yb0, yb1);
-            const float sb0 = __shfl(yb0, lane & 31), sb1 = __shfl(yb1, lane & 31);
-            const float y0 = lane < 32 ? ya0 : sb0, y1 = lane < 32 ? ya1 : sb1;
-            // decode: the network predicts u = asinh(d / 1e-3) for the
-            // changes d = log10(xHI'/xHI) and log10(T'/T); d = 1e-3 sinh u
-            auto change = [](float u) {
-                const float e = fexp2(u * 1.4426950408889634f);
-                return 0.5e-3f * (e - frcp(e));
-            };
-            const float dx0 = change(y0 * nm[12] + nm[10]);
-            const float dT0 = change(y1 * nm[13] + nm[11]);
-            const float xs = fexp2((f[1] + dx0) * 3.321928094887362f);
-            float Ts = fexp2((f[2] + dT0) * 3.321928094887362f);
-            if (A.chem != RT_CHEM_FULL) Ts = c_T;
-            // photons absorbed over dt: net ionisations + recombinations -
-            // collisional ionisations at the predicted end state
-            const RateSet rs = rates_f32(Ts, A.inv15kB);
-            float sR, sI;
-            clump_f32(A.cl, c_nh, sR, sI);
-            const float x1 = 1.0f - xs, x0 = 1.0f - c_xh;
-            const float nh2dt = c_nh * c_nh * A.dt;
-            float Ph = c_nh * (c_xh - xs) + sR * rs.alpha * nh2dt * x1 * x1 -
-                       rs.beta * nh2dt * x1 * xs;
-            Ph = rmin(rmax(Ph, 0.0f), Nt);
-            const float Ns = Nt - Ph;
-            // backward-Euler residuals of one step dt at the predicted end
-            const float inv_nh = frcp(c_nh);
-            const float rx = fabsf(Ph - sI * A.csig * A.dt * Ns * c_nh * xs) * inv_nh;
-            float rT = 0.0f;
-            if (A.chem == RT_CHEM_FULL) {
-                const float lu = A.dt * c_nh * (x1 * x1 * sR * rs.crb + x1 * xs * rs.cci) *
-                                 frcp((1.0f + x1) * Ts);
-                const float TBE = ((1.0f + x0) * c_T + Ph * inv_nh * A.T_h) *
-                                  frcp((1.0f + lu) * (1.0f + x1));
-                rT = fabsf(Ts - TBE) * frcp(Ts);
-            }
-            const bool ok = A.chem == RT_CHEM_FULL && !dark && !ood && xs >= 1e-12f && xs <= 1.0f &&
-                            Ts >= A.T_floor && isfinite(Ts) && rx <= A.surr_tol &&
-                            rT <= A.surr_tol;
-            if (ok) {
-                fallback = false;
-                Nn = Ns;
-                xh = xs;
-                Tc = Ts;
-                pabs = Ph;
-            }
-        }
-        if (A.chem != RT_CHEM_OFF && fallback && !dark) {
-            if (DEFER && c_xh < A.xhi_thr) {
-                deferred = true;   // N, F leave transported; xHI, T as they are
-            } else if (MIXED && !DEFER && c_xh < A.xhi_thr) {
-                double Nd = Nt, xd = c_xh, Td = c_T, ad = 0.0;
+        if (A.chem != RT_CHEM_OFF) {
+            if (dark) {
+                if (A.chem == RT_CHEM_FULL) Tc = rmax(c_T, A.T_floor);
+            } else if (A.mixed && c_xh < A.xhi_thr) {
+                deferred = true;   // FP64 chemistry, in the deferred kernel
+            } else {
                 float cR, cI;
                 clump_f32(A.cl, c_nh, cR, cI);
-                ncyc = chem_cell<double>(A.chem, A.nsub, A.adaptive, A.inv15kB, Kd, double(cR),
-                                         double(cI), double(c_nh), Nd, xd, Td, ad);
-                Nn = float(Nd);
-                xh = float(xd);
-                Tc = float(Td);
-                pabs = ad;
-                used64 = true;
-            } else {
-                float af = 0.0f, cR, cI;
-                clump_f32(A.cl, c_nh, cR, cI);
-                ncyc = chem_cell<float>(A.chem, A.nsub, A.adaptive, A.inv15kB, Kf, cR, cI, c_nh,
-                                        Nn, xh, Tc, af);
-                pabs = af;
+                if (A.defer_stiff) {
+                    // the adaptive operator's first sub-cycle: if it spans the
+                    // step, this is the whole of Phi; otherwise the cell is
+                    // stiff and goes to the deferred kernel
+                    const RateSet rs = rates_f32(c_T, A.inv15kB);
+                    const float tc = chem_timescale<float>(A.chem, Kf, rs, cR, cI, c_nh, Nt,
+                                                           c_xh, 1.0f - c_xh, c_T);
+                    if (A.sub_eps * tc < A.dt) {
+                        deferred = true;
+                    } else if (A.adaptive || A.nsub == 1) {
+                        float xi = 1.0f - c_xh;
+                        chem_sub<float>(A.chem, Kf, rs, cR, cI, c_nh, frcp(c_nh), A.dt, Nn, xh,
+                                        xi, Tc, pabs);
+                        ncyc = 1;
+                    } else {
+                        ncyc = chem_cell<float>(A.chem, A.nsub, 0, Kf, cR, cI, c_nh, Nn, xh, Tc,
+                                                pabs);
+                    }
+                } else {
+                    ncyc = chem_cell<float>(A.chem, A.nsub, A.adaptive, Kf, cR, cI, c_nh, Nn, xh,
+                                            Tc, pabs);
+                }
             }
         }
         if (A.chem != RT_CHEM_OFF && !deferred) {
@@ -599,7 +515,7 @@ void m1_step_kernel(StepArgs A)
             store_out(active ? &A.xHI[i] : sink, xh);
             store_out(active ? &A.T[i] : sink, Tc);
         }
-        if constexpr (DEFER) {
+        if (A.defer) {
             // the word of plane z is kept by lane z - z0 and stored after
             // the march: no store here to disturb the waits for the
             // prefetched loads
@@ -614,14 +530,12 @@ void m1_step_kernel(StepArgs A)
                   0.0f * c_T + 0.0f * c_nh;
             const bool fin = z0 == 0.0f;
             n_bad += fin ? 0 : 1;
-            n_fp64 += used64 ? 1 : 0;
-            n_fb += (SURR && fallback && !dark && A.chem != RT_CHEM_OFF) ? 1 : 0;
         }
         if (active && !deferred) {
             acc_xhi += double(xh);
             acc_nhxhi = fma(double(c_nh), double(xh), acc_nhxhi);
             acc_N += double(Nn);
-            acc_abs += pabs;
+            acc_abs += double(pabs);
         }
         {
             if (A.any_outflow) {
@@ -637,12 +551,11 @@ void m1_step_kernel(StepArgs A)
                 if (lx == 0) s_acc[wave][5] += f;
             }
         }
-        if ((A.adaptive || SURR) && A.chem != RT_CHEM_OFF) {
+        if (A.count_hist && A.chem != RT_CHEM_OFF) {
             const int bin = hist_bin(ncyc);
 #pragma unroll
             for (int hb = 0; hb < 8; ++hb) {
-                const unsigned long long m =
-                    __ballot(active && fallback && !deferred && bin == hb);
+                const unsigned long long m = __ballot(active && !deferred && bin == hb);
                 if (lx == 0 && m) atomicAdd(&shist[hb], __popcll(m));
             }
         }
@@ -658,22 +571,11 @@ void m1_step_kernel(StepArgs A)
         }
     };
 
-    if constexpr (SURR) {
-        // the surrogate forms need their registers for the network: no
-        // unrolling, the prefetched set is copied forward every plane
-        for (int z = z0; z < z1; ++z) {
-            plane_step(z, nx1, nx0, ha0, ha1, ch0, ch1);
-            nx1 = nx0;
-            ha0 = ha1;
-            ch0 = ch1;
-        }
-    } else {
-        for (int z = z0; z < z1; z += 2) {
-            plane_step(z, nx1, nx0, ha0, ha1, ch0, ch1);
-            if (z + 1 < z1) plane_step(z + 1, nx0, nx1, ha1, ha0, ch1, ch0);
-        }
+    for (int z = z0; z < z1; z += 2) {
+        plane_step(z, nx1, nx0, ha0, ha1, ch0, ch1);
+        if (z + 1 < z1) plane_step(z + 1, nx0, nx1, ha1, ha0, ch1, ch0);
     }
-    if constexpr (DEFER) {
+    if (A.defer) {
         // one x-row per wave, the chunk's planes z0 .. z1-1 one per lane
         // (chunks are at most 64 planes)
         if (gy < A.ny && z0 + lx < z1)
@@ -693,12 +595,9 @@ void m1_step_kernel(StepArgs A)
     }
 
     // block reduction of the partial sums (fixed order, FP64)
-    double v[3] = {double(n_bad), double(n_fp64), double(n_fb)};
+    double v[1] = {double(n_bad)};
 #pragma unroll
-    for (int j = 0; j < 3; ++j) {
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) v[j] += __shfl_xor(v[j], off);
-    }
+    for (int off = 32; off > 0; off >>= 1) v[0] += __shfl_xor(v[0], off);
     if (lx == 0) {
         sred[wave][R_XHI] = s_acc[wave][0];
         sred[wave][R_NHXHI] = s_acc[wave][1];
@@ -708,8 +607,9 @@ void m1_step_kernel(StepArgs A)
         sred[wave][R_ESC] = s_acc[wave][4] * A.esc_scale;
         sred[wave][R_FLOOR] = s_acc[wave][5] * A.vol;
         sred[wave][R_NONFINITE] = v[0];
-        sred[wave][R_FP64] = v[1];
-        sred[wave][R_FALLBACK] = v[2];
+        sred[wave][R_FP64] = 0.0;       // FP64 cells are all deferred
+        sred[wave][R_FALLBACK] = 0.0;   // so are the learned chemistry's cells
+        sred[wave][R_LEARNED] = 0.0;
     }
     __syncthreads();
     if (tid < NRED) {
@@ -724,55 +624,178 @@ void m1_step_kernel(StepArgs A)
     }
 }
 
-// ---------------------------------- deferred FP64 chemistry (mixed forms)
+// ------------------------------------------- deferred chemistry (dense)
 // The cells the step marked in fp64_mask hold their transported N, F in the
 // next buffer and their step-start xHI, T.  Each wavefront reads 64 mask
-// words at a time (one per lane) and then takes the non-empty ones in turn,
-// its lanes being the 64 cells of the word's tile row: Phi in FP64, F scaled
-// by the photons left, and the cell's share of the sums that the step left
-// out, reduced per block in a fixed order.
+// words at a time (one per lane), gathers the marked cells of those 64 tile
+// rows into a list in LDS and then takes them 64 at a time, one per lane,
+// so that every lane of every batch works: the learned chemistry on the
+// matrix cores (SURR, full chemistry only) with its photon accounting and
+// acceptance test, and the exact operator Phi -- FP64 for the cells below
+// the mixed form's threshold, FP32 otherwise -- for the cells it does not
+// accept.  F is scaled by the photons left; the cell's share of the sums
+// that the step left out is reduced per block in a fixed order.
 constexpr int DEFER_THREADS = 256, DEFER_MAX_BLOCKS = 8192;
+constexpr int DEFER_WAVES = DEFER_THREADS / 64;
 
+// Learned chemistry of one cell from the network's standardised outputs
+// (y0, y1): the predicted end state, the photons it absorbs (net
+// ionisations + recombinations - collisional ionisations over dt at that
+// state, so the photon budget stays exact) and the acceptance test: one
+// backward-Euler step of length dt with every rate frozen at the predicted
+// state (photoionisation by the photons left, case-B recombination,
+// collisional ionisation and cooling at T') must land within surr_tol of
+// the prediction (absolute in xHI, relative in T); the features must lie in
+// the training range and the end state inside its bounds.  f: the raw log10
+// features.  Returns true if accepted.
+__device__ __forceinline__ bool surr_accept(const StepArgs &A, const float f[5], bool ood,
+                                            float y0, float y1, float Nt, float c_xh, float c_T,
+                                            float c_nh, float sR, float sI, float &Ns,
+                                            float &xs, float &Ts, float &Ph)
+{
+    const float *nm = A.surr_norm;
+    // the network predicts u = asinh(d / 1e-3) of the changes d of log10
+    // xHI and log10 T; d = 1e-3 sinh u
+    auto change = [](float u) {
+        const float e = fexp2(u * 1.4426950408889634f);
+        return 0.5e-3f * (e - frcp(e));
+    };
+    const float dx0 = change(y0 * nm[12] + nm[10]);
+    const float dT0 = change(y1 * nm[13] + nm[11]);
+    xs = fexp2((f[1] + dx0) * 3.321928094887362f);
+    Ts = fexp2((f[2] + dT0) * 3.321928094887362f);
+    const RateSet rs = rates_f32(Ts, A.inv15kB);
+    const float x1 = 1.0f - xs, x0 = 1.0f - c_xh;
+    const float nh2dt = c_nh * c_nh * A.dt;
+    Ph = c_nh * (c_xh - xs) + sR * rs.alpha * nh2dt * x1 * x1 - rs.beta * nh2dt * x1 * xs;
+    Ph = rmin(rmax(Ph, 0.0f), Nt);
+    Ns = Nt - Ph;
+    const float inv_nh = frcp(c_nh);
+    const float xBE = (c_xh + sR * rs.alpha * c_nh * A.dt * x1 * x1) *
+                      frcp(1.0f + sI * A.csig * A.dt * Ns + rs.beta * c_nh * A.dt * x1);
+    const float rx = fabsf(xs - xBE);
+    const float lu = A.dt * c_nh * (x1 * x1 * sR * rs.crb + x1 * xs * rs.cci) *
+                     frcp((1.0f + x1) * Ts);
+    const float TBE = ((1.0f + x0) * c_T + Ph * inv_nh * A.T_h) * frcp((1.0f + lu) * (1.0f + x1));
+    const float rT = fabsf(Ts - TBE) * frcp(Ts);
+    return !ood && xs >= 1e-12f && xs <= 1.0f && Ts >= A.T_floor && isfinite(Ts) &&
+           rx <= A.surr_tol && rT <= A.surr_tol;
+}
+
+template <bool SURR>
 __global__ __launch_bounds__(DEFER_THREADS) void defer_chem_kernel(StepArgs A, uint64_t nwords)
 {
-    __shared__ double sred[DEFER_THREADS / 64][NRED];
+    __shared__ uint16_t s_list[DEFER_WAVES][64 * 64];
+    __shared__ __attribute__((aligned(16))) __bf16 s_pk[SURR ? PK_FWD * 8 : 8];
+    __shared__ float s_bias[SURR ? SURR_NBIAS : 1];
+    __shared__ double sred[DEFER_WAVES][NRED];
     __shared__ int shist[8];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     if (tid < 8) shist[tid] = 0;
+    if constexpr (SURR) {
+        for (int i = tid; i < PK_FWD; i += DEFER_THREADS)
+            reinterpret_cast<uint4 *>(s_pk)[i] = reinterpret_cast<const uint4 *>(A.surr_pk)[i];
+        for (int i = tid; i < SURR_NBIAS; i += DEFER_THREADS) s_bias[i] = A.surr_bias[i];
+    }
     __syncthreads();
-    const ChemK<double> Kd{A.dt_d, A.dt_d / double(A.nsub), A.csig_d, A.T_h_d, A.T_floor_d,
-                           A.sub_eps_d};
+    const ChemK<double> Kd{A.dt_d,      A.dt_d / double(A.nsub), A.csig_d,   A.T_h_d,
+                           A.T_floor_d, A.sub_eps_d,             A.inv15kB_d};
+    const ChemK<float> Kf{A.dt,      A.dt / float(A.nsub), A.csig,   A.T_h,
+                          A.T_floor, A.sub_eps,            A.inv15kB};
+    const bool use_net = SURR && A.chem == RT_CHEM_FULL;
     double acc_xhi = 0.0, acc_nhxhi = 0.0, acc_N = 0.0, acc_abs = 0.0;
-    int n_bad = 0, n_fp64 = 0;
-    const uint64_t waves = uint64_t(gridDim.x) * (DEFER_THREADS / 64);
-    for (uint64_t base = (uint64_t(blockIdx.x) * (DEFER_THREADS / 64) + wave) * 64;
-         base < nwords; base += waves * 64) {
+    int n_bad = 0, n_fp64 = 0, n_fb = 0, n_net = 0;
+    uint16_t *list = s_list[wave];
+    const uint64_t waves = uint64_t(gridDim.x) * DEFER_WAVES;
+    for (uint64_t base = (uint64_t(blockIdx.x) * DEFER_WAVES + wave) * 64; base < nwords;
+         base += waves * 64) {
         const uint64_t mine = base + lane < nwords ? A.fp64_mask[base + lane] : 0ull;
-        unsigned long long todo = __ballot(mine != 0ull);
-        while (todo) {
-            const int src = __builtin_ctzll(todo);
-            todo &= todo - 1ull;
-            const uint32_t lo = __shfl(uint32_t(mine), src), hi = __shfl(uint32_t(mine >> 32), src);
-            const uint64_t m = (uint64_t(hi) << 32) | lo;
-            const uint64_t w = base + src;
+        // gather the marked cells: (word - base) << 6 | bit, in word order
+        const int cnt = __popcll(mine);
+        int incl = cnt;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const int v = __shfl_up(incl, off);
+            if (lane >= off) incl += v;
+        }
+        const int total = __shfl(incl, 63);
+        int pos = incl - cnt;
+        for (uint64_t m = mine; m; m &= m - 1ull)
+            list[pos++] = uint16_t((lane << 6) | __builtin_ctzll(m));
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        for (int b0 = 0; b0 < total; b0 += 64) {
+            const bool valid = b0 + lane < total;
+            const int e = valid ? int(list[b0 + lane]) : 0;
+            const uint64_t w = base + uint64_t(e >> 6);
             const int itx = int(w % uint64_t(A.ntx));
             const uint64_t row = w / uint64_t(A.ntx);
             const int y = int(row % uint64_t(A.ny)), z = int(row / uint64_t(A.ny));
-            const int x = itx * TX + lane;
+            const int x = itx * TX + (e & 63);
+            const uint32_t i = (uint32_t(z) * uint32_t(A.ny) + uint32_t(y)) * uint32_t(A.nx) +
+                               uint32_t(x);
+            float Nt = 0.0f, Fx = 0.0f, Fy = 0.0f, Fz = 0.0f;
+            float c_xh = 1.0f, c_T = 1.0e4f, c_nh = 1.0f;
+            if (valid) {
+                Nt = A.No[i];
+                Fx = A.Fxo[i];
+                Fy = A.Fyo[i];
+                Fz = A.Fzo[i];
+                c_xh = A.xHI[i];
+                c_T = A.T[i];
+                c_nh = A.nH[i];
+            }
+            float cR, cI;
+            clump_f32(A.cl, c_nh, cR, cI);
+            float Nn = Nt, xh = c_xh, Tc = c_T, pab = 0.0f;
+            double pabs = 0.0;
+            bool ok = false, used64 = false;
             int ncyc = 0;
-            const bool mark = (m >> lane) & 1ull;
-            if (mark) {
-                const uint32_t i = (uint32_t(z) * uint32_t(A.ny) + uint32_t(y)) * uint32_t(A.nx) +
-                                   uint32_t(x);
-                const float Nt = A.No[i];
-                float Fx = A.Fxo[i], Fy = A.Fyo[i], Fz = A.Fzo[i];
-                const float c_xh = A.xHI[i], c_T = A.T[i], c_nh = A.nH[i];
-                double Nd = Nt, xd = c_xh, Td = c_T, ad = 0.0;
-                float cR, cI;
-                clump_f32(A.cl, c_nh, cR, cI);
-                ncyc = chem_cell<double>(A.chem, A.nsub, A.adaptive, A.inv15kB, Kd, double(cR),
-                                         double(cI), double(c_nh), Nd, xd, Td, ad);
-                const float Nn = float(Nd), xh = float(xd), Tc = float(Td);
+            if (use_net) {
+                const float *nm = A.surr_norm;
+                const float LOG10_2 = 0.301029995664f;
+                float f[5] = {LOG10_2 * flog2(c_nh), LOG10_2 * flog2(rmax(c_xh, 1e-30f)),
+                              LOG10_2 * flog2(c_T), LOG10_2 * flog2(rmax(Nt, 1e-30f)),
+                              A.log10_dt};
+                bool ood = !(c_nh > 0.0f && c_T > 0.0f);
+                float sv[5];
+#pragma unroll
+                for (int k = 0; k < 5; ++k) {
+                    ood = ood || !(f[k] >= nm[14 + k] && f[k] <= nm[19 + k]);
+                    sv[k] = valid ? (f[k] - nm[k]) * frcp(nm[5 + k]) : 0.0f;
+                }
+                const MlpBias mb{s_bias, s_bias + 64, s_bias + 128, s_bias + 192};
+                float y0, y1;
+                mlp_predict64(reinterpret_cast<const bf16x8 *>(s_pk), mb, sv, y0, y1);
+                float Ns, xs, Ts, Ph;
+                ok = valid && surr_accept(A, f, ood, y0, y1, Nt, c_xh, c_T, c_nh, cR, cI, Ns, xs,
+                                          Ts, Ph);
+                if (ok) {
+                    Nn = Ns;
+                    xh = xs;
+                    Tc = Ts;
+                    pabs = Ph;
+                }
+            }
+            if (valid && !ok) {
+                if (A.mixed && c_xh < A.xhi_thr) {
+                    double Nd = Nt, xd = c_xh, Td = c_T, ad = 0.0, dR, dI;
+                    clump_f64(A.cld, double(c_nh), dR, dI);
+                    ncyc = chem_cell<double>(A.chem, A.nsub, A.adaptive, Kd, dR, dI,
+                                             double(c_nh), Nd, xd, Td, ad);
+                    Nn = float(Nd);
+                    xh = float(xd);
+                    Tc = float(Td);
+                    pabs = ad;
+                    used64 = true;
+                } else {
+                    ncyc = chem_cell<float>(A.chem, A.nsub, A.adaptive, Kf, cR, cI, c_nh, Nn, xh,
+                                            Tc, pab);
+                    pabs = pab;
+                }
+            }
+            if (valid) {
                 const float sc = (Nt > N_TINY) ? rmin(Nn * frcp(Nt), 1.0f) : 0.0f;
                 Fx *= sc;
                 Fy *= sc;
@@ -786,25 +809,28 @@ __global__ __launch_bounds__(DEFER_THREADS) void defer_chem_kernel(StepArgs A, u
                 float z0v = 0.0f * Nn + 0.0f * Fx + 0.0f * Fy + 0.0f * Fz + 0.0f * xh + 0.0f * Tc;
                 z0v += 0.0f * Nt + 0.0f * c_xh + 0.0f * c_T + 0.0f * c_nh;
                 n_bad += z0v == 0.0f ? 0 : 1;
-                n_fp64 += 1;
+                n_fp64 += used64 ? 1 : 0;
+                n_fb += (use_net && !ok) ? 1 : 0;
+                n_net += ok ? 1 : 0;
                 acc_xhi += double(xh);
                 acc_nhxhi = fma(double(c_nh), double(xh), acc_nhxhi);
                 acc_N += double(Nn);
-                acc_abs += ad;
+                acc_abs += pabs;
             }
-            if (A.adaptive) {
+            if (A.count_hist) {
                 const int bin = hist_bin(ncyc);
 #pragma unroll
                 for (int hb = 0; hb < 8; ++hb) {
-                    const unsigned long long hm = __ballot(mark && bin == hb);
+                    const unsigned long long hm = __ballot(valid && bin == hb);
                     if (lane == 0 && hm) atomicAdd(&shist[hb], __popcll(hm));
                 }
             }
         }
     }
-    double v[6] = {acc_xhi, acc_nhxhi, acc_N, acc_abs, double(n_bad), double(n_fp64)};
+    double v[8] = {acc_xhi, acc_nhxhi, acc_N, acc_abs, double(n_bad), double(n_fp64),
+                   double(n_fb), double(n_net)};
 #pragma unroll
-    for (int j = 0; j < 6; ++j) {
+    for (int j = 0; j < 8; ++j) {
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) v[j] += __shfl_xor(v[j], off);
     }
@@ -817,13 +843,15 @@ __global__ __launch_bounds__(DEFER_THREADS) void defer_chem_kernel(StepArgs A, u
         sred[wave][R_ABS] = v[3] * A.vol;
         sred[wave][R_NONFINITE] = v[4];
         sred[wave][R_FP64] = v[5];
+        sred[wave][R_FALLBACK] = v[6];
+        sred[wave][R_LEARNED] = v[7];
     }
     __syncthreads();
     if (tid < NRED) {
         double s = 0.0;
         if (tid < R_HIST0) {
 #pragma unroll
-            for (int w = 0; w < DEFER_THREADS / 64; ++w) s += sred[w][tid];
+            for (int w = 0; w < DEFER_WAVES; ++w) s += sred[w][tid];
         } else {
             s = double(shist[tid - R_HIST0]);
         }
@@ -839,7 +867,12 @@ int defer_chem_blocks(uint64_t nwords)
 
 hipError_t launch_defer_chem(const StepArgs &a, uint64_t nwords, int nb2, hipStream_t s)
 {
-    hipLaunchKernelGGL(defer_chem_kernel, dim3(nb2), dim3(DEFER_THREADS), 0, s, a, nwords);
+    if (a.surr)
+        hipLaunchKernelGGL(defer_chem_kernel<true>, dim3(nb2), dim3(DEFER_THREADS), 0, s, a,
+                           nwords);
+    else
+        hipLaunchKernelGGL(defer_chem_kernel<false>, dim3(nb2), dim3(DEFER_THREADS), 0, s, a,
+                           nwords);
     return hipGetLastError();
 }
 
@@ -973,28 +1006,12 @@ int state_sums_blocks(uint32_t ncell)
 hipError_t launch_step(const StepArgs &a, hipStream_t s)
 {
     const dim3 g(a.nblocks), b(a.big ? NTHREADS_LF : NTHREADS);
-    // the learned chemistry runs with the LF flux only (rejected on the host)
-    if (a.surr) {
-        if (a.mixed)
-            hipLaunchKernelGGL((m1_step_kernel<true, true, false, false>), g, b, 0, s, a);
-        else
-            hipLaunchKernelGGL((m1_step_kernel<false, true, false, false>), g, b, 0, s, a);
-    } else if (a.hll) {
-        if (a.mixed)
-            hipLaunchKernelGGL((m1_step_kernel<true, false, true, false>), g, b, 0, s, a);
-        else
-            hipLaunchKernelGGL((m1_step_kernel<false, false, true, false>), g, b, 0, s, a);
-    } else if (a.big) {
-        if (a.mixed)
-            hipLaunchKernelGGL((m1_step_kernel<true, false, false, true>), g, b, 0, s, a);
-        else
-            hipLaunchKernelGGL((m1_step_kernel<false, false, false, true>), g, b, 0, s, a);
-    } else {
-        if (a.mixed)
-            hipLaunchKernelGGL((m1_step_kernel<true, false, false, false>), g, b, 0, s, a);
-        else
-            hipLaunchKernelGGL((m1_step_kernel<false, false, false, false>), g, b, 0, s, a);
-    }
+    if (a.hll)
+        hipLaunchKernelGGL((m1_step_kernel<true, false>), g, b, 0, s, a);
+    else if (a.big)
+        hipLaunchKernelGGL((m1_step_kernel<false, true>), g, b, 0, s, a);
+    else
+        hipLaunchKernelGGL((m1_step_kernel<false, false>), g, b, 0, s, a);
     return hipGetLastError();
 }
 

@@ -52,16 +52,42 @@ def features(torch, nH, N, xHI, T, dt):
                         torch.log10(N.clamp_min(FLOOR)), torch.log10(dt)], dim=1)
 
 
-def exact_pairs(params, nH, N, xHI, T, dt, nsub):
+def exact_pairs(params, nH, N, xHI, T, dt, nsub, ncycles=None):
     """Apply the exact operator to copies of the given cells (device tensors);
-    returns (X raw features, Y raw targets, N after)."""
+    returns (X raw features, Y raw targets, N after).  ncycles (device
+    int32, optional) receives the sub-cycles each cell took."""
     import torch
 
     N1, x1, T1 = N.clone(), xHI.clone(), T.clone()
-    rt.check(rt.rt_chem_apply(params, nH, N1, x1, T1, dt, nsub), "rt_chem_apply")
+    rt.check(rt.rt_chem_apply(params, nH, N1, x1, T1, dt, nsub, ncycles), "rt_chem_apply")
     X = features(torch, nH, N, xHI, T, dt)
     Y = torch.stack([torch.log10(x1.clamp_min(FLOOR)), torch.log10(T1)], dim=1)
     return X, Y, N1
+
+
+def candidate_pairs(params, cells: dict, dt: float, n_keep: int, nsub: int = 64,
+                    fp64_thr: float = 0.0, seed: int = 0):
+    """Exact pairs weighted towards the cells the step asks the network for.
+    The exact adaptive operator `params` (at most nsub sub-cycles) runs on
+    every sampled cell; the stiff ones (more than one sub-cycle) and those
+    below fp64_thr are all kept, the others fill the rest of n_keep at
+    random.  Returns (X, Y, number of stiff-or-FP64 pairs kept)."""
+    import torch
+
+    n = cells["N"].numel()
+    dev = cells["N"].device
+    ncyc = torch.zeros(n, dtype=torch.int32, device=dev)
+    X, Y, _ = exact_pairs(params, cells["nH"], cells["N"], cells["xHI"], cells["T"],
+                          torch.full_like(cells["N"], dt), nsub, ncyc)
+    hard = (ncyc > 1) | (cells["xHI"] < fp64_thr)
+    idx_hard = torch.nonzero(hard).reshape(-1)[:n_keep]
+    idx_easy = torch.nonzero(~hard).reshape(-1)
+    g = torch.Generator(device=dev)
+    g.manual_seed(seed)
+    m = max(0, min(n_keep - idx_hard.numel(), idx_easy.numel()))
+    pick = idx_easy[torch.randperm(idx_easy.numel(), generator=g, device=dev)[:m]]
+    idx = torch.cat([idx_hard, pick])
+    return X[idx], Y[idx], int(idx_hard.numel())
 
 
 def sample_cells(state: dict, n: int, seed: int, lit_fraction: float = 0.8):

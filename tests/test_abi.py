@@ -51,6 +51,7 @@ int main(void) {
   printf("%zu %zu %zu %zu\n", offsetof(rt_params, dx_cm), offsetof(rt_params, xhi_fp64_thr),
          offsetof(rt_reductions, steps), offsetof(rt_reductions, subcycle_hist));
   printf("%zu %zu\n", offsetof(rt_fields, xHI), offsetof(rt_fields, nH));
+  printf("%zu %zu\n", offsetof(rt_reductions, tau_e), offsetof(rt_reductions, n_learned));
   return 0;
 }
 '''
@@ -69,7 +70,8 @@ def test_struct_layouts_match_header(tmp_path):
            ctypes.sizeof(rt.rt_reductions),
            rt.rt_params.dx_cm.offset, rt.rt_params.xhi_fp64_thr.offset,
            rt.rt_reductions.steps.offset, rt.rt_reductions.subcycle_hist.offset,
-           rt.rt_fields.xHI.offset, rt.rt_fields.nH.offset]
+           rt.rt_fields.xHI.offset, rt.rt_fields.nH.offset,
+           rt.rt_reductions.tau_e.offset, rt.rt_reductions.n_learned.offset]
     assert got == want
 
 

@@ -145,15 +145,26 @@ def test_hll_differs_from_lf():
     assert np.max(np.abs(outs[0] - outs[1])) > 1e-2 * np.max(outs[0])
 
 
-def test_surrogate_is_refused_with_hll():
+def test_surrogate_runs_with_hll():
+    """The learned chemistry runs in the deferred kernel, after either flux:
+    with the chemistry off it changes nothing, with it on the HLL step still
+    closes the photon budget."""
     shape = (8, 8, 64)
     st = W.random_state(shape, seed=1)
     theta = torch.zeros(rt.MLP_NPARAM, dtype=torch.float32, device="cuda")
     norm = [0.0] * 5 + [1.0] * 5 + [0.0, 0.0, 1.0, 1.0] + [-40.0] * 5 + [40.0] * 5
-    rcs = {}
-    for flux in (rt.FLUX_LF, HLL):
-        G = rt.RTGrid(rt.make_params(shape, DX, flux=flux), st)
-        rcs[flux] = rt.rt_set_surrogate(G.ctx, theta, norm, 1e-2)
-        G.close()
-    assert rcs[rt.FLUX_LF] == rt.RT_OK
-    assert rcs[HLL] == rt.RT_E_ARG
+    outs = []
+    for chem in (rt.CHEM_OFF, rt.CHEM_FULL):
+        for surr in (False, True):
+            G = rt.RTGrid(rt.make_params(shape, DX, flux=HLL, chem=chem), st)
+            if surr:
+                rt.check(rt.rt_set_surrogate(G.ctx, theta, norm, 1e-2), "rt_set_surrogate")
+            G.step(DT, 1)
+            red = G.reduce()
+            outs.append(G.state_numpy())
+            G.close()
+            lhs = red["photons_initial"] + red["photons_emitted"] + red["photons_floor"]
+            rhs = red["photons_stored"] + red["photons_absorbed"] + red["photons_escaped"]
+            assert rhs == pytest.approx(lhs, rel=1e-5)
+    for k in outs[0]:
+        assert np.array_equal(outs[0][k], outs[1][k]), k

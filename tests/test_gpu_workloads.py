@@ -16,7 +16,6 @@
     sources), the oracle stepping each from the library's input state; with
     the LF fluxes and with HLL."""
 
-import os
 
 import numpy as np
 import pytest
@@ -123,8 +122,6 @@ def test_cosmological_trajectory_error_64():
     assert_parity(e, tol=dict(N=1e-3, F=1e-3, xHI=1e-2, T=1e-2), what="trajectory")
 
 
-@pytest.mark.skipif(not os.environ.get("RT_LONG_TESTS"),
-                    reason="minutes of FP64 oracle time; set RT_LONG_TESTS=1")
 @pytest.mark.timeout(1200)
 def test_cosmo256_per_field_error_after_500_steps():
     w = W.workload("cosmo256")

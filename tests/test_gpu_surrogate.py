@@ -122,20 +122,28 @@ def test_fused_surrogate_step_matches_batch_network(run64, trained):
                               ex["x"], ex["T"], torch.full_like(nH, dt), 1), "rt_chem_apply")
     torch.cuda.synchronize()
     is_exact = (got == ex["x"]) & (out["T"].reshape(-1) == ex["T"])
-    # dark fully neutral cells are left unchanged by both paths and are not
-    # counted as fallbacks
+    # dark fully neutral cells are left unchanged by both paths; with
+    # sub_eps = 0 every other cell is offered to the network, which either
+    # keeps its prediction or falls back to the exact operator
     dark = (Nt.reshape(-1) == 0) & (xHI0 >= 1)
+    n_lit = int((~dark).sum())
+    assert red["n_learned"] + red["n_fallback"] == n_lit, (red["n_learned"],
+                                                           red["n_fallback"], n_lit)
+    # a cell whose result differs from the exact operator's kept the
+    # network's prediction (a kept prediction may also coincide with it, on
+    # cells the step barely changes), and agrees with the batch network
     net = ~is_exact
     n_net = int(net.sum())
-    assert red["n_fallback"] == pytest.approx(int((is_exact & ~dark).sum()),
-                                              abs=int(0.001 * got.numel()) + 5)
+    assert n_net <= red["n_learned"]
+    assert red["n_fallback"] <= int((is_exact & ~dark).sum())
     if n_net:
         rel = ((got[net] - xs[net]).abs() / xs[net].clamp_min(1e-12))
         assert float(rel.max()) < 2e-2
     lhs = red["photons_initial"] + red["photons_emitted"] + red["photons_floor"]
     rhs = red["photons_stored"] + red["photons_absorbed"] + red["photons_escaped"]
     assert rhs == pytest.approx(lhs, rel=1e-5)
-    print(f"surrogate step: {n_net} network cells, {red['n_fallback']} fallbacks", flush=True)
+    print(f"surrogate step: {red['n_learned']} network cells ({n_net} differing from the exact "
+          f"operator), {red['n_fallback']} fallbacks", flush=True)
     G.close()
 
 

@@ -58,8 +58,9 @@ def test_fp64_chemistry_on_ionised_cells(nsub):
     print(f"nsub={nsub}: xHI relative error on xHI<1e-3 cells, max / median: "
           f"FP32 {f32[0]:.2e} / {f32[1]:.2e}, mixed {mix[0]:.2e} / {mix[1]:.2e}; "
           f"T: FP32 {f32[2]:.2e}, mixed {mix[2]:.2e}", flush=True)
-    # the FP64 operator is limited by the FP32 storage of its inputs and
-    # result (and by N, which the chemistry takes after the FP32 transport)
-    assert mix[0] <= 1e-5 and mix[2] <= 1e-5
-    # and it is at least an order of magnitude closer than the FP32 operator
-    assert mix[0] * 10.0 <= f32[0]
+    # The FP64 operator is limited by the FP32 storage of its result (a few
+    # 1e-8 relative); the FP32 operator, measured at 8e-7 (one sub-cycle)
+    # and 4e-6 (16) on these inputs, fails the same bound.
+    BOUND = 2e-7
+    assert mix[0] <= BOUND and mix[2] <= BOUND
+    assert f32[0] > BOUND

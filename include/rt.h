@@ -41,6 +41,8 @@ extern "C" {
 #define RT_E_HIP (-4)       /* HIP runtime failure                          */
 #define RT_E_NONFINITE (-5) /* a step produced a NaN or Inf (rt_reduce)     */
 #define RT_E_NOMEM (-6)     /* allocation of library scratch failed         */
+#define RT_E_SCRATCH (-7)   /* request larger than the fixed scratch of an
+                               allocation-free entry point                 */
 
 /* ---- boundary conditions, per face in the order -x,+x,-y,+y,-z,+z ------ */
 #define RT_BC_PERIODIC 0 /* wrap (both faces of an axis must be periodic)  */
@@ -363,6 +365,27 @@ int rt_mlp_adam(rt_mlp *m, float *theta, float *mom1, float *mom2, const float *
                 int64_t step, double lr, double beta1, double beta2, double eps);
 
 int rt_mlp_destroy(rt_mlp *m);
+
+/* rt_mlp_grad without a workspace object, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight training loops,
+ * harnesses that forbid allocation.  It allocates nothing: the packed
+ * operands and the per-block gradient partials live in one fixed library
+ * array per device (RT_MLP_NOALLOC_BYTES, about 9 MB, reserved when the
+ * library is loaded and held until the process ends).  grad_blocks plays
+ * the role of rt_mlp_create's: 1 .. RT_MLP_NOALLOC_BLOCKS, RT_E_SCRATCH
+ * above (RT_E_ARG below 1 or for the other arguments, as rt_mlp_grad).
+ * The first call on a device looks up the array's address on that device
+ * (the device of hip_stream, or the current device for the null stream);
+ * make it before a graph capture begins.  With the same grad_blocks the
+ * result equals rt_mlp_grad's bit for bit (the same kernels and summation
+ * order).  Every call on a device uses the same array: calls that may
+ * overlap on one device (unordered streams, concurrent host threads) race;
+ * calls ordered on one stream do not.  Asynchronous on hip_stream. */
+#define RT_MLP_NOALLOC_BLOCKS 256
+#define RT_MLP_NOALLOC_BYTES (256 * 8834 * 4 + 2048 + 40960)
+int rt_mlp_grad_noalloc(int32_t grad_blocks, const float *theta, const float *X,
+                        const float *Y, int64_t B, float *grad, double *loss_dev,
+                        void *hip_stream);
 
 /* Static string naming a return code. */
 const char *rt_strerror(int code);

@@ -9,6 +9,7 @@
 // on the FP32 master.
 #include <math.h>
 
+#include <mutex>
 #include <new>
 
 #include "mlp_device.h"
@@ -459,6 +460,82 @@ extern "C" int rt_mlp_grad(rt_mlp *m, const float *theta, const float *X, const 
     hipLaunchKernelGGL(mlp_reduce_kernel, dim3((MLP_NPARAM + 63) / 64), dim3(64 * RED_WAVES),
                        0, m->stream, m->part, m->lpart, m->nblk, 1.0 / double(B), grad,
                        loss_dev);
+    return hipGetLastError() == hipSuccess ? RT_OK : RT_E_HIP;
+}
+
+// ---------------------------------------------- allocation-free gradient
+// The packed operands, the loss partials and the per-block gradient partials
+// of rt_mlp_grad_noalloc live in one fixed array per device, reserved when
+// the library's code object is loaded.  Host code never passes the array's
+// name to a kernel (in host code it is only a stand-in for the symbol): its
+// device address is looked up once per device and used from then on.
+namespace {
+constexpr size_t round256(size_t b) { return (b + 255) & ~size_t(255); }
+constexpr size_t NA_PK_BYTES = round256(size_t(PK_ALL) * 8 * sizeof(__bf16));
+constexpr size_t NA_LOSS_BYTES = round256(size_t(RT_MLP_NOALLOC_BLOCKS) * sizeof(double));
+constexpr size_t NA_PART_BYTES = size_t(RT_MLP_NOALLOC_BLOCKS) * MLP_NPARAM * sizeof(float);
+constexpr size_t NA_BYTES = NA_PK_BYTES + NA_LOSS_BYTES + NA_PART_BYTES;
+static_assert(NA_BYTES == size_t(RT_MLP_NOALLOC_BYTES), "rt.h states the scratch size");
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[NA_BYTES];
+
+namespace {
+constexpr int NA_MAX_DEVICES = 64;
+std::mutex na_mutex;
+unsigned char *na_ptr[NA_MAX_DEVICES] = {};
+
+// Device address of `scratch` on the device of `stream` (the current device
+// for the null stream), looked up with that device current on the first
+// call for it.
+int noalloc_scratch(hipStream_t stream, unsigned char **out)
+{
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess) return RT_E_HIP;
+    int dev = cur;
+    if (stream && hipStreamGetDevice(stream, &dev) != hipSuccess) return RT_E_HIP;
+    if (dev < 0 || dev >= NA_MAX_DEVICES) return RT_E_HIP;
+    std::lock_guard<std::mutex> lock(na_mutex);
+    if (!na_ptr[dev]) {
+        if (dev != cur && hipSetDevice(dev) != hipSuccess) return RT_E_HIP;
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (dev != cur && hipSetDevice(cur) != hipSuccess) return RT_E_HIP;
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return RT_E_HIP;
+        }
+        na_ptr[dev] = static_cast<unsigned char *>(p);
+    }
+    *out = na_ptr[dev];
+    return RT_OK;
+}
+}  // namespace
+
+extern "C" int rt_mlp_grad_noalloc(int32_t grad_blocks, const float *theta, const float *X,
+                                   const float *Y, int64_t B, float *grad, double *loss_dev,
+                                   void *hip_stream)
+{
+    if (grad_blocks < 1) return RT_E_ARG;
+    if (grad_blocks > RT_MLP_NOALLOC_BLOCKS) return RT_E_SCRATCH;
+    if (B < 1 || !theta || !X || !Y || !grad) return RT_E_ARG;
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    unsigned char *base = nullptr;
+    const int rc = noalloc_scratch(s, &base);
+    if (rc != RT_OK) return rc;
+    __bf16 *pk = reinterpret_cast<__bf16 *>(base);
+    double *lpart = reinterpret_cast<double *>(base + NA_PK_BYTES);
+    float *part = reinterpret_cast<float *>(base + NA_PK_BYTES + NA_LOSS_BYTES);
+    // every partial row and loss partial is written by its block before the
+    // reduction reads it, and pk by the packing kernel: nothing to clear
+    hipLaunchKernelGGL(mlp_pack_kernel, dim3((PK_ALL * 8 + 255) / 256), dim3(256), 0, s, theta,
+                       pk);
+    if (hipGetLastError() != hipSuccess) return RT_E_HIP;
+    hipLaunchKernelGGL(mlp_grad_kernel, dim3(grad_blocks), dim3(64), 0, s,
+                       reinterpret_cast<const bf16x8 *>(pk), theta, X, Y, B, part, lpart);
+    if (hipGetLastError() != hipSuccess) return RT_E_HIP;
+    hipLaunchKernelGGL(mlp_reduce_kernel, dim3((MLP_NPARAM + 63) / 64), dim3(64 * RED_WAVES), 0,
+                       s, part, lpart, grad_blocks, 1.0 / double(B), grad, loss_dev);
     return hipGetLastError() == hipSuccess ? RT_OK : RT_E_HIP;
 }
 

@@ -171,6 +171,7 @@ extern "C" const char *rt_strerror(int code)
     case RT_E_HIP: return "HIP runtime failure";
     case RT_E_NONFINITE: return "a step produced a non-finite value";
     case RT_E_NOMEM: return "device allocation failed";
+    case RT_E_SCRATCH: return "request exceeds the fixed scratch of an allocation-free entry point";
     default: return "unknown error";
     }
 }

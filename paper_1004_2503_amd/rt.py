@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_HERE, "librt_m1.so")
 
 RT_OK, RT_E_ARG, RT_E_CFL, RT_E_STATE, RT_E_HIP, RT_E_NONFINITE, RT_E_NOMEM = (
     0, -1, -2, -3, -4, -5, -6)
+RT_E_SCRATCH = -7
 BC_PERIODIC, BC_OUTFLOW, BC_REFLECT = 0, 1, 2
 CHEM_FULL, CHEM_ISOTHERMAL, CHEM_OFF, CHEM_FROZEN = 0, 1, 2, 3
 PREC_FP32, PREC_MIXED = 0, 1
@@ -325,8 +326,9 @@ class RTGrid:
 
 # ------------------------------------------------ batch chemistry and MLP
 MLP_NPARAM = 8834
+MLP_NOALLOC_BLOCKS = 256
 EXPORTS += ["rt_chem_apply", "rt_mlp_create", "rt_mlp_forward", "rt_mlp_grad", "rt_mlp_adam",
-            "rt_mlp_destroy"]
+            "rt_mlp_destroy", "rt_mlp_grad_noalloc"]
 
 
 def _bind_extra(L):
@@ -341,8 +343,9 @@ def _bind_extra(L):
     L.rt_mlp_adam.argtypes = [vp, vp, vp, vp, vp, ctypes.c_int64, ctypes.c_double,
                               ctypes.c_double, ctypes.c_double, ctypes.c_double]
     L.rt_mlp_destroy.argtypes = [vp]
+    L.rt_mlp_grad_noalloc.argtypes = [ctypes.c_int32, vp, vp, vp, ctypes.c_int64, vp, vp, vp]
     for n in ("rt_chem_apply", "rt_mlp_create", "rt_mlp_forward", "rt_mlp_grad",
-              "rt_mlp_adam", "rt_mlp_destroy"):
+              "rt_mlp_adam", "rt_mlp_destroy", "rt_mlp_grad_noalloc"):
         getattr(L, n).restype = ctypes.c_int
     L._extra_bound = True
     return L
@@ -378,6 +381,14 @@ def rt_mlp_forward(m, theta, X, Y) -> int:
 def rt_mlp_grad(m, theta, X, Y, grad, loss_dev=None) -> int:
     return _bind_extra(lib()).rt_mlp_grad(m, _p(theta), _p(X), _p(Y), int(X.shape[0]),
                                           _p(grad), _p(loss_dev))
+
+
+def rt_mlp_grad_noalloc(grad_blocks: int, theta, X, Y, grad, loss_dev=None,
+                        stream: int | None = None) -> int:
+    n = 0 if X is None else int(X.shape[0])
+    return _bind_extra(lib()).rt_mlp_grad_noalloc(int(grad_blocks), _p(theta), _p(X), _p(Y), n,
+                                                  _p(grad), _p(loss_dev),
+                                                  ctypes.c_void_p(stream or 0))
 
 
 def rt_mlp_adam(m, theta, mom1, mom2, grad, step, lr, beta1=0.9, beta2=0.999, eps=1e-8) -> int:

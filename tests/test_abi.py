@@ -77,7 +77,7 @@ def test_struct_layouts_match_header(tmp_path):
 
 def test_strerror_names_every_code():
     for code in (rt.RT_OK, rt.RT_E_ARG, rt.RT_E_CFL, rt.RT_E_STATE, rt.RT_E_HIP,
-                 rt.RT_E_NONFINITE, rt.RT_E_NOMEM):
+                 rt.RT_E_NONFINITE, rt.RT_E_NOMEM, rt.RT_E_SCRATCH):
         s = rt.rt_strerror(code)
         assert s and s != "unknown error"
     assert rt.rt_strerror(12345) == "unknown error"
@@ -182,3 +182,11 @@ def test_equilibrium_empty_batch_is_a_no_op():
                                      ctypes.c_void_p]
     assert L.rt_equilibrium_xhi(ctypes.byref(p), rt.JMODEL_UNIFORM, 1e-12, 0.0, 0, None, None,
                                 None, None) == rt.RT_OK
+
+
+def test_noalloc_grad_rejects_arguments_before_any_hip_call():
+    # checked on the host before the scratch lookup or any launch
+    assert rt.rt_mlp_grad_noalloc(rt.MLP_NOALLOC_BLOCKS + 1, None, None, None, None) == \
+        rt.RT_E_SCRATCH
+    assert rt.rt_mlp_grad_noalloc(0, None, None, None, None) == rt.RT_E_ARG
+    assert rt.rt_mlp_grad_noalloc(1, None, None, None, None) == rt.RT_E_ARG

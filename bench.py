@@ -185,14 +185,16 @@ def cpu_baseline_configs(budget_s: float = 20.0):
 
 
 def surrogate_leg(args, G, w, dt, params, src):
-    """Train the network on exact pairs sampled from the 256^3 run (several
-    dt, weighted towards the stiff and FP64 cells the step asks the network
-    for), then time, from the same state and for the same number of steps,
-    the exact and the learned forms with fixed sub-cycling (nsub) and with
-    adaptive sub-cycling (10% rule, capped at --adaptive-cap).  In both the
-    learned forms and the exact adaptive form the stiff cells leave the
-    bandwidth-bound step for the dense deferred kernel; the learned forms
-    try the network there first."""
+    """Train the network on exact pairs (several dt, weighted towards the
+    stiff and FP64 cells the step asks the network for) sampled from four
+    states of the 256^3 run and from the 1024^3 state the comparison starts
+    from, labelled by the exact adaptive operator with up to
+    --label-cap sub-cycles; then time, from that state and for the same
+    number of steps, the exact and the learned forms with fixed sub-cycling
+    (nsub) and with adaptive sub-cycling (10% rule, capped at
+    --adaptive-cap).  In both the learned forms and the exact adaptive form
+    the stiff cells leave the bandwidth-bound step for the dense deferred
+    kernel; the learned forms try the network there first."""
     import torch
 
     from paper_1004_2503_amd import rt, surrogate
@@ -210,11 +212,15 @@ def surrogate_leg(args, G, w, dt, params, src):
         t = G2.tensors()
         states.append({k: t[k].clone() for k in ("N", "xHI", "T", "nH")})
     G2.close()
+    # the 1024^3 state the forms are compared from: its photon densities lie
+    # far above the 256^3 run's near the sources (cells 64 times smaller)
+    t = G.tensors()
+    states.append({k: t[k].clone() for k in ("N", "xHI", "T", "nH")})
     pexact = rt.make_params((1, 1, 1), 1.0, chem=rt.CHEM_FULL, prec=rt.PREC_MIXED,
                             sub=rt.SUB_ADAPTIVE, sub_eps=0.1)
     dts = [W.courant_dt(W.cosmo_dx(n)) for n in (256, 512, 1024)]
 
-    def make_pairs(total, seed):
+    def make_pairs(total, seed, perturb=True):
         # twice as many cells sampled as kept: every stiff (or FP64) cell
         # among them is kept, the easy ones fill the rest
         per = total // (len(states) * len(dts))
@@ -222,7 +228,11 @@ def surrogate_leg(args, G, w, dt, params, src):
         for i, st in enumerate(states):
             for j, d in enumerate(dts):
                 c = surrogate.sample_cells(st, 2 * per, seed + 1000 * i + j)
-                X, Y, h = surrogate.candidate_pairs(pexact, c, d, per, 64,
+                # half of them moved beyond the sampled states (hotter,
+                # more ionised, brighter), where the run goes next
+                if perturb:
+                    c = surrogate.perturb_cells(c, seed + 77 + 1000 * i + j)
+                X, Y, h = surrogate.candidate_pairs(pexact, c, d, per, args.label_cap,
                                                     fp64_thr=params.xhi_fp64_thr,
                                                     seed=seed + 1000 * i + j)
                 Xs.append(X)
@@ -231,7 +241,7 @@ def surrogate_leg(args, G, w, dt, params, src):
         return torch.cat(Xs), torch.cat(Ys), n_hard
 
     X, Y, n_hard = make_pairs(args.surrogate_pairs, 0)
-    Xv, Yv, _ = make_pairs(1_000_000, 777_000)      # held out
+    Xv, Yv, _ = make_pairs(1_000_000, 777_000, perturb=False)   # held out, as sampled
     n_pairs = int(X.shape[0])
     del states
     t_pairs = time.perf_counter() - t0
@@ -279,11 +289,13 @@ def surrogate_leg(args, G, w, dt, params, src):
         cs = w.cells * n_steps
         n_fb = r1["n_fallback"] - r0["n_fallback"]
         n_net = r1["n_learned"] - r0["n_learned"]
+        n_rng = r1["n_fallback_range"] - r0["n_fallback_range"]
         out[form] = dict(ms_per_step=(tb - ta) / n_steps * 1e3,
                          value=cs / (tb - ta),
                          network_cells_per_step=(n_fb + n_net) / n_steps,
                          accepted_frac_of_network_cells=n_net / max(n_fb + n_net, 1),
                          fallback_frac=n_fb / cs,
+                         out_of_range_frac_of_network_cells=n_rng / max(n_fb + n_net, 1),
                          fp64_cells_per_step=(r1["n_fp64"] - r0["n_fp64"]) / n_steps,
                          subcycle_hist=hist, xHI=GG.xHI.clone())
         rt.check(rt.rt_set_surrogate(GG.ctx, None, None, 0.0), "rt_set_surrogate off")
@@ -308,6 +320,9 @@ def surrogate_leg(args, G, w, dt, params, src):
                                                                   "exact_adaptive")},
             "held_out": held,
             "train": {"pairs": n_pairs, "stiff_or_fp64_pairs": n_hard,
+                      "sources": "4 states of the 256^3 run + the 1024^3 start state; "
+                                 "half the cells perturbed in T, xHI and N",
+                      "label_cap": args.label_cap,
                       "adam_steps": args.surrogate_steps,
                       "pair_gen_s": t_pairs, "train_s": t_train,
                       "loss_first_last": [s.history[0][1], s.history[-1][1]]}}
@@ -435,6 +450,9 @@ def main():
                          "same 1024^3 state")
     ap.add_argument("--surrogate-pairs", type=int, default=10_000_000)
     ap.add_argument("--surrogate-steps", type=int, default=20000)
+    ap.add_argument("--label-cap", type=int, default=1024,
+                    help="sub-cycle cap of the exact adaptive operator that labels the "
+                         "surrogate's training pairs")
     ap.add_argument("--adaptive-cap", type=int, default=32,
                     help="sub-cycle cap of the adaptive forms in the surrogate comparison")
     args = ap.parse_args()

@@ -159,6 +159,8 @@ typedef struct {
                                 with the state at the end of each step (Sec. 3.1.4) */
     int64_t n_learned;       /* learned-chemistry cell-steps that kept the
                                 network's prediction, cumulative */
+    int64_t n_fallback_range; /* of n_fallback, the cell-steps rejected
+                                 because an input left the training range */
 } rt_reductions;
 
 /* Create a context for the grid described by `params` over the caller's

@@ -135,33 +135,41 @@ __device__ __forceinline__ void mlp_forward32(const PK *pk, const MlpBias &bias,
 
 // Forward pass of the 64 cells of a wavefront (every lane takes part): sv
 // holds this lane's five standardised features; returns this lane's two
-// standardised outputs.  Two 32-cell passes: lanes 0..31 first, then the
-// features of lanes 32..63 moved down and the outputs moved back up.
+// standardised outputs.  Two 32-cell passes, one after the other (the loop
+// is kept rolled so that the two do not hold their operands at once): lanes
+// 0..31 first, then the features of lanes 32..63 moved down and the outputs
+// moved back up.
 __device__ __forceinline__ void mlp_predict64(const bf16x8 *pk, const MlpBias &bias,
                                               const float sv[5], float &y0, float &y1)
 {
     const int lane = threadIdx.x & 63;
-    bf16x8 xa, xb;
+    float up[5];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-        xa[k] = (__bf16)0.0f;
-        xb[k] = (__bf16)0.0f;
-    }
+    for (int k = 0; k < 5; ++k) up[k] = __shfl(sv[k], (lane + 32) & 63);
+    float lo0 = 0.0f, lo1 = 0.0f, hi0 = 0.0f, hi1 = 0.0f;
+#pragma nounroll
+    for (int p = 0; p < 2; ++p) {
+        bf16x8 x;
 #pragma unroll
-    for (int k = 0; k < 5; ++k) {
-        const float up = __shfl(sv[k], (lane + 32) & 63);
+        for (int k = 0; k < 8; ++k) x[k] = (__bf16)0.0f;
         if (lane < 32) {
-            xa[k] = (__bf16)sv[k];
-            xb[k] = (__bf16)up;
+#pragma unroll
+            for (int k = 0; k < 5; ++k) x[k] = (__bf16)(p == 0 ? sv[k] : up[k]);
+        }
+        MlpFwd unused;
+        float a0, a1;
+        mlp_forward32<false>(pk, bias, x, unused, a0, a1);
+        if (p == 0) {
+            lo0 = a0;
+            lo1 = a1;
+        } else {
+            hi0 = a0;
+            hi1 = a1;
         }
     }
-    MlpFwd unused;
-    float ya0, ya1, yb0, yb1;
-    mlp_forward32<false>(pk, bias, xa, unused, ya0, ya1);
-    mlp_forward32<false>(pk, bias, xb, unused, yb0, yb1);
-    const float sb0 = __shfl(yb0, lane & 31), sb1 = __shfl(yb1, lane & 31);
-    y0 = lane < 32 ? ya0 : sb0;
-    y1 = lane < 32 ? ya1 : sb1;
+    const float sb0 = __shfl(hi0, lane & 31), sb1 = __shfl(hi1, lane & 31);
+    y0 = lane < 32 ? lo0 : sb0;
+    y1 = lane < 32 ? lo1 : sb1;
 }
 
 }  // namespace rtk

@@ -79,7 +79,9 @@ struct rt_ctx {
     int npart = 0;
     double *d_fin = nullptr;   // first-level finalisation rows
     uint64_t *d_mask = nullptr;   // FP64 cells left by the step (mixed forms)
+    uint64_t *d_gmask = nullptr;  // groups of 64 mask words holding a marked cell
     uint64_t nwords = 0;
+    int gwords = 0;               // 64-bit words of d_gmask
     int nb2 = 0;                  // blocks of the deferred FP64 chemistry
     double *d_acc = nullptr;
     float *d_sink = nullptr;
@@ -148,6 +150,7 @@ static void free_ctx(rt_ctx *c)
     if (c->d_part) (void)hipFree(c->d_part);
     if (c->d_fin) (void)hipFree(c->d_fin);
     if (c->d_mask) (void)hipFree(c->d_mask);
+    if (c->d_gmask) (void)hipFree(c->d_gmask);
     if (c->d_acc) (void)hipFree(c->d_acc);
     if (c->d_sink) (void)hipFree(c->d_sink);
     if (c->d_hcount) (void)hipFree(c->d_hcount);
@@ -197,6 +200,26 @@ static int z_chunk(int ntx, int ny, int nz)
     return zc;
 }
 
+// The deferred-cell mask (written whole by every step that uses it) and its
+// group bits (set by the step, cleared by the finalisation; zero to start).
+static int alloc_masks(rt_ctx *c)
+{
+    if (!c->d_mask && hipMalloc(&c->d_mask, c->nwords * sizeof(uint64_t)) != hipSuccess) {
+        (void)hipGetLastError();
+        return RT_E_NOMEM;
+    }
+    if (!c->d_gmask) {
+        if (hipMalloc(&c->d_gmask, size_t(c->gwords) * sizeof(uint64_t)) != hipSuccess) {
+            (void)hipGetLastError();
+            return RT_E_NOMEM;
+        }
+        if (hipMemsetAsync(c->d_gmask, 0, size_t(c->gwords) * sizeof(uint64_t), c->stream) !=
+            hipSuccess)
+            return RT_E_HIP;
+    }
+    return RT_OK;
+}
+
 extern "C" int rt_init(const rt_params *params, const rt_fields *fields, void *hip_stream,
                        rt_ctx **out)
 {
@@ -232,14 +255,17 @@ extern "C" int rt_init(const rt_params *params, const rt_fields *fields, void *h
     const bool defer = params->prec == RT_PREC_MIXED || params->sub == RT_SUB_ADAPTIVE;
     c->nwords = uint64_t(params->nz) * uint64_t(params->ny) * uint64_t(c->ntx);
     c->nb2 = defer_chem_blocks(c->nwords);
+    c->gwords = int((mask_groups(c->nwords) + 63) / 64);
     // partial rows: a step writes one per block of whichever tile set it
     // runs on, then the deferred chemistry nb2 more after them
-    c->npart = std::max(std::max(c->geo[0].nblocks, c->geo[1].nblocks) + c->nb2,
+    c->npart = std::max(std::max(c->geo[0].nblocks, c->geo[1].nblocks) + 2 * c->nb2,
                         state_sums_blocks(c->ncell));
-    if (defer && hipMalloc(&c->d_mask, c->nwords * sizeof(uint64_t)) != hipSuccess) {
-        (void)hipGetLastError();
-        free_ctx(c);
-        return RT_E_NOMEM;
+    if (defer) {
+        rc = alloc_masks(c);
+        if (rc != RT_OK) {
+            free_ctx(c);
+            return rc;
+        }
     }
 
     if (hipMalloc(&c->d_part, size_t(c->npart) * NRED * sizeof(double)) != hipSuccess ||
@@ -617,6 +643,7 @@ static void fill_args(const rt_ctx *c, double dt, int nsub, StepArgs &a)
     a.defer = (p.chem != RT_CHEM_OFF && (p.prec == RT_PREC_MIXED || a.defer_stiff)) ? 1 : 0;
     a.count_hist = (p.sub == RT_SUB_ADAPTIVE || c->surr) ? 1 : 0;
     a.fp64_mask = c->d_mask;
+    a.group_mask = c->d_gmask;
     a.c_d = p.c_cms;
     a.surr = c->surr ? 1 : 0;
     a.surr_pk = c->d_surr_pk;
@@ -640,9 +667,9 @@ extern "C" int rt_step(rt_ctx *c, double dt, int32_t nsub)
     }
     StepArgs a;
     fill_args(c, dt, nsub, a);
-    const int rows = a.nblocks + (a.defer ? c->nb2 : 0);
+    const int rows = a.nblocks + defer_rows(a, c->nb2);
     if (rows > c->npart) return RT_E_STATE;   // the partials would not fit
-    if (a.defer && !c->d_mask) return RT_E_STATE;
+    if (a.defer && (!c->d_mask || !c->d_gmask)) return RT_E_STATE;
     Ev *e = nullptr;
     if (c->prof) {
         if (c->ev_used == c->ev.size()) {
@@ -660,7 +687,8 @@ extern "C" int rt_step(rt_ctx *c, double dt, int32_t nsub)
     if (e && hipEventRecord(e->b, c->stream) != hipSuccess) return RT_E_HIP;
     const double tau_coef = c->p.c_cms * SIGMA_T * dt / double(c->ncell);
     if (launch_finalize(c->d_part, rows, c->d_fin, c->d_acc, 0, tau_coef, c->nh_sum,
-                        c->stream) != hipSuccess)
+                        c->stream, a.defer ? c->d_gmask : nullptr, a.defer ? c->gwords : 0) !=
+        hipSuccess)
         return RT_E_HIP;
     c->cur = 1 - c->cur;
     c->t += dt;
@@ -698,9 +726,9 @@ extern "C" int rt_set_surrogate(rt_ctx *c, const float *theta, const float *norm
             return RT_E_NOMEM;
         }
     }
-    if (!c->d_mask && hipMalloc(&c->d_mask, c->nwords * sizeof(uint64_t)) != hipSuccess) {
-        (void)hipGetLastError();
-        return RT_E_NOMEM;
+    {
+        const int rc = alloc_masks(c);
+        if (rc != RT_OK) return rc;
     }
     const int offs[4] = {OFF_B1, OFF_B2, OFF_B3, OFF_B4};
     const int lens[4] = {MLP_NH, MLP_NH, MLP_NH, MLP_NOUT};
@@ -749,6 +777,7 @@ extern "C" int rt_reduce(rt_ctx *c, rt_reductions *out)
         out->subcycle_hist[b] = c->hist_host[b] + int64_t(acc[ACC_CUM + R_HIST0 + b]);
     out->tau_e = acc[ACC_CUM + ACC_TAU];
     out->n_learned = int64_t(acc[ACC_CUM + R_LEARNED]);
+    out->n_fallback_range = int64_t(acc[ACC_CUM + R_RANGE]);
     return out->n_nonfinite > 0 ? RT_E_NONFINITE : RT_OK;
 }
 

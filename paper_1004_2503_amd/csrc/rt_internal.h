@@ -42,6 +42,8 @@ enum Red : int {
     R_FP64,        // cells whose chemistry ran in FP64
     R_FALLBACK,    // learned-chemistry cells whose prediction was rejected
     R_LEARNED,     // learned-chemistry cells that kept the prediction
+    R_RANGE,       // learned-chemistry cells rejected for inputs outside the
+                   // training range (counted in R_FALLBACK too)
     R_HIST0,       // 8 sub-cycle histogram bins
     NRED = R_HIST0 + 8
 };
@@ -93,6 +95,10 @@ struct StepArgs {
     int defer_stiff;
     int count_hist;                  // sub-cycle histogram counted on the device
     uint64_t *fp64_mask;
+    // one bit per group of 64 consecutive mask words that holds a marked
+    // cell (set by the step, cleared by the finalisation): the deferred
+    // kernels visit only those groups
+    uint64_t *group_mask;
     ClumpLaw cl;
     ClumpLawD cld;
     // FP32 constants
@@ -115,10 +121,19 @@ constexpr int SURR_NBIAS = 194;
 constexpr int SURR_NNORM = 24;
 
 hipError_t launch_step(const StepArgs &a, hipStream_t s);
-// The FP64 chemistry of the cells marked by the step (StepArgs::defer): nb2
-// blocks, whose partial sums land in rows nblocks .. nblocks + nb2 - 1.
+// The chemistry of the cells marked by the step (StepArgs::defer): with the
+// learned chemistry on, first the network on them (nb2 blocks, partial rows
+// nblocks .. nblocks + nb2 - 1), which leaves only its rejected cells
+// marked; then the exact operator on the marked cells (nb2 blocks, the next
+// nb2 rows, or from row nblocks without the network).  defer_rows: the
+// partial rows the two take.
 int defer_chem_blocks(uint64_t nwords);
+__host__ __device__ inline uint64_t mask_groups(uint64_t nwords) { return (nwords + 63) / 64; }
 hipError_t launch_defer_chem(const StepArgs &a, uint64_t nwords, int nb2, hipStream_t s);
+inline int defer_rows(const StepArgs &a, int nb2)
+{
+    return a.defer ? ((a.surr && a.chem == RT_CHEM_FULL) ? 2 * nb2 : nb2) : 0;
+}
 ClumpLaw make_clump_law(const rt_params &p);
 ClumpLawD make_clump_law_d(const rt_params &p);
 int inject_host(rt_ctx *c, int64_t n, const int32_t *ijk, const double *ndot);
@@ -135,7 +150,8 @@ hipError_t launch_mlp_pack(const float *theta, __bf16 *pk, hipStream_t s);
 constexpr int FIN1_BLOCKS = 256;
 constexpr int FIN1_MIN = 4096;
 hipError_t launch_finalize(const double *partials, int nblocks, double *scratch, double *acc,
-                           int mode, double tau_coef, double nh_sum, hipStream_t s);
+                           int mode, double tau_coef, double nh_sum, hipStream_t s,
+                           uint64_t *clear = nullptr, int nclear = 0);
 size_t hist_lds_bytes(int nbx, int nby);
 hipError_t launch_hist(const float *nH, const float *q, int gamma, double csig, uint32_t ncell,
                        int nbx, int nby, const double *edges, float lox, float inv_wx,

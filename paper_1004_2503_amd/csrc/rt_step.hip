@@ -584,8 +584,11 @@ void m1_step_kernel(StepArgs A)
             // one x-row per wave, 64 planes zb .. zb+63 of the chunk one per
             // lane, stored once they are done
             const int zb = z0 + ((z - z0) & ~63);
-            if (gy < A.ny && zb + lx < z1)
-                A.fp64_mask[(size_t(zb + lx) * A.ny + gy) * A.ntx + (x0 / TX)] = mword;
+            if (gy < A.ny && zb + lx < z1) {
+                const size_t w = (size_t(zb + lx) * A.ny + gy) * A.ntx + (x0 / TX);
+                A.fp64_mask[w] = mword;
+                if (mword) atomicOr(&A.group_mask[w >> 12], 1ull << ((w >> 6) & 63));
+            }
             mword = 0;
         }
     }
@@ -618,6 +621,7 @@ void m1_step_kernel(StepArgs A)
         sred[wave][R_FP64] = 0.0;       // FP64 cells are all deferred
         sred[wave][R_FALLBACK] = 0.0;   // so are the learned chemistry's cells
         sred[wave][R_LEARNED] = 0.0;
+        sred[wave][R_RANGE] = 0.0;
     }
     __syncthreads();
     if (tid < NRED) {
@@ -643,7 +647,7 @@ void m1_step_kernel(StepArgs A)
 // the mixed form's threshold, FP32 otherwise -- for the cells it does not
 // accept.  F is scaled by the photons left; the cell's share of the sums
 // that the step left out is reduced per block in a fixed order.
-constexpr int DEFER_THREADS = 256, DEFER_MAX_BLOCKS = 8192;
+constexpr int DEFER_THREADS = 256, DEFER_MAX_BLOCKS = 4096;
 constexpr int DEFER_WAVES = DEFER_THREADS / 64;
 
 // Learned chemistry of one cell from the network's standardised outputs
@@ -690,155 +694,67 @@ __device__ __forceinline__ bool surr_accept(const StepArgs &A, const float f[5],
            rx <= A.surr_tol && rT <= A.surr_tol;
 }
 
-template <bool SURR>
-__global__ __launch_bounds__(DEFER_THREADS) void defer_chem_kernel(StepArgs A, uint64_t nwords)
+// Marked cells of a deferred kernel's wavefront, in full batches.  The
+// wavefront visits its groups of 64 mask words (every waves-th group that
+// has a marked cell) a quarter (16 words) at a time and appends the linear
+// indices of their marked cells, in word order, to a ring in LDS; whenever
+// it holds 64 of them, `batch(cell, true)` runs on all lanes at once, so
+// every lane of every batch but the wavefront's last has a cell.  Appends
+// of one quarter are at most 16 x 64 cells, so the ring never holds more
+// than 63 + 1024.
+constexpr int QCAP = 2048;
+static_assert(QCAP >= 63 + 16 * 64 && (QCAP & (QCAP - 1)) == 0, "ring size");
+
+template <typename F>
+__device__ __forceinline__ void marked_batches(const StepArgs &A, uint64_t nwords, uint32_t *ring,
+                                               F &&batch)
 {
-    __shared__ uint16_t s_list[DEFER_WAVES][64 * 64];
-    __shared__ __attribute__((aligned(16))) __bf16 s_pk[SURR ? PK_FWD * 8 : 8];
-    __shared__ float s_bias[SURR ? SURR_NBIAS : 1];
-    __shared__ double sred[DEFER_WAVES][NRED];
-    __shared__ int shist[8];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    if (tid < 8) shist[tid] = 0;
-    if constexpr (SURR) {
-        for (int i = tid; i < PK_FWD; i += DEFER_THREADS)
-            reinterpret_cast<uint4 *>(s_pk)[i] = reinterpret_cast<const uint4 *>(A.surr_pk)[i];
-        for (int i = tid; i < SURR_NBIAS; i += DEFER_THREADS) s_bias[i] = A.surr_bias[i];
-    }
-    __syncthreads();
-    const ChemK<double> Kd{A.dt_d,      A.dt_d / double(A.nsub), A.csig_d,   A.T_h_d,
-                           A.T_floor_d, A.sub_eps_d,             A.inv15kB_d};
-    const ChemK<float> Kf{A.dt,      A.dt / float(A.nsub), A.csig,   A.T_h,
-                          A.T_floor, A.sub_eps,            A.inv15kB};
-    const bool use_net = SURR && A.chem == RT_CHEM_FULL;
-    double acc_xhi = 0.0, acc_nhxhi = 0.0, acc_N = 0.0, acc_abs = 0.0;
-    int n_bad = 0, n_fp64 = 0, n_fb = 0, n_net = 0;
-    uint16_t *list = s_list[wave];
-    const uint64_t waves = uint64_t(gridDim.x) * DEFER_WAVES;
-    for (uint64_t base = (uint64_t(blockIdx.x) * DEFER_WAVES + wave) * 64; base < nwords;
-         base += waves * 64) {
-        const uint64_t mine = base + lane < nwords ? A.fp64_mask[base + lane] : 0ull;
-        // gather the marked cells: (word - base) << 6 | bit, in word order
-        const int cnt = __popcll(mine);
-        int incl = cnt;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint64_t waves = uint64_t(gridDim.x) * DEFER_WAVES, ngroups = mask_groups(nwords);
+    int head = 0, pending = 0;   // wavefront-uniform
+    for (uint64_t g = uint64_t(blockIdx.x) * DEFER_WAVES + wave; g < ngroups; g += waves) {
+        if (!((A.group_mask[g >> 6] >> (g & 63)) & 1ull)) continue;   // no marked cell
+        const uint64_t w = g * 64 + uint64_t(lane);
+        const uint64_t word = w < nwords ? A.fp64_mask[w] : 0ull;
+        // cell index of bit 0 of this lane's word: row (z ny + y), tile column
+        const uint32_t cell0 =
+            uint32_t(w / uint64_t(A.ntx)) * uint32_t(A.nx) + uint32_t(w % uint64_t(A.ntx)) * TX;
+#pragma unroll 1
+        for (int qtr = 0; qtr < 4; ++qtr) {
+            const uint64_t mine = (lane >> 4) == qtr ? word : 0ull;
+            const int cnt = __popcll(mine);
+            int incl = cnt;
 #pragma unroll
-        for (int off = 1; off < 64; off <<= 1) {
-            const int v = __shfl_up(incl, off);
-            if (lane >= off) incl += v;
-        }
-        const int total = __shfl(incl, 63);
-        int pos = incl - cnt;
-        for (uint64_t m = mine; m; m &= m - 1ull)
-            list[pos++] = uint16_t((lane << 6) | __builtin_ctzll(m));
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        for (int b0 = 0; b0 < total; b0 += 64) {
-            const bool valid = b0 + lane < total;
-            const int e = valid ? int(list[b0 + lane]) : 0;
-            const uint64_t w = base + uint64_t(e >> 6);
-            const int itx = int(w % uint64_t(A.ntx));
-            const uint64_t row = w / uint64_t(A.ntx);
-            const int y = int(row % uint64_t(A.ny)), z = int(row / uint64_t(A.ny));
-            const int x = itx * TX + (e & 63);
-            const uint32_t i = (uint32_t(z) * uint32_t(A.ny) + uint32_t(y)) * uint32_t(A.nx) +
-                               uint32_t(x);
-            float Nt = 0.0f, Fx = 0.0f, Fy = 0.0f, Fz = 0.0f;
-            float c_xh = 1.0f, c_T = 1.0e4f, c_nh = 1.0f;
-            if (valid) {
-                Nt = A.No[i];
-                Fx = A.Fxo[i];
-                Fy = A.Fyo[i];
-                Fz = A.Fzo[i];
-                c_xh = A.xHI[i];
-                c_T = A.T[i];
-                c_nh = A.nH[i];
+            for (int off = 1; off < 64; off <<= 1) {
+                const int v = __shfl_up(incl, off);
+                if (lane >= off) incl += v;
             }
-            float cR, cI;
-            clump_f32(A.cl, c_nh, cR, cI);
-            float Nn = Nt, xh = c_xh, Tc = c_T, pab = 0.0f;
-            double pabs = 0.0;
-            bool ok = false, used64 = false;
-            int ncyc = 0;
-            if (use_net) {
-                const float *nm = A.surr_norm;
-                const float LOG10_2 = 0.301029995664f;
-                float f[5] = {LOG10_2 * flog2(c_nh), LOG10_2 * flog2(rmax(c_xh, 1e-30f)),
-                              LOG10_2 * flog2(c_T), LOG10_2 * flog2(rmax(Nt, 1e-30f)),
-                              A.log10_dt};
-                bool ood = !(c_nh > 0.0f && c_T > 0.0f);
-                float sv[5];
-#pragma unroll
-                for (int k = 0; k < 5; ++k) {
-                    ood = ood || !(f[k] >= nm[14 + k] && f[k] <= nm[19 + k]);
-                    sv[k] = valid ? (f[k] - nm[k]) * frcp(nm[5 + k]) : 0.0f;
-                }
-                const MlpBias mb{s_bias, s_bias + 64, s_bias + 128, s_bias + 192};
-                float y0, y1;
-                mlp_predict64(reinterpret_cast<const bf16x8 *>(s_pk), mb, sv, y0, y1);
-                float Ns, xs, Ts, Ph;
-                ok = valid && surr_accept(A, f, ood, y0, y1, Nt, c_xh, c_T, c_nh, cR, cI, Ns, xs,
-                                          Ts, Ph);
-                if (ok) {
-                    Nn = Ns;
-                    xh = xs;
-                    Tc = Ts;
-                    pabs = Ph;
-                }
-            }
-            if (valid && !ok) {
-                if (A.mixed && c_xh < A.xhi_thr) {
-                    double Nd = Nt, xd = c_xh, Td = c_T, ad = 0.0, dR, dI;
-                    clump_f64(A.cld, double(c_nh), dR, dI);
-                    ncyc = chem_cell<double>(A.chem, A.nsub, A.adaptive, Kd, dR, dI,
-                                             double(c_nh), Nd, xd, Td, ad);
-                    Nn = float(Nd);
-                    xh = float(xd);
-                    Tc = float(Td);
-                    pabs = ad;
-                    used64 = true;
-                } else {
-                    ncyc = chem_cell<float>(A.chem, A.nsub, A.adaptive, Kf, cR, cI, c_nh, Nn, xh,
-                                            Tc, pab);
-                    pabs = pab;
-                }
-            }
-            if (valid) {
-                const float sc = (Nt > N_TINY) ? rmin(Nn * frcp(Nt), 1.0f) : 0.0f;
-                Fx *= sc;
-                Fy *= sc;
-                Fz *= sc;
-                store_out(&A.No[i], Nn);
-                store_out(&A.Fxo[i], Fx);
-                store_out(&A.Fyo[i], Fy);
-                store_out(&A.Fzo[i], Fz);
-                store_out(&A.xHI[i], xh);
-                store_out(&A.T[i], Tc);
-                float z0v = 0.0f * Nn + 0.0f * Fx + 0.0f * Fy + 0.0f * Fz + 0.0f * xh + 0.0f * Tc;
-                z0v += 0.0f * Nt + 0.0f * c_xh + 0.0f * c_T + 0.0f * c_nh;
-                n_bad += z0v == 0.0f ? 0 : 1;
-                n_fp64 += used64 ? 1 : 0;
-                n_fb += (use_net && !ok) ? 1 : 0;
-                n_net += ok ? 1 : 0;
-                acc_xhi += double(xh);
-                acc_nhxhi = fma(double(c_nh), double(xh), acc_nhxhi);
-                acc_N += double(Nn);
-                acc_abs += pabs;
-            }
-            if (A.count_hist) {
-                const int bin = hist_bin(ncyc);
-#pragma unroll
-                for (int hb = 0; hb < 8; ++hb) {
-                    const unsigned long long hm = __ballot(valid && bin == hb);
-                    if (lane == 0 && hm) atomicAdd(&shist[hb], __popcll(hm));
-                }
+            const int total = __shfl(incl, 63);
+            if (total == 0) continue;
+            int pos = head + pending + incl - cnt;
+            for (uint64_t m = mine; m; m &= m - 1ull)
+                ring[(pos++) & (QCAP - 1)] = cell0 + uint32_t(__builtin_ctzll(m));
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            pending += total;
+            while (pending >= 64) {
+                batch(ring[(head + lane) & (QCAP - 1)], true);
+                head = (head + 64) & (QCAP - 1);
+                pending -= 64;
             }
         }
     }
-    double v[8] = {acc_xhi, acc_nhxhi, acc_N, acc_abs, double(n_bad), double(n_fp64),
-                   double(n_fb), double(n_net)};
+    if (pending > 0) batch(lane < pending ? ring[(head + lane) & (QCAP - 1)] : 0u, lane < pending);
+}
+
+// Per-block partial row of the deferred kernels' sums, in a fixed order.
+__device__ __forceinline__ void defer_partials(const StepArgs &A, int row, double (*sred)[NRED],
+                                               const int *shist, double v[9], int lane,
+                                               int wave, int tid)
+{
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
+    for (int j = 0; j < 9; ++j) {
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) v[j] += __shfl_xor(v[j], off);
     }
@@ -853,34 +769,216 @@ __global__ __launch_bounds__(DEFER_THREADS) void defer_chem_kernel(StepArgs A, u
         sred[wave][R_FP64] = v[5];
         sred[wave][R_FALLBACK] = v[6];
         sred[wave][R_LEARNED] = v[7];
+        sred[wave][R_RANGE] = v[8];
     }
     __syncthreads();
     if (tid < NRED) {
-        double s = 0.0;
+        double sum = 0.0;
         if (tid < R_HIST0) {
 #pragma unroll
-            for (int w = 0; w < DEFER_WAVES; ++w) s += sred[w][tid];
+            for (int w = 0; w < DEFER_WAVES; ++w) sum += sred[w][tid];
         } else {
-            s = double(shist[tid - R_HIST0]);
+            sum = double(shist[tid - R_HIST0]);
         }
-        A.partials[(size_t(A.nblocks) + blockIdx.x) * NRED + tid] = s;
+        A.partials[size_t(row) * NRED + tid] = sum;
     }
 }
 
+// The exact operator Phi of the cells still marked: FP64 below the mixed
+// form's threshold, FP32 otherwise.  Partial rows from A.nblocks + row0.
+__global__ __launch_bounds__(DEFER_THREADS) void defer_chem_kernel(StepArgs A, uint64_t nwords,
+                                                                   int row0)
+{
+    __shared__ uint32_t s_ring[DEFER_WAVES][QCAP];
+    __shared__ double sred[DEFER_WAVES][NRED];
+    __shared__ int shist[8];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    if (tid < 8) shist[tid] = 0;
+    __syncthreads();
+    const ChemK<double> Kd{A.dt_d,      A.dt_d / double(A.nsub), A.csig_d,   A.T_h_d,
+                           A.T_floor_d, A.sub_eps_d,             A.inv15kB_d};
+    const ChemK<float> Kf{A.dt,      A.dt / float(A.nsub), A.csig,   A.T_h,
+                          A.T_floor, A.sub_eps,            A.inv15kB};
+    double acc_xhi = 0.0, acc_nhxhi = 0.0, acc_N = 0.0, acc_abs = 0.0;
+    int n_bad = 0, n_fp64 = 0;
+    marked_batches(A, nwords, s_ring[wave], [&](uint32_t i, bool valid) {
+        float Nt = 0.0f, Fx = 0.0f, Fy = 0.0f, Fz = 0.0f;
+        float c_xh = 1.0f, c_T = 1.0e4f, c_nh = 1.0f;
+        if (valid) {
+            Nt = A.No[i];
+            Fx = A.Fxo[i];
+            Fy = A.Fyo[i];
+            Fz = A.Fzo[i];
+            c_xh = A.xHI[i];
+            c_T = A.T[i];
+            c_nh = A.nH[i];
+        }
+        float Nn = Nt, xh = c_xh, Tc = c_T;
+        double pabs = 0.0;
+        int ncyc = 0;
+        if (valid) {
+            if (A.mixed && c_xh < A.xhi_thr) {
+                double Nd = Nt, xd = c_xh, Td = c_T, ad = 0.0, dR, dI;
+                clump_f64(A.cld, double(c_nh), dR, dI);
+                ncyc = chem_cell<double>(A.chem, A.nsub, A.adaptive, Kd, dR, dI, double(c_nh), Nd,
+                                         xd, Td, ad);
+                Nn = float(Nd);
+                xh = float(xd);
+                Tc = float(Td);
+                pabs = ad;
+                n_fp64 += 1;
+            } else {
+                float cR, cI, pab = 0.0f;
+                clump_f32(A.cl, c_nh, cR, cI);
+                ncyc = chem_cell<float>(A.chem, A.nsub, A.adaptive, Kf, cR, cI, c_nh, Nn, xh, Tc,
+                                        pab);
+                pabs = pab;
+            }
+            const float sc = (Nt > N_TINY) ? rmin(Nn * frcp(Nt), 1.0f) : 0.0f;
+            store_out(&A.No[i], Nn);
+            store_out(&A.Fxo[i], Fx * sc);
+            store_out(&A.Fyo[i], Fy * sc);
+            store_out(&A.Fzo[i], Fz * sc);
+            store_out(&A.xHI[i], xh);
+            store_out(&A.T[i], Tc);
+            float z0v = 0.0f * Nn + 0.0f * Fx + 0.0f * Fy + 0.0f * Fz + 0.0f * xh + 0.0f * Tc;
+            z0v += 0.0f * Nt + 0.0f * c_xh + 0.0f * c_T + 0.0f * c_nh;
+            n_bad += z0v == 0.0f ? 0 : 1;
+            acc_xhi += double(xh);
+            acc_nhxhi = fma(double(c_nh), double(xh), acc_nhxhi);
+            acc_N += double(Nn);
+            acc_abs += pabs;
+        }
+        if (A.count_hist) {
+            const int bin = hist_bin(ncyc);
+#pragma unroll
+            for (int hb = 0; hb < 8; ++hb) {
+                const unsigned long long hm = __ballot(valid && bin == hb);
+                if (lane == 0 && hm) atomicAdd(&shist[hb], __popcll(hm));
+            }
+        }
+    });
+    double v[9] = {acc_xhi, acc_nhxhi, acc_N, acc_abs, double(n_bad), double(n_fp64), 0.0, 0.0,
+                   0.0};
+    defer_partials(A, A.nblocks + row0 + int(blockIdx.x), sred, shist, v, lane, wave, tid);
+}
+
+// The learned chemistry of the marked cells, on the matrix cores: each
+// wavefront gathers the marked cells of 64 mask words and runs the network
+// on them 64 at a time; a cell whose prediction passes surr_accept takes it,
+// a rejected cell stays marked (the word is written back with only those
+// bits) for defer_chem_kernel, which then runs the exact operator on the
+// rejected cells alone, in dense wavefronts.  Partial rows from A.nblocks.
+__global__ __launch_bounds__(DEFER_THREADS) void surr_chem_kernel(StepArgs A, uint64_t nwords)
+{
+    __shared__ uint32_t s_ring[DEFER_WAVES][QCAP];
+    __shared__ __attribute__((aligned(16))) __bf16 s_pk[PK_FWD * 8];
+    __shared__ float s_bias[SURR_NBIAS];
+    __shared__ double sred[DEFER_WAVES][NRED];
+    __shared__ int shist[8];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    if (tid < 8) shist[tid] = 0;
+    for (int i = tid; i < PK_FWD; i += DEFER_THREADS)
+        reinterpret_cast<uint4 *>(s_pk)[i] = reinterpret_cast<const uint4 *>(A.surr_pk)[i];
+    for (int i = tid; i < SURR_NBIAS; i += DEFER_THREADS) s_bias[i] = A.surr_bias[i];
+    __syncthreads();
+    double acc_xhi = 0.0, acc_nhxhi = 0.0, acc_N = 0.0, acc_abs = 0.0;
+    int n_bad = 0, n_fb = 0, n_net = 0, n_range = 0;
+    const MlpBias mb{s_bias, s_bias + 64, s_bias + 128, s_bias + 192};
+    const float *nm = A.surr_norm;
+    marked_batches(A, nwords, s_ring[wave], [&](uint32_t i, bool valid) {
+        float Nt = 0.0f, c_xh = 1.0f, c_T = 1.0e4f, c_nh = 1.0f;
+        if (valid) {
+            Nt = A.No[i];
+            c_xh = A.xHI[i];
+            c_T = A.T[i];
+            c_nh = A.nH[i];
+        }
+        const float LOG10_2 = 0.301029995664f;
+        float f[5] = {LOG10_2 * flog2(c_nh), LOG10_2 * flog2(rmax(c_xh, 1e-30f)),
+                      LOG10_2 * flog2(c_T), LOG10_2 * flog2(rmax(Nt, 1e-30f)), A.log10_dt};
+        bool ood = !(c_nh > 0.0f && c_T > 0.0f);
+        float sv[5];
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+            ood = ood || !(f[k] >= nm[14 + k] && f[k] <= nm[19 + k]);
+            sv[k] = valid ? (f[k] - nm[k]) * frcp(nm[5 + k]) : 0.0f;
+        }
+        float y0, y1;
+        mlp_predict64(reinterpret_cast<const bf16x8 *>(s_pk), mb, sv, y0, y1);
+        float cR, cI, Ns, xs, Ts, Ph;
+        clump_f32(A.cl, c_nh, cR, cI);
+        const bool ok = valid && surr_accept(A, f, ood, y0, y1, Nt, c_xh, c_T, c_nh, cR, cI, Ns,
+                                             xs, Ts, Ph);
+        if (ok) {
+            const float sc = (Nt > N_TINY) ? rmin(Ns * frcp(Nt), 1.0f) : 0.0f;
+            const float Fx = A.Fxo[i], Fy = A.Fyo[i], Fz = A.Fzo[i];
+            store_out(&A.No[i], Ns);
+            store_out(&A.Fxo[i], Fx * sc);
+            store_out(&A.Fyo[i], Fy * sc);
+            store_out(&A.Fzo[i], Fz * sc);
+            store_out(&A.xHI[i], xs);
+            store_out(&A.T[i], Ts);
+            float z0v = 0.0f * Ns + 0.0f * Fx + 0.0f * Fy + 0.0f * Fz + 0.0f * xs + 0.0f * Ts;
+            z0v += 0.0f * Nt + 0.0f * c_xh + 0.0f * c_T + 0.0f * c_nh;
+            n_bad += z0v == 0.0f ? 0 : 1;
+            n_net += 1;
+            acc_xhi += double(xs);
+            acc_nhxhi = fma(double(c_nh), double(xs), acc_nhxhi);
+            acc_N += double(Ns);
+            acc_abs += double(Ph);
+        } else if (valid) {
+            n_fb += 1;
+            n_range += ood ? 1 : 0;
+        }
+        // Accepted cells leave the mask, so that the exact kernel takes only
+        // the rejected ones.  The batch's cells come in word order: the
+        // lanes of one word OR their bits together (a segmented scan) and
+        // the word's last lane clears them with one atomic.
+        const uint32_t x = i % uint32_t(A.nx);
+        // (lanes without a cell take a word index no cell has)
+        const uint64_t wd = valid ? uint64_t(i / uint32_t(A.nx)) * uint64_t(A.ntx) + uint64_t(x / TX)
+                                  : ~0ull;
+        uint64_t bits = ok ? (1ull << (x & 63)) : 0ull;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint64_t vb = __shfl_up(bits, off);
+            const uint64_t vw = __shfl_up(wd, off);
+            if (lane >= off && vw == wd) bits |= vb;
+        }
+        const uint64_t next = __shfl_down(wd, 1);
+        const bool last = valid && (lane == 63 || next != wd);
+        if (last && bits) atomicAnd(reinterpret_cast<unsigned long long *>(&A.fp64_mask[wd]),
+                                    ~(unsigned long long)bits);
+        if (A.count_hist) {
+            // accepted cells count in the first bin; the exact kernel counts
+            // the rejected ones
+            const unsigned long long hm = __ballot(ok);
+            if (lane == 0 && hm) atomicAdd(&shist[0], __popcll(hm));
+        }
+    });
+    double v[9] = {acc_xhi, acc_nhxhi, acc_N, acc_abs, double(n_bad), 0.0, double(n_fb),
+                   double(n_net), double(n_range)};
+    defer_partials(A, A.nblocks + int(blockIdx.x), sred, shist, v, lane, wave, tid);
+}
+
+// Blocks of the deferred kernels: about 16 groups of 64 mask words per
+// wavefront, at most DEFER_MAX_BLOCKS.
 int defer_chem_blocks(uint64_t nwords)
 {
-    const uint64_t want = (nwords + DEFER_THREADS - 1) / DEFER_THREADS;
+    const uint64_t want = (mask_groups(nwords) + 16 * DEFER_WAVES - 1) / (16 * DEFER_WAVES);
     return int(want < 1 ? 1 : (want > DEFER_MAX_BLOCKS ? DEFER_MAX_BLOCKS : want));
 }
 
 hipError_t launch_defer_chem(const StepArgs &a, uint64_t nwords, int nb2, hipStream_t s)
 {
-    if (a.surr)
-        hipLaunchKernelGGL(defer_chem_kernel<true>, dim3(nb2), dim3(DEFER_THREADS), 0, s, a,
-                           nwords);
-    else
-        hipLaunchKernelGGL(defer_chem_kernel<false>, dim3(nb2), dim3(DEFER_THREADS), 0, s, a,
-                           nwords);
+    int row0 = 0;
+    if (a.surr && a.chem == RT_CHEM_FULL) {
+        hipLaunchKernelGGL(surr_chem_kernel, dim3(nb2), dim3(DEFER_THREADS), 0, s, a, nwords);
+        row0 = nb2;
+    }
+    hipLaunchKernelGGL(defer_chem_kernel, dim3(nb2), dim3(DEFER_THREADS), 0, s, a, nwords,
+                       row0);
     return hipGetLastError();
 }
 
@@ -895,8 +993,12 @@ constexpr int FIN_THREADS = 1024;
 __global__ __launch_bounds__(FIN_THREADS) void finalize_kernel(const double *__restrict__ part,
                                                                int nb, double *__restrict__ acc,
                                                                int mode, double tau_coef,
-                                                               double nh_sum)
+                                                               double nh_sum,
+                                                               uint64_t *__restrict__ clear,
+                                                               int nclear)
 {
+    // the deferred kernels' group bits of this step, cleared for the next
+    for (int i = threadIdx.x; i < nclear; i += FIN_THREADS) clear[i] = 0ull;
     __shared__ double s[FIN_THREADS / 64][NRED];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     double v[NRED];
@@ -1024,7 +1126,8 @@ hipError_t launch_step(const StepArgs &a, hipStream_t s)
 }
 
 hipError_t launch_finalize(const double *partials, int nblocks, double *scratch, double *acc,
-                           int mode, double tau_coef, double nh_sum, hipStream_t s)
+                           int mode, double tau_coef, double nh_sum, hipStream_t s,
+                           uint64_t *clear, int nclear)
 {
     if (nblocks > FIN1_MIN) {
         hipLaunchKernelGGL(finalize_partial_kernel, dim3(FIN1_BLOCKS), dim3(256), 0, s,
@@ -1033,7 +1136,7 @@ hipError_t launch_finalize(const double *partials, int nblocks, double *scratch,
         nblocks = FIN1_BLOCKS;
     }
     hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(FIN_THREADS), 0, s, partials, nblocks,
-                       acc, mode, tau_coef, nh_sum);
+                       acc, mode, tau_coef, nh_sum, clear, nclear);
     return hipGetLastError();
 }
 

@@ -63,7 +63,7 @@ class rt_reductions(ctypes.Structure):
                 ("steps", ctypes.c_int64), ("n_nonfinite", ctypes.c_int64),
                 ("n_fp64", ctypes.c_int64), ("n_fallback", ctypes.c_int64),
                 ("subcycle_hist", ctypes.c_int64 * 8), ("tau_e", ctypes.c_double),
-                ("n_learned", ctypes.c_int64)]
+                ("n_learned", ctypes.c_int64), ("n_fallback_range", ctypes.c_int64)]
 
     def as_dict(self) -> dict:
         d = {k: getattr(self, k) for k, _ in self._fields_ if k != "subcycle_hist"}

@@ -107,6 +107,33 @@ def sample_cells(state: dict, n: int, seed: int, lit_fraction: float = 0.8):
     return {k: state[k].reshape(-1)[idx].clone() for k in ("N", "xHI", "T", "nH")}
 
 
+def perturb_cells(cells: dict, seed: int, frac: float = 0.5, dex_T=(-0.15, 0.25),
+                  dex_xhi=(-2.0, 0.3), dex_N=(-0.5, 1.0)):
+    """Widen the training inputs beyond the states sampled: a fraction
+    `frac` of the cells gets T, xHI and N multiplied by 10^U(lo, hi) dex
+    (xHI kept in [1e-12, 1]).  The exact operator labels whatever state it
+    is given, so the pairs stay exact; the network then also covers the
+    states a run reaches later (hotter ionised gas, lower neutral fractions,
+    brighter regions), which its training-range test would otherwise send
+    back to the exact operator."""
+    import torch
+
+    n = cells["N"].numel()
+    g = torch.Generator(device=cells["N"].device)
+    g.manual_seed(seed)
+
+    def u(lo, hi):
+        return lo + (hi - lo) * torch.rand(n, generator=g, device=cells["N"].device)
+
+    pick = torch.rand(n, generator=g, device=cells["N"].device) < frac
+    out = {k: v.clone() for k, v in cells.items()}
+    out["T"] = torch.where(pick, cells["T"] * 10.0 ** u(*dex_T), cells["T"])
+    out["xHI"] = torch.where(pick, (cells["xHI"] * 10.0 ** u(*dex_xhi)).clamp(1e-12, 1.0),
+                             cells["xHI"])
+    out["N"] = torch.where(pick, cells["N"] * 10.0 ** u(*dex_N), cells["N"])
+    return out
+
+
 def _init_params(seed: int) -> np.ndarray:
     """He-style uniform initialisation (fan-in), biases zero."""
     rng = np.random.default_rng(seed)

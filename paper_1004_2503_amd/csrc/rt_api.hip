@@ -80,6 +80,9 @@ struct rt_ctx {
     double *d_fin = nullptr;   // first-level finalisation rows
     uint64_t *d_mask = nullptr;   // FP64 cells left by the step (mixed forms)
     uint64_t *d_gmask = nullptr;  // groups of 64 mask words holding a marked cell
+    uint32_t *d_goff = nullptr;   // marked cells per group -> offsets (deferred kernels)
+    uint32_t *d_cells = nullptr;  // dense list of the marked cells (one slot per cell)
+    uint64_t *d_mask2 = nullptr;  // the learned form's rejected cells
     uint64_t nwords = 0;
     int gwords = 0;               // 64-bit words of d_gmask
     int nb2 = 0;                  // blocks of the deferred FP64 chemistry
@@ -151,6 +154,9 @@ static void free_ctx(rt_ctx *c)
     if (c->d_fin) (void)hipFree(c->d_fin);
     if (c->d_mask) (void)hipFree(c->d_mask);
     if (c->d_gmask) (void)hipFree(c->d_gmask);
+    if (c->d_goff) (void)hipFree(c->d_goff);
+    if (c->d_cells) (void)hipFree(c->d_cells);
+    if (c->d_mask2) (void)hipFree(c->d_mask2);
     if (c->d_acc) (void)hipFree(c->d_acc);
     if (c->d_sink) (void)hipFree(c->d_sink);
     if (c->d_hcount) (void)hipFree(c->d_hcount);
@@ -205,6 +211,16 @@ static int z_chunk(int ntx, int ny, int nz)
 static int alloc_masks(rt_ctx *c)
 {
     if (!c->d_mask && hipMalloc(&c->d_mask, c->nwords * sizeof(uint64_t)) != hipSuccess) {
+        (void)hipGetLastError();
+        return RT_E_NOMEM;
+    }
+    if (!c->d_goff &&
+        hipMalloc(&c->d_goff, defer_offsets_size(c->nwords) * sizeof(uint32_t)) !=
+            hipSuccess) {
+        (void)hipGetLastError();
+        return RT_E_NOMEM;
+    }
+    if (!c->d_cells && hipMalloc(&c->d_cells, size_t(c->ncell) * sizeof(uint32_t)) != hipSuccess) {
         (void)hipGetLastError();
         return RT_E_NOMEM;
     }
@@ -669,7 +685,8 @@ extern "C" int rt_step(rt_ctx *c, double dt, int32_t nsub)
     fill_args(c, dt, nsub, a);
     const int rows = a.nblocks + defer_rows(a, c->nb2);
     if (rows > c->npart) return RT_E_STATE;   // the partials would not fit
-    if (a.defer && (!c->d_mask || !c->d_gmask)) return RT_E_STATE;
+    if (a.defer && (!c->d_mask || !c->d_gmask || !c->d_goff || !c->d_cells)) return RT_E_STATE;
+    if (a.surr && !c->d_mask2) return RT_E_STATE;
     Ev *e = nullptr;
     if (c->prof) {
         if (c->ev_used == c->ev.size()) {
@@ -682,7 +699,9 @@ extern "C" int rt_step(rt_ctx *c, double dt, int32_t nsub)
         if (hipEventRecord(e->a, c->stream) != hipSuccess) return RT_E_HIP;
     }
     if (launch_step(a, c->stream) != hipSuccess) return RT_E_HIP;
-    if (a.defer && launch_defer_chem(a, c->nwords, c->nb2, c->stream) != hipSuccess)
+    if (a.defer &&
+        launch_defer_chem(a, c->nwords, c->nb2, c->d_goff, c->d_cells, c->d_mask2, c->stream) !=
+            hipSuccess)
         return RT_E_HIP;
     if (e && hipEventRecord(e->b, c->stream) != hipSuccess) return RT_E_HIP;
     const double tau_coef = c->p.c_cms * SIGMA_T * dt / double(c->ncell);
@@ -729,6 +748,10 @@ extern "C" int rt_set_surrogate(rt_ctx *c, const float *theta, const float *norm
     {
         const int rc = alloc_masks(c);
         if (rc != RT_OK) return rc;
+    }
+    if (!c->d_mask2 && hipMalloc(&c->d_mask2, c->nwords * sizeof(uint64_t)) != hipSuccess) {
+        (void)hipGetLastError();
+        return RT_E_NOMEM;
     }
     const int offs[4] = {OFF_B1, OFF_B2, OFF_B3, OFF_B4};
     const int lens[4] = {MLP_NH, MLP_NH, MLP_NH, MLP_NOUT};

@@ -129,7 +129,12 @@ hipError_t launch_step(const StepArgs &a, hipStream_t s);
 // partial rows the two take.
 int defer_chem_blocks(uint64_t nwords);
 __host__ __device__ inline uint64_t mask_groups(uint64_t nwords) { return (nwords + 63) / 64; }
-hipError_t launch_defer_chem(const StepArgs &a, uint64_t nwords, int nb2, hipStream_t s);
+// goff: defer_offsets_size(nwords) entries (group and block offsets);
+// cells: one entry per cell of the grid (the dense list of marked cells);
+// mask2: a second mask of nwords words (the learned form's rejected cells).
+size_t defer_offsets_size(uint64_t nwords);
+hipError_t launch_defer_chem(const StepArgs &a, uint64_t nwords, int nb2, uint32_t *goff,
+                             uint32_t *cells, uint64_t *mask2, hipStream_t s);
 inline int defer_rows(const StepArgs &a, int nb2)
 {
     return a.defer ? ((a.surr && a.chem == RT_CHEM_FULL) ? 2 * nb2 : nb2) : 0;

@@ -25,6 +25,8 @@
 //     own L2.
 #include <math.h>
 
+#include <algorithm>
+
 #include "mlp_device.h"
 
 #ifndef RT_M1_NT_STORES
@@ -647,7 +649,7 @@ void m1_step_kernel(StepArgs A)
 // the mixed form's threshold, FP32 otherwise -- for the cells it does not
 // accept.  F is scaled by the photons left; the cell's share of the sums
 // that the step left out is reduced per block in a fixed order.
-constexpr int DEFER_THREADS = 256, DEFER_MAX_BLOCKS = 4096;
+constexpr int DEFER_THREADS = 256, DEFER_MAX_BLOCKS = 2048;
 constexpr int DEFER_WAVES = DEFER_THREADS / 64;
 
 // Learned chemistry of one cell from the network's standardised outputs
@@ -694,58 +696,179 @@ __device__ __forceinline__ bool surr_accept(const StepArgs &A, const float f[5],
            rx <= A.surr_tol && rT <= A.surr_tol;
 }
 
-// Marked cells of a deferred kernel's wavefront, in full batches.  The
-// wavefront visits its groups of 64 mask words (every waves-th group that
-// has a marked cell) a quarter (16 words) at a time and appends the linear
-// indices of their marked cells, in word order, to a ring in LDS; whenever
-// it holds 64 of them, `batch(cell, true)` runs on all lanes at once, so
-// every lane of every batch but the wavefront's last has a cell.  Appends
-// of one quarter are at most 16 x 64 cells, so the ring never holds more
-// than 63 + 1024.
-constexpr int QCAP = 2048;
-static_assert(QCAP >= 63 + 16 * 64 && (QCAP & (QCAP - 1)) == 0, "ring size");
+// ------------------------------------------- deferred cells, balanced
+// The deferred kernels share the marked cells out evenly.  A counting pass
+// gives every group of 64 mask words the rank of its first marked cell in
+// word order: block b of the pass takes groups [256 b, 256 b + 256),
+// counts their marked cells (only the groups whose bit is set hold any)
+// and writes their offsets within the block (loc[g]) and the block's total;
+// one block then turns the totals into exclusive block offsets
+// (boff[nbc] = the number of marked cells), so that the rank of group g's
+// first cell is boff[g / 256] + loc[g].  Wavefront k of a deferred kernel
+// takes the cells of ranks [k CHUNK, (k + 1) CHUNK), then the chunk a grid
+// further on: every wavefront gets the same number of cells however they
+// cluster, and which wavefront takes which cell depends only on the mask.
+constexpr int CHUNK = 256;          // cells per chunk: four batches of 64
+constexpr int GPB = 256;            // groups per counting block (4 wavefronts x 64)
+constexpr int SCAN_THREADS = 1024;
 
-template <typename F>
-__device__ __forceinline__ void marked_batches(const StepArgs &A, uint64_t nwords, uint32_t *ring,
-                                               F &&batch)
+__host__ __device__ inline uint64_t count_blocks(uint64_t nwords)
+{
+    return (mask_groups(nwords) + GPB - 1) / GPB;
+}
+
+// Offsets of the groups of src, see above; loc: ngroups entries, boff:
+// count_blocks + 1 (the totals here, turned into offsets by
+// block_offsets_kernel).  With copy, the words of the groups whose bit is
+// set are also copied there.
+__global__ __launch_bounds__(GPB) void mask_count_kernel(const StepArgs A, const uint64_t *src,
+                                                         uint64_t *copy, uint64_t nwords,
+                                                         uint32_t *loc, uint32_t *boff)
+{
+    __shared__ uint32_t s_cnt[GPB];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const uint64_t ngroups = mask_groups(nwords);
+    const uint64_t g0 = uint64_t(blockIdx.x) * GPB + uint64_t(wave) * 64;   // 64-aligned
+    s_cnt[t] = 0u;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    uint64_t bits = g0 < ngroups ? A.group_mask[g0 >> 6] : 0ull;
+    while (bits) {
+        // up to four marked groups at a time, their loads in flight together
+        int gi[4];
+        uint64_t wd[4];
+        int n = 0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            gi[j] = bits ? __builtin_ctzll(bits) : 0;
+            n += bits ? 1 : 0;
+            bits &= bits ? bits - 1ull : 0ull;
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint64_t w = (g0 + uint64_t(gi[j])) * 64 + uint64_t(lane);
+            wd[j] = (j < n && w < nwords) ? src[w] : 0ull;
+            if (copy && j < n && w < nwords) copy[w] = wd[j];
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            int c = __popcll(wd[j]);
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
+            if (lane == 0 && j < n) s_cnt[wave * 64 + gi[j]] = uint32_t(c);
+        }
+    }
+    __syncthreads();
+    // exclusive scan of the block's 256 counts (one per thread)
+    const uint32_t mine = s_cnt[t];
+    uint32_t incl = mine;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t v = __shfl_up(incl, off);
+        if (lane >= off) incl += v;
+    }
+    __shared__ uint32_t s_wsum[GPB / 64];
+    if (lane == 63) s_wsum[wave] = incl;
+    __syncthreads();
+    uint32_t before = 0;
+    for (int w2 = 0; w2 < wave; ++w2) before += s_wsum[w2];
+    const uint64_t g = uint64_t(blockIdx.x) * GPB + uint64_t(t);
+    if (g < ngroups) loc[g] = before + incl - mine;
+    if (t == GPB - 1) boff[blockIdx.x] = before + incl;
+}
+
+// boff[0 .. nb) block totals -> exclusive offsets, boff[nb] = their sum.
+__global__ __launch_bounds__(SCAN_THREADS) void block_offsets_kernel(uint32_t *boff, int nb)
+{
+    __shared__ uint32_t s[SCAN_THREADS];
+    const int t = threadIdx.x;
+    const int per = (nb + SCAN_THREADS - 1) / SCAN_THREADS;
+    const int lo = t * per, hi = lo + per < nb ? lo + per : nb;
+    uint32_t sum = 0;
+    for (int i = lo; i < hi; ++i) sum += boff[i];
+    s[t] = sum;
+    __syncthreads();
+    for (int off = 1; off < SCAN_THREADS; off <<= 1) {   // inclusive scan of the run sums
+        const uint32_t v = t >= off ? s[t - off] : 0u;
+        __syncthreads();
+        s[t] += v;
+        __syncthreads();
+    }
+    uint32_t run = s[t] - sum;
+    for (int i = lo; i < hi; ++i) {
+        const uint32_t c = boff[i];
+        boff[i] = run;
+        run += c;
+    }
+    if (t == SCAN_THREADS - 1) boff[nb] = s[t];
+}
+
+// The marked cells of src as a dense list in word order: cells[rank] =
+// linear cell index, ranks from loc and boff (mask_count_kernel and
+// block_offsets_kernel on the same src first).  Same blocks as the count.
+__global__ __launch_bounds__(GPB) void mask_compact_kernel(const StepArgs A, const uint64_t *src,
+                                                           uint64_t nwords, const uint32_t *loc,
+                                                           const uint32_t *boff,
+                                                           uint32_t *cells)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const uint64_t waves = uint64_t(gridDim.x) * DEFER_WAVES, ngroups = mask_groups(nwords);
-    int head = 0, pending = 0;   // wavefront-uniform
-    for (uint64_t g = uint64_t(blockIdx.x) * DEFER_WAVES + wave; g < ngroups; g += waves) {
-        if (!((A.group_mask[g >> 6] >> (g & 63)) & 1ull)) continue;   // no marked cell
-        const uint64_t w = g * 64 + uint64_t(lane);
-        const uint64_t word = w < nwords ? A.fp64_mask[w] : 0ull;
-        // cell index of bit 0 of this lane's word: row (z ny + y), tile column
-        const uint32_t cell0 =
-            uint32_t(w / uint64_t(A.ntx)) * uint32_t(A.nx) + uint32_t(w % uint64_t(A.ntx)) * TX;
-#pragma unroll 1
-        for (int qtr = 0; qtr < 4; ++qtr) {
-            const uint64_t mine = (lane >> 4) == qtr ? word : 0ull;
-            const int cnt = __popcll(mine);
+    const uint64_t ngroups = mask_groups(nwords);
+    const uint64_t g0 = uint64_t(blockIdx.x) * GPB + uint64_t(wave) * 64;   // 64-aligned
+    const uint32_t bbase = boff[blockIdx.x];
+    uint64_t bits = g0 < ngroups ? A.group_mask[g0 >> 6] : 0ull;
+    while (bits) {
+        int gi[4];
+        uint64_t wd[4];
+        int n = 0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            gi[j] = bits ? __builtin_ctzll(bits) : 0;
+            n += bits ? 1 : 0;
+            bits &= bits ? bits - 1ull : 0ull;
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint64_t w = (g0 + uint64_t(gi[j])) * 64 + uint64_t(lane);
+            wd[j] = (j < n && w < nwords) ? src[w] : 0ull;
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            if (j >= n) break;
+            const uint64_t g = g0 + uint64_t(gi[j]);
+            const int cnt = __popcll(wd[j]);
             int incl = cnt;
 #pragma unroll
             for (int off = 1; off < 64; off <<= 1) {
                 const int v = __shfl_up(incl, off);
                 if (lane >= off) incl += v;
             }
-            const int total = __shfl(incl, 63);
-            if (total == 0) continue;
-            int pos = head + pending + incl - cnt;
-            for (uint64_t m = mine; m; m &= m - 1ull)
-                ring[(pos++) & (QCAP - 1)] = cell0 + uint32_t(__builtin_ctzll(m));
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            pending += total;
-            while (pending >= 64) {
-                batch(ring[(head + lane) & (QCAP - 1)], true);
-                head = (head + 64) & (QCAP - 1);
-                pending -= 64;
-            }
+            uint32_t r = bbase + loc[g] + uint32_t(incl - cnt);
+            const uint64_t w = g * 64 + uint64_t(lane);
+            const uint32_t cell0 = uint32_t(w / uint64_t(A.ntx)) * uint32_t(A.nx) +
+                                   uint32_t(w % uint64_t(A.ntx)) * TX;
+            for (uint64_t m = wd[j]; m; m &= m - 1ull) cells[r++] = cell0 + uint32_t(__builtin_ctzll(m));
         }
     }
-    if (pending > 0) batch(lane < pending ? ring[(head + lane) & (QCAP - 1)] : 0u, lane < pending);
+}
+
+// The cells of this wavefront's chunks of the dense list, four batches of
+// 64 per chunk: `batch(cell, valid)` on all lanes at once.
+template <typename F>
+__device__ __forceinline__ void marked_chunks(const uint64_t nwords, const uint32_t *boff,
+                                              const uint32_t *cells, F &&batch)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint32_t total = boff[count_blocks(nwords)];
+    const uint32_t nchunks = (total + CHUNK - 1) / CHUNK;
+    const uint32_t waves = gridDim.x * DEFER_WAVES;
+    for (uint32_t k = blockIdx.x * DEFER_WAVES + wave; k < nchunks; k += waves) {
+        const uint32_t c0 = k * CHUNK, c1 = c0 + CHUNK < total ? c0 + CHUNK : total;
+        for (uint32_t b0 = c0; b0 < c1; b0 += 64) {
+            const bool valid = b0 + uint32_t(lane) < c1;
+            batch(valid ? cells[b0 + lane] : 0u, valid);
+        }
+    }
 }
 
 // Per-block partial row of the deferred kernels' sums, in a fixed order.
@@ -787,9 +910,9 @@ __device__ __forceinline__ void defer_partials(const StepArgs &A, int row, doubl
 // The exact operator Phi of the cells still marked: FP64 below the mixed
 // form's threshold, FP32 otherwise.  Partial rows from A.nblocks + row0.
 __global__ __launch_bounds__(DEFER_THREADS) void defer_chem_kernel(StepArgs A, uint64_t nwords,
-                                                                   int row0)
+                                                                   const uint32_t *boff,
+                                                                   const uint32_t *cells, int row0)
 {
-    __shared__ uint32_t s_ring[DEFER_WAVES][QCAP];
     __shared__ double sred[DEFER_WAVES][NRED];
     __shared__ int shist[8];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -801,7 +924,7 @@ __global__ __launch_bounds__(DEFER_THREADS) void defer_chem_kernel(StepArgs A, u
                           A.T_floor, A.sub_eps,            A.inv15kB};
     double acc_xhi = 0.0, acc_nhxhi = 0.0, acc_N = 0.0, acc_abs = 0.0;
     int n_bad = 0, n_fp64 = 0;
-    marked_batches(A, nwords, s_ring[wave], [&](uint32_t i, bool valid) {
+    marked_chunks(nwords, boff, cells, [&](uint32_t i, bool valid) {
         float Nt = 0.0f, Fx = 0.0f, Fy = 0.0f, Fz = 0.0f;
         float c_xh = 1.0f, c_T = 1.0e4f, c_nh = 1.0f;
         if (valid) {
@@ -869,9 +992,11 @@ __global__ __launch_bounds__(DEFER_THREADS) void defer_chem_kernel(StepArgs A, u
 // a rejected cell stays marked (the word is written back with only those
 // bits) for defer_chem_kernel, which then runs the exact operator on the
 // rejected cells alone, in dense wavefronts.  Partial rows from A.nblocks.
-__global__ __launch_bounds__(DEFER_THREADS) void surr_chem_kernel(StepArgs A, uint64_t nwords)
+__global__ __launch_bounds__(DEFER_THREADS) void surr_chem_kernel(StepArgs A, uint64_t nwords,
+                                                                  const uint32_t *boff,
+                                                                  const uint32_t *cells,
+                                                                  uint64_t *rejected)
 {
-    __shared__ uint32_t s_ring[DEFER_WAVES][QCAP];
     __shared__ __attribute__((aligned(16))) __bf16 s_pk[PK_FWD * 8];
     __shared__ float s_bias[SURR_NBIAS];
     __shared__ double sred[DEFER_WAVES][NRED];
@@ -886,7 +1011,7 @@ __global__ __launch_bounds__(DEFER_THREADS) void surr_chem_kernel(StepArgs A, ui
     int n_bad = 0, n_fb = 0, n_net = 0, n_range = 0;
     const MlpBias mb{s_bias, s_bias + 64, s_bias + 128, s_bias + 192};
     const float *nm = A.surr_norm;
-    marked_batches(A, nwords, s_ring[wave], [&](uint32_t i, bool valid) {
+    marked_chunks(nwords, boff, cells, [&](uint32_t i, bool valid) {
         float Nt = 0.0f, c_xh = 1.0f, c_T = 1.0e4f, c_nh = 1.0f;
         if (valid) {
             Nt = A.No[i];
@@ -931,10 +1056,12 @@ __global__ __launch_bounds__(DEFER_THREADS) void surr_chem_kernel(StepArgs A, ui
             n_fb += 1;
             n_range += ood ? 1 : 0;
         }
-        // Accepted cells leave the mask, so that the exact kernel takes only
-        // the rejected ones.  The batch's cells come in word order: the
-        // lanes of one word OR their bits together (a segmented scan) and
-        // the word's last lane clears them with one atomic.
+        // Accepted cells leave the copy of the mask that the exact kernel
+        // reads next (`rejected`; the mask this kernel reads stays as it is),
+        // so that the exact kernel takes only the rejected ones.  The
+        // batch's cells come in word order: the lanes of one word OR their
+        // bits together (a segmented scan) and the word's last lane clears
+        // them with one atomic.
         const uint32_t x = i % uint32_t(A.nx);
         // (lanes without a cell take a word index no cell has)
         const uint64_t wd = valid ? uint64_t(i / uint32_t(A.nx)) * uint64_t(A.ntx) + uint64_t(x / TX)
@@ -948,7 +1075,7 @@ __global__ __launch_bounds__(DEFER_THREADS) void surr_chem_kernel(StepArgs A, ui
         }
         const uint64_t next = __shfl_down(wd, 1);
         const bool last = valid && (lane == 63 || next != wd);
-        if (last && bits) atomicAnd(reinterpret_cast<unsigned long long *>(&A.fp64_mask[wd]),
+        if (last && bits) atomicAnd(reinterpret_cast<unsigned long long *>(&rejected[wd]),
                                     ~(unsigned long long)bits);
         if (A.count_hist) {
             // accepted cells count in the first bin; the exact kernel counts
@@ -962,22 +1089,49 @@ __global__ __launch_bounds__(DEFER_THREADS) void surr_chem_kernel(StepArgs A, ui
     defer_partials(A, A.nblocks + int(blockIdx.x), sred, shist, v, lane, wave, tid);
 }
 
-// Blocks of the deferred kernels: about 16 groups of 64 mask words per
-// wavefront, at most DEFER_MAX_BLOCKS.
+size_t defer_offsets_size(uint64_t nwords)
+{
+    return size_t(mask_groups(nwords) + count_blocks(nwords) + 1);
+}
+
+// Blocks of the deferred kernels: enough wavefronts to fill the chip
+// whatever the number of marked cells (they share the chunks of CHUNK
+// cells), fewer on small grids.
 int defer_chem_blocks(uint64_t nwords)
 {
-    const uint64_t want = (mask_groups(nwords) + 16 * DEFER_WAVES - 1) / (16 * DEFER_WAVES);
+    const uint64_t want = (nwords * 64 / CHUNK + DEFER_WAVES - 1) / DEFER_WAVES;
     return int(want < 1 ? 1 : (want > DEFER_MAX_BLOCKS ? DEFER_MAX_BLOCKS : want));
 }
 
-hipError_t launch_defer_chem(const StepArgs &a, uint64_t nwords, int nb2, hipStream_t s)
+hipError_t launch_defer_chem(const StepArgs &a, uint64_t nwords, int nb2, uint32_t *goff,
+                             uint32_t *cells, uint64_t *mask2, hipStream_t s)
 {
+    const uint64_t nbc = count_blocks(nwords);
+    uint32_t *loc = goff, *boff = goff + mask_groups(nwords);
+    // the marked cells of `mask` into the dense list (copying the marked
+    // groups' words to `copy` on the way when it is given)
+    auto list = [&](const uint64_t *mask, uint64_t *copy) {
+        hipLaunchKernelGGL(mask_count_kernel, dim3(unsigned(nbc)), dim3(GPB), 0, s, a, mask, copy,
+                           nwords, loc, boff);
+        hipLaunchKernelGGL(block_offsets_kernel, dim3(1), dim3(SCAN_THREADS), 0, s, boff,
+                           int(nbc));
+        hipLaunchKernelGGL(mask_compact_kernel, dim3(unsigned(nbc)), dim3(GPB), 0, s, a, mask,
+                           nwords, static_cast<const uint32_t *>(loc),
+                           static_cast<const uint32_t *>(boff), cells);
+    };
+    const uint64_t *exact_mask = a.fp64_mask;
     int row0 = 0;
     if (a.surr && a.chem == RT_CHEM_FULL) {
-        hipLaunchKernelGGL(surr_chem_kernel, dim3(nb2), dim3(DEFER_THREADS), 0, s, a, nwords);
+        list(a.fp64_mask, mask2);
+        hipLaunchKernelGGL(surr_chem_kernel, dim3(nb2), dim3(DEFER_THREADS), 0, s, a, nwords,
+                           static_cast<const uint32_t *>(boff), static_cast<const uint32_t *>(cells),
+                           mask2);
+        exact_mask = mask2;
         row0 = nb2;
     }
+    list(exact_mask, nullptr);
     hipLaunchKernelGGL(defer_chem_kernel, dim3(nb2), dim3(DEFER_THREADS), 0, s, a, nwords,
+                       static_cast<const uint32_t *>(boff), static_cast<const uint32_t *>(cells),
                        row0);
     return hipGetLastError();
 }

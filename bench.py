@@ -352,7 +352,7 @@ def diagnostics_leg(G, w, reps: int = 5):
     out["tau_e"] = G.reduce()["tau_e"]
     # Sec. 3.1.5 analysis: plateau rate below 1e-3 cm^-3, then the equilibrium
     # neutral fraction under the plateau, J1 and J4 models at a few densities
-    g0 = rt.gamma_plateau(counts, sums, xr, 1e-3)
+    g0, _ = G.gamma_plateau(1e-3)
     dens = torch.tensor([1e-4, 1e-3, 1e-2, 1e-1], dtype=torch.float64, device=G.device)
     temp = torch.full_like(dens, 1e4)
     eq = {"gamma0": g0, "nH": dens.tolist()}

@@ -253,9 +253,11 @@ int rt_step(rt_ctx *ctx, double dt, int32_t nsub);
 int rt_set_surrogate(rt_ctx *ctx, const float *theta, const float *norm, double residual_tol);
 
 /* Wait for the stream and report the sums of the last step (or of the
- * initial state before any step) and the cumulative tallies.  Returns
- * RT_E_NONFINITE (with *out filled) if any step produced a non-finite
- * value. */
+ * initial state before any step) and the cumulative tallies: the volume-
+ * and mass-weighted neutral fractions and the volume-averaged
+ * photoionisation rate whose histories Sec. 3.1.1-3.1.3 follow, the photon
+ * budget, and the Thomson depth of Sec. 3.1.4.  Returns RT_E_NONFINITE
+ * (with *out filled) if any step produced a non-finite value. */
 int rt_reduce(rt_ctx *ctx, rt_reductions *out);
 
 /* Quantities binned by rt_histogram against the cell density. */
@@ -272,7 +274,8 @@ int rt_reduce(rt_ctx *ctx, rt_reductions *out);
  * (c_cms * sigma_n) * N evaluated in FP64 for RT_HQ_GAMMA.
  * counts (host, nbx * nby int64, row ix: counts[ix * nby + iy]) receives
  * the exact cell counts; sum_q (host, nbx doubles) the FP64 sum of q over
- * the cells of each density bin (summation order unspecified).  Both are
+ * the cells of each density bin (in a fixed order: the same state gives the
+ * same sums bit for bit).  Both are
  * overwritten.  1 <= nbx, nby <= 256, nbx * nby <= RT_HIST_MAX_BINS,
  * lo < hi, |lo|, |hi| <= 300, else RT_E_ARG.  Waits for the stream. */
 int rt_histogram(rt_ctx *ctx, int32_t quantity, int32_t nbx, double lox, double hix,
@@ -303,9 +306,19 @@ int rt_equilibrium_xhi(const rt_params *params, int32_t model, double gamma0, do
                        int64_t n, const double *nH, const double *T, double *xhi,
                        void *hip_stream);
 
+/* Plateau of the photoionisation rate (Sec. 3.1.5: at low density the
+ * intensity of a run is nearly constant, and its mean there is taken as the
+ * J0 of the self-shielding models): *gamma0 = the mean of c_cms * sigma_n * N
+ * over the cells of the current state with nH < nH_max [cm^-3], in FP64 and
+ * in a fixed summation order; *ncells (may be NULL) receives how many cells
+ * that is.  RT_E_ARG for nH_max not positive and finite, or when no cell lies
+ * below it (*ncells = 0 then).  Waits for the stream. */
+int rt_gamma_plateau(rt_ctx *ctx, double nH_max, double *gamma0, int64_t *ncells);
+
 /* Copy field `field` (RT_FIELD_*) of the current state into dst (nx*ny*nz
  * floats; device memory if dst_on_device != 0, else host memory) and wait
- * for the copy. */
+ * for the copy: the output step of Appendix A, where the host reads the
+ * fields back from the device (the paper every few thousand steps). */
 int rt_state(rt_ctx *ctx, int32_t field, void *dst, int32_t dst_on_device);
 
 /* Index (0 or 1) of the N/F buffer that holds the current state. */

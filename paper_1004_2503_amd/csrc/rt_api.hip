@@ -90,6 +90,7 @@ struct rt_ctx {
     float *d_sink = nullptr;
     unsigned long long *d_hcount = nullptr;  // RT_HIST_MAX_BINS
     double *d_hsum = nullptr;                // 256 + edges 2 * 257
+    double *d_hpart = nullptr;               // histogram partial rows: blocks x 256
     double t = 0.0, emitted = 0.0, photons_initial = 0.0, nh_sum = 0.0;
     int64_t steps = 0;
     int64_t hist_host[8] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -161,6 +162,7 @@ static void free_ctx(rt_ctx *c)
     if (c->d_sink) (void)hipFree(c->d_sink);
     if (c->d_hcount) (void)hipFree(c->d_hcount);
     if (c->d_hsum) (void)hipFree(c->d_hsum);
+    if (c->d_hpart) (void)hipFree(c->d_hpart);
     if (c->d_surr_pk) (void)hipFree(c->d_surr_pk);
     if (c->d_surr_bias) (void)hipFree(c->d_surr_bias);
     for (auto &e : c->ev) {
@@ -275,7 +277,8 @@ extern "C" int rt_init(const rt_params *params, const rt_fields *fields, void *h
     // partial rows: a step writes one per block of whichever tile set it
     // runs on, then the deferred chemistry nb2 more after them
     c->npart = std::max(std::max(c->geo[0].nblocks, c->geo[1].nblocks) + 2 * c->nb2,
-                        state_sums_blocks(c->ncell));
+                        std::max(state_sums_blocks(c->ncell),
+                                 (2 * plateau_blocks(c->ncell) + NRED - 1) / NRED));
     if (defer) {
         rc = alloc_masks(c);
         if (rc != RT_OK) {
@@ -293,7 +296,9 @@ extern "C" int rt_init(const rt_params *params, const rt_fields *fields, void *h
             hipSuccess ||
         hipMalloc(&c->d_sink, NTHREADS_MAX * sizeof(float)) != hipSuccess ||
         hipMalloc(&c->d_hcount, RT_HIST_MAX_BINS * sizeof(unsigned long long)) != hipSuccess ||
-        hipMalloc(&c->d_hsum, HSUM_DOUBLES * sizeof(double)) != hipSuccess) {
+        hipMalloc(&c->d_hsum, HSUM_DOUBLES * sizeof(double)) != hipSuccess ||
+        hipMalloc(&c->d_hpart, size_t(hist_blocks(c->ncell)) * 256 * sizeof(double)) !=
+            hipSuccess) {
         (void)hipGetLastError();
         free_ctx(c);
         return RT_E_NOMEM;
@@ -844,10 +849,9 @@ extern "C" int rt_histogram(rt_ctx *c, int32_t quantity, int32_t nbx, double lox
                        hipMemcpyHostToDevice, c->stream) != hipSuccess ||
         hipMemsetAsync(c->d_hcount, 0, hc.size() * sizeof(unsigned long long), c->stream) !=
             hipSuccess ||
-        hipMemsetAsync(d_sum, 0, size_t(nbx) * sizeof(double), c->stream) != hipSuccess ||
         launch_hist(c->f.nH, q, quantity == RT_HQ_GAMMA, c->p.c_cms * c->p.sigma_n, c->ncell,
                     nbx, nby, d_edges, float(lox), float(1.0 / wx), float(loy),
-                    float(1.0 / wy), c->d_hcount, d_sum, c->stream) != hipSuccess ||
+                    float(1.0 / wy), c->d_hcount, c->d_hpart, d_sum, c->stream) != hipSuccess ||
         hipMemcpyAsync(hc.data(), c->d_hcount, hc.size() * sizeof(unsigned long long),
                        hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
         hipMemcpyAsync(sum_q, d_sum, size_t(nbx) * sizeof(double), hipMemcpyDeviceToHost,
@@ -855,6 +859,22 @@ extern "C" int rt_histogram(rt_ctx *c, int32_t quantity, int32_t nbx, double lox
         hipStreamSynchronize(c->stream) != hipSuccess)
         return RT_E_HIP;
     for (size_t i = 0; i < hc.size(); ++i) counts[i] = int64_t(hc[i]);
+    return RT_OK;
+}
+
+extern "C" int rt_gamma_plateau(rt_ctx *c, double nH_max, double *gamma0, int64_t *ncells)
+{
+    if (!c) return RT_E_STATE;
+    if (!gamma0 || !(nH_max > 0.0) || !isfinite(nH_max)) return RT_E_ARG;
+    double h[2] = {0.0, 0.0};
+    if (launch_plateau(c->f.nH, c->f.N[c->cur], c->ncell, nH_max, c->p.c_cms * c->p.sigma_n,
+                       c->d_part, c->d_fin, c->stream) != hipSuccess ||
+        hipMemcpyAsync(h, c->d_fin, sizeof(h), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess)
+        return RT_E_HIP;
+    if (ncells) *ncells = int64_t(h[1]);
+    if (!(h[1] > 0.0)) return RT_E_ARG;
+    *gamma0 = h[0] / h[1];
     return RT_OK;
 }
 

@@ -158,10 +158,17 @@ hipError_t launch_finalize(const double *partials, int nblocks, double *scratch,
                            int mode, double tau_coef, double nh_sum, hipStream_t s,
                            uint64_t *clear = nullptr, int nclear = 0);
 size_t hist_lds_bytes(int nbx, int nby);
+// histogram blocks for ncell cells; each writes a partial row of nbx sums
+constexpr int HIST_MAX_BLOCKS = 2048;
+int hist_blocks(uint32_t ncell);
 hipError_t launch_hist(const float *nH, const float *q, int gamma, double csig, uint32_t ncell,
                        int nbx, int nby, const double *edges, float lox, float inv_wx,
-                       float loy, float inv_wy, unsigned long long *counts, double *sums,
-                       hipStream_t s);
+                       float loy, float inv_wy, unsigned long long *counts, double *partials,
+                       double *sums, hipStream_t s);
+// plateau: part holds 2 plateau_blocks(ncell) doubles; out 2 (sum, count)
+int plateau_blocks(uint32_t ncell);
+hipError_t launch_plateau(const float *nH, const float *N, uint32_t ncell, double nh_max,
+                          double csig, double *part, double *out, hipStream_t s);
 hipError_t launch_equilibrium(int64_t n, const double *nH, const double *T, double *xhi,
                               int model, double gamma0, double n_star, const rt_params &p,
                               hipStream_t s);

@@ -298,6 +298,12 @@ class RTGrid:
         check(rc, "rt_sources_from_particles")
         return m
 
+    def gamma_plateau(self, nH_max: float):
+        """(gamma0, ncells): mean photoionisation rate below nH_max."""
+        rc, g, n = rt_gamma_plateau(self.ctx, nH_max)
+        check(rc, "rt_gamma_plateau")
+        return g, n
+
     def histogram(self, quantity: int, xrange, yrange):
         """(counts, per-density-bin sums) of the current state, see rt_histogram."""
         rc, counts, sums = rt_histogram(self.ctx, quantity, xrange, yrange)
@@ -474,14 +480,17 @@ def equilibrium_xhi(params: rt_params, model: int, gamma0: float, n_star: float,
     return out
 
 
-def gamma_plateau(counts, sums, xrange, nH_max: float) -> float:
-    """The plateau rate J0 (as Gamma) from an RT_HQ_GAMMA histogram: the mean
-    rate over the density bins whose upper edge is at most nH_max."""
-    lo, hi, nb = xrange
-    w = (hi - lo) / nb
-    upper = np.array([10.0 ** (lo + (k + 1) * w) for k in range(nb)])
-    sel = upper <= nH_max
-    n = int(np.asarray(counts)[sel].sum())
-    if n == 0:
-        raise ValueError("no cells below nH_max")
-    return float(np.asarray(sums)[sel].sum() / n)
+EXPORTS += ["rt_gamma_plateau"]
+
+
+def rt_gamma_plateau(ctx, nH_max: float):
+    """Returns (code, gamma0, ncells)."""
+    L = lib()
+    L.rt_gamma_plateau.argtypes = [ctypes.c_void_p, ctypes.c_double,
+                                   ctypes.POINTER(ctypes.c_double),
+                                   ctypes.POINTER(ctypes.c_int64)]
+    L.rt_gamma_plateau.restype = ctypes.c_int
+    g = ctypes.c_double()
+    n = ctypes.c_int64()
+    rc = L.rt_gamma_plateau(ctx, float(nH_max), ctypes.byref(g), ctypes.byref(n))
+    return rc, g.value, n.value

@@ -223,10 +223,13 @@ def test_equilibrium_curves_of_an_evolved_state(evolved64):
     counts, sums = G.histogram(rt.HQ_GAMMA, xr, yr)
     edges = D.log_edges(*xr)
     cut = edges[30]                                    # 10^-2.25 cm^-3
-    g0 = rt.gamma_plateau(counts.sum(axis=1), sums, xr, cut)
+    g0, ncut = G.gamma_plateau(cut)
     gam = D.photoionisation_rate(st["N"], C, rt.SIGMA_N)
     want0 = D.gamma_plateau(st["nH"], gam, cut)
     assert g0 == pytest.approx(want0, rel=1e-12)
+    assert ncut == int((np.asarray(st["nH"], np.float64) < cut).sum())
+    # the same state gives the same plateau bit for bit
+    assert G.gamma_plateau(cut)[0] == g0
     assert g0 > 0.0
     centres = np.sqrt(edges[:-1] * edges[1:])
     T = np.full_like(centres, 1e4)
@@ -237,3 +240,16 @@ def test_equilibrium_curves_of_an_evolved_state(evolved64):
         _compare_eq(y, D.xhi_equilibrium(centres, T, D.gamma_model(model, g0, ns, centres)))
         # denser gas is more neutral (up to rounding once collisions alone set it)
         assert np.all(np.diff(y) >= -4e-16)
+
+
+@pytest.mark.parametrize("quantity", [rt.HQ_XHI, rt.HQ_GAMMA])
+def test_histogram_sums_bit_identical_on_rerun(evolved64, quantity):
+    # the per-density-bin FP64 sums are added in a fixed order (no float
+    # atomics): the same state gives the same sums bit for bit
+    G, st = evolved64
+    yr = (-7.0, 0.5, 64) if quantity == rt.HQ_XHI else (-16.0, -8.0, 64)
+    c1, s1 = G.histogram(quantity, (-6.0, 0.0, 48), yr)
+    c2, s2 = G.histogram(quantity, (-6.0, 0.0, 48), yr)
+    assert np.array_equal(c1, c2)
+    assert np.array_equal(s1.view(np.uint64), s2.view(np.uint64))
+    assert np.any(s1 != 0.0)

@@ -211,3 +211,52 @@ def test_mixed_lf_on_64x8_tiles_with_many_deferred_blocks():
     vol = DX ** 3
     assert red["photons_stored"] == pytest.approx(g["N"].astype(np.float64).sum() * vol,
                                                   rel=1e-12)
+
+
+@pytest.mark.parametrize("sub", [rt.SUB_FIXED, rt.SUB_ADAPTIVE])
+def test_checkpoint_and_resume_is_bit_identical(sub):
+    # Export the state through rt_state after some steps, start a new
+    # context from it and continue: every field equals, bit for bit, that of
+    # a run that was never interrupted (the step depends only on the state
+    # and the sources).
+    shape = (40, 36, 70)
+    st = W.random_state(shape, seed=505, nmax=1e-2)
+    src = sources_for(shape, 25, 12)
+    params = rt.make_params(shape, DX, bc=MIXED_BC, prec=rt.PREC_MIXED, sub=sub)
+    G = rt.RTGrid(params, st)
+    G.inject_sources(*src)
+    G.step(DT, 8, 12)
+    whole = G.state_numpy()
+    G.close()
+    G = rt.RTGrid(params, st)
+    G.inject_sources(*src)
+    G.step(DT, 8, 5)
+    ckpt = G.state_numpy()
+    G.close()
+    R = rt.RTGrid(params, ckpt)
+    R.inject_sources(*src)
+    R.step(DT, 8, 7)
+    resumed = R.state_numpy()
+    R.close()
+    for k in whole:
+        assert np.array_equal(whole[k].view(np.uint32), resumed[k].view(np.uint32)), k
+
+
+def test_dark_neutral_cells_below_the_temperature_floor():
+    # Dark, fully neutral cells skip the chemistry's arithmetic in the step
+    # kernel, but the full chemistry still lifts T to T_floor there, as the
+    # operator does on every sub-cycle; T below the floor in dark cells (and
+    # in lit ones) must come out as the oracle's.
+    shape = (20, 18, 66)
+    st = W.random_state(shape, seed=606, nmax=1e-3)
+    for k in ("N", "Fx", "Fy", "Fz"):
+        st[k][:, :, :33] = 0.0
+    st["xHI"][:, :, :30] = 1.0
+    st["T"][:, :, ::3] = 4.0                       # below the 10 K floor
+    for prec in (rt.PREC_FP32, rt.PREC_MIXED):
+        g, o, red, _ = one_step_pair(st, shape, DX, DT, 2, (rt.BC_PERIODIC,) * 6,
+                                     rt.CHEM_FULL, prec)
+        assert_parity(errors(g, o), what=f"T below the floor, prec {prec}")
+        dark = (o["N"] == 0) & (st["xHI"] >= 1.0)
+        assert dark.any()
+        assert np.all(g["T"][dark] >= 10.0)

@@ -215,3 +215,86 @@ def test_cosmo1024_sampled_subblocks(flux):
           flush=True)
     G.close()
     torch.cuda.empty_cache()
+
+
+def _blocks(t, origins, B, halo, n):
+    """Sub-blocks of a device field at the given origins (batched gather),
+    periodic wrap, as FP64 host arrays of shape (len(origins), B+2h, ...)."""
+    o = torch.tensor(origins, device=t.device, dtype=torch.int64)
+    r = torch.arange(-halo, B + halo, device=t.device)
+    zz = (o[:, 0:1] + r) % n
+    yy = (o[:, 1:2] + r) % n
+    xx = (o[:, 2:3] + r) % n
+    a = t[zz[:, :, None, None], yy[:, None, :, None], xx[:, None, None, :]]
+    return a.double().cpu().numpy()
+
+
+@pytest.mark.timeout(900)
+def test_cosmo1024_every_source_cell_and_the_faces():
+    """The benchmark configuration (LF, 64 x 16 tiles, 128-plane chunks,
+    deferred FP64 chemistry) after 20 steps, one more step checked against
+    the oracle on every cell of every aligned 16^3 block that holds a
+    source (so on every source cell), and on 16 random 32^3 blocks against
+    each of the six faces of the periodic box (where the stencil wraps)."""
+    w = W.workload("cosmo1024")
+    n = w.n
+    nH, ijk, ndot = W.cosmo_inputs(w, device="cuda")
+    G = rt.RTGrid(rt.make_params((n,) * 3, w.dx, prec=rt.PREC_MIXED), dict(nH=nH))
+    del nH
+    G.inject_sources(ijk, ndot)
+    G.step(w.dt, 1, 20)
+    pre = {k: v.clone() for k, v in G.tensors().items() if k in ("xHI", "T")}
+    G.step(w.dt, 1)
+    post = G.tensors()
+    cur = G.current()
+    Nin, Fin = G.N[1 - cur], [G.Fx[1 - cur], G.Fy[1 - cur], G.Fz[1 - cur]]
+    vol = w.dx ** 3
+    rng = np.random.default_rng(2048)
+    src_blocks = sorted({(int(k) // 16 * 16, int(j) // 16 * 16, int(i) // 16 * 16)
+                         for i, j, k in ijk})
+    face_blocks = []
+    for axis in range(3):
+        for side in (0, n - 32):
+            for _ in range(16):
+                o = [int(v) for v in rng.integers(0, n - 32 + 1, 3)]
+                o[axis] = side
+                face_blocks.append(tuple(o))
+    print(f"1024^3: {len(src_blocks)} source blocks of 16^3 for {len(ijk)} sources, "
+          f"{len(face_blocks)} face blocks", flush=True)
+    worst = dict(N=0.0, F=0.0, xHI=0.0, T=0.0)
+    checked_src = 0
+    for B, blocks in ((16, src_blocks), (32, face_blocks)):
+        p = oracle.make_params((B, B, B), w.dx, chem=oracle.CHEM_FULL)
+        for b0 in range(0, len(blocks), 256):
+            batch = blocks[b0:b0 + 256]
+            Nb = _blocks(Nin, batch, B, 1, n)
+            Fb = [_blocks(f, batch, B, 1, n) for f in Fin]
+            xb, Tb = _blocks(pre["xHI"], batch, B, 0, n), _blocks(pre["T"], batch, B, 0, n)
+            hb = _blocks(G.nH, batch, B, 0, n)
+            got = {k: _blocks(post[k], batch, B, 0, n) for k in
+                   ("N", "Fx", "Fy", "Fz", "xHI", "T")}
+            for q, o in enumerate(batch):
+                z0, y0, x0 = o
+                S = np.zeros((B, B, B))
+                inside = ((ijk[:, 0] >= x0) & (ijk[:, 0] < x0 + B) & (ijk[:, 1] >= y0) &
+                          (ijk[:, 1] < y0 + B) & (ijk[:, 2] >= z0) & (ijk[:, 2] < z0 + B))
+                for (i, j, k), s in zip(ijk[inside], ndot[inside]):
+                    S[k - z0, j - y0, i - x0] += s / vol
+                if B == 16:
+                    checked_src += int(inside.sum())
+                res = oracle.step_subblock(p, w.dt, 1, Nb[q], [F[q] for F in Fb], xb[q], Tb[q],
+                                           hb[q], S)
+                ref = dict(N=res[0], Fx=res[1], Fy=res[2], Fz=res[3], xHI=res[4], T=res[5])
+                g = {k: v[q] for k, v in got.items()}
+                if np.max(np.abs(ref["N"])) == 0:
+                    assert np.all(g["N"] == 0)
+                    continue
+                e = errors(g, ref)
+                for k in worst:
+                    worst[k] = max(worst[k], e[k])
+                assert_parity(e, what=f"1024^3 block at {o} ({B}^3)")
+            print(f"1024^3: {min(b0 + 256, len(blocks))}/{len(blocks)} blocks of {B}^3 "
+                  f"checked, worst so far {worst}", flush=True)
+    assert checked_src == len(ijk)
+    G.close()
+    torch.cuda.empty_cache()

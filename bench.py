@@ -420,6 +420,41 @@ def sources_leg(G, w, nH_dev, n: int = 1_000_000, reps: int = 3):
     return {"particles": n, "emitting": m, "ms": dt * 1e3}
 
 
+def stream_ceiling(dev, n: int = 1 << 30, reps: int = 10):
+    """GB/s of the step's stream mix (7 float arrays of n read, 6 written)
+    and of a 1-read/1-write copy, on plain grid-stride kernels, for a few
+    grid sizes; the step kernel's traffic is compared with the best."""
+    import torch
+
+    from paper_1004_2503_amd import rt
+
+    arr = [torch.zeros(n, dtype=torch.float32, device=dev) for _ in range(13)]
+    rows = []
+    for blocks in (4096, 16384, 65536):
+        for name, nin, nout in (("7 read + 6 write (the step's mix)", 7, 6),
+                                ("7 read + 1 write", 7, 1)):
+            rc, ms = rt.rt_stream_probe(arr[:nin], arr[7:7 + nout], blocks, reps)
+            rt.check(rc, "rt_stream_probe")
+            gbs = (nin + nout) * 4 * n / (ms * 1e-3) / 1e9
+            rows.append({"mix": name, "blocks": blocks, "ms": ms, "GBs": gbs})
+            print(f"# {name}, {blocks} blocks: {ms:.3f} ms, {gbs:.1f} GB/s", file=sys.stderr,
+                  flush=True)
+    # a device copy of 4 GiB (torch's copy_) for reference
+    src, dst = arr[0], arr[7]
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / reps * 1e3
+    rows.append({"mix": "device copy (torch copy_)", "blocks": None, "ms": ms,
+                 "GBs": 8 * n / (ms * 1e-3) / 1e9})
+    best = max(r["GBs"] for r in rows if r["mix"].startswith("7 read + 6"))
+    return {"stream_ceiling": rows, "best_step_mix_GBs": best, "n_floats_per_array": n,
+            "reps": reps}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -440,6 +475,10 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="instead of the step, time a plain device copy of MIB MiB "
                          "(the reference for the HBM byte counters)")
+    ap.add_argument("--stream-ceiling", action="store_true",
+                    help="instead of the step, measure the bandwidth the step's stream mix "
+                         "can reach: 7 arrays of 1024^3 floats read and 6 written by a "
+                         "plain grid-stride kernel (rt_stream_probe), and plain copies")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-baseline-configs", action="store_true",
                     help="instead of the step, time the FP64 oracle on the 32^3, 128^3 and "
@@ -488,6 +527,9 @@ def main():
         dtc = (time.perf_counter() - t0) / args.steps
         print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n,
                           "ms": dtc * 1e3, "GBs": 8 * n / dtc / 1e9}), flush=True)
+        return
+    if args.stream_ceiling:
+        print(json.dumps(stream_ceiling(dev)), flush=True)
         return
     w = W.workload(args.workload)
     prec = rt.PREC_MIXED if args.prec == "mixed" else rt.PREC_FP32

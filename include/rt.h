@@ -402,6 +402,18 @@ int rt_mlp_grad_noalloc(int32_t grad_blocks, const float *theta, const float *X,
                         const float *Y, int64_t B, float *grad, double *loss_dev,
                         void *hip_stream);
 
+/* ---- measurement utility (not part of the method) --------------------- */
+
+/* The HBM bandwidth the step's stream mix can reach: a plain grid-stride
+ * kernel reads nin (1..16) device arrays in[k] of n floats and writes nout
+ * (1..16) arrays out[k] (non-temporal stores, each output depending on every
+ * input), `blocks` blocks of 256 threads; one warm-up launch, then reps
+ * launches timed with HIP events on hip_stream.  *ms receives the average
+ * launch time; (nin + nout) * 4 * n bytes move per launch.  Arrays are
+ * caller-owned and must not alias.  Waits for the stream. */
+int rt_stream_probe(const float *const *in, int32_t nin, float *const *out, int32_t nout,
+                    int64_t n, int32_t blocks, int32_t reps, double *ms, void *hip_stream);
+
 /* Static string naming a return code. */
 const char *rt_strerror(int code);
 

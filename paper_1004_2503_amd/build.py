@@ -12,7 +12,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "librt_m1.so")
 
-SOURCES = ["rt_api.hip", "rt_step.hip", "mlp.hip", "diag.hip", "sources.hip"]
+SOURCES = ["rt_api.hip", "rt_step.hip", "mlp.hip", "diag.hip", "sources.hip", "probe.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

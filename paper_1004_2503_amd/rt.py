@@ -480,7 +480,24 @@ def equilibrium_xhi(params: rt_params, model: int, gamma0: float, n_star: float,
     return out
 
 
-EXPORTS += ["rt_gamma_plateau"]
+EXPORTS += ["rt_gamma_plateau", "rt_stream_probe"]
+
+
+def rt_stream_probe(ins, outs, blocks: int, reps: int, stream: int | None = None):
+    """ins, outs: lists of equal-size float32 device tensors.  Returns
+    (code, average ms per launch)."""
+    L = lib()
+    vp = ctypes.c_void_p
+    L.rt_stream_probe.argtypes = [ctypes.POINTER(vp), ctypes.c_int32, ctypes.POINTER(vp),
+                                  ctypes.c_int32, ctypes.c_int64, ctypes.c_int32,
+                                  ctypes.c_int32, ctypes.POINTER(ctypes.c_double), vp]
+    L.rt_stream_probe.restype = ctypes.c_int
+    a = (vp * len(ins))(*[t.data_ptr() for t in ins])
+    b = (vp * len(outs))(*[t.data_ptr() for t in outs])
+    ms = ctypes.c_double()
+    rc = L.rt_stream_probe(a, len(ins), b, len(outs), int(ins[0].numel()), int(blocks),
+                           int(reps), ctypes.byref(ms), vp(stream or 0))
+    return rc, ms.value
 
 
 def rt_gamma_plateau(ctx, nH_max: float):

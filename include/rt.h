@@ -273,10 +273,12 @@ int rt_reduce(rt_ctx *ctx, rt_reductions *out);
  * e_k <= value, values below e_0 (zero included) in bin 0.  q = xHI, or
  * (c_cms * sigma_n) * N evaluated in FP64 for RT_HQ_GAMMA.
  * counts (host, nbx * nby int64, row ix: counts[ix * nby + iy]) receives
- * the exact cell counts; sum_q (host, nbx doubles) the FP64 sum of q over
- * the cells of each density bin (in a fixed order: the same state gives the
- * same sums bit for bit).  Both are
- * overwritten.  1 <= nbx, nby <= 256, nbx * nby <= RT_HIST_MAX_BINS,
+ * the exact cell counts; sum_q (host, nbx doubles) the sum of q over the
+ * cells of each density bin: xHI (resp. N) is summed exactly in fixed point,
+ * independent of the order of the additions, rounded to FP64 (a few ulp)
+ * and, for RT_HQ_GAMMA, multiplied by c_cms * sigma_n in FP64, so the same
+ * state gives the same sums bit for bit; a negative or non-finite value
+ * makes its bin's sum NaN.  Both are overwritten.  1 <= nbx, nby <= 256, nbx * nby <= RT_HIST_MAX_BINS,
  * lo < hi, |lo|, |hi| <= 300, else RT_E_ARG.  Waits for the stream. */
 int rt_histogram(rt_ctx *ctx, int32_t quantity, int32_t nbx, double lox, double hix,
                  int32_t nby, double loy, double hiy, int64_t *counts, double *sum_q);

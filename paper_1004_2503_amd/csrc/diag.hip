@@ -6,9 +6,9 @@
 // models of the same section (one thread per element, FP64).
 //
 // One streaming pass over nH and the chosen quantity (8 bytes per cell).
-// Each block keeps a private histogram in LDS (integer atomics) and FP64
-// per-density-bin sums (deterministic: see hist_kernel); blocks then add
-// their non-zero count bins to the global result.  Bin decisions are exact:
+// Each block keeps a private histogram in LDS (integer atomics) and exact
+// fixed-point per-density-bin sums (see hist_kernel); blocks then add their
+// non-zero bins to the global result.  Bin decisions are exact:
 // an FP32 logarithm proposes the bin and comparisons against the FP64 edges
 // settle it.
 
@@ -33,30 +33,44 @@ __device__ __forceinline__ int find_bin(double v, float lv, const double *e, int
     return k;
 }
 
-// Sums of q per density bin are made deterministic: every wavefront adds
-// into its own LDS row, and within a wavefront the lanes holding the same
-// bin are summed by a fixed butterfly before one lane adds the result (a
-// loop over the distinct bins present); the block then writes the sum of
-// its rows, in wavefront order, as its partial row, and hist_sum_kernel
-// adds the partial rows in block order.  Counts are integers, added with
-// atomics (exact in any order).
-constexpr int HIST_THREADS = 256, HIST_WAVES = HIST_THREADS / 64;
+// Sums of q per density bin are exact, hence independent of the order of
+// the additions: every value is a float (xHI, or N for the rate, whose bin
+// sum is multiplied by c sigma_n at the end), i.e. m 2^(s - 149) with an
+// integer m < 2^24 and 0 <= s <= 253, and it is added as the integer
+// m 2^s, split over two 32-bit-aligned limbs of a fixed-point accumulator
+// (HLIMBS limbs of 64 bits per bin, 32 bits of headroom each: fewer than
+// 2^32 cells cannot overflow one).  Blocks add their LDS limbs to the
+// global ones with integer atomics; hist_sum_kernel propagates the carries
+// and converts.  Negative or non-finite values are counted in a slot of
+// their own and turn the bin's sum into NaN.  Counts are integers, added
+// with atomics (exact in any order).
+constexpr int HIST_THREADS = 256;
+constexpr int HLIMBS = 9;            // limb k holds bits 32k .. 32k + 31 of m 2^s
+constexpr int HSLOT = HLIMBS + 1;    // + the count of values without an exact sum
 
-__device__ __forceinline__ void wave_bin_add(double *row, int bx, double q, bool active)
+// v as an integer on the fixed-point grid: v = p 2^(32 k - 149) with
+// p < 2^56; p = 0 for +-0.  Returns false for a negative or non-finite v.
+__device__ __forceinline__ bool fixed_point(float v, int &k, unsigned long long &p)
 {
-    const int lane = threadIdx.x & 63;
-    unsigned long long pend = __ballot(active);
-    while (pend) {
-        const int leader = __builtin_ctzll(pend);
-        const int b = __shfl(bx, leader);
-        const bool mine = active && bx == b;
-        const unsigned long long m = __ballot(mine);
-        double v = mine ? q : 0.0;
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-        if (lane == leader) row[b] += v;
-        pend &= ~m;
-    }
+    const uint32_t u = __float_as_uint(v);
+    k = 0;
+    p = 0ull;
+    if (u == 0u || u == 0x80000000u) return true;      // +0, -0
+    if (u >= 0x7f800000u) return false;                 // inf, NaN, negative
+    const uint32_t e = u >> 23, mant = u & 0x7fffffu;
+    const uint32_t m = e ? (mant | 0x800000u) : mant;
+    const uint32_t s = e ? e - 1u : 0u;                 // v = m 2^(s - 149)
+    k = int(s >> 5);
+    p = (unsigned long long)m << (s & 31u);
+    return true;
+}
+
+// Adds p 2^(32 k - 149) (p < 2^59: up to eight values of one limb) to a
+// bin's limbs.
+__device__ __forceinline__ void limb_add(unsigned long long *acc, int k, unsigned long long p)
+{
+    if (p & 0xffffffffull) atomicAdd(&acc[k], p & 0xffffffffull);
+    if (p >> 32) atomicAdd(&acc[k + 1], p >> 32);
 }
 
 __global__ __launch_bounds__(HIST_THREADS) void hist_kernel(const float *__restrict__ nH,
@@ -67,123 +81,135 @@ __global__ __launch_bounds__(HIST_THREADS) void hist_kernel(const float *__restr
                                                             float lox, float inv_wx, float loy,
                                                             float inv_wy, int vec,
                                                             unsigned long long *__restrict__ counts,
-                                                            double *__restrict__ partials)
+                                                            unsigned long long *__restrict__ limbs)
 {
     extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
     double *se = reinterpret_cast<double *>(lds);                 // nbx + nby + 2
-    double *ssum = se + (nbx + nby + 2);                          // HIST_WAVES rows of nbx
-    unsigned *scnt = reinterpret_cast<unsigned *>(ssum + HIST_WAVES * nbx);   // nbx * nby
+    unsigned long long *sacc =
+        reinterpret_cast<unsigned long long *>(se + (nbx + nby + 2));   // nbx * HSLOT
+    unsigned *scnt = reinterpret_cast<unsigned *>(sacc + size_t(nbx) * HSLOT);   // nbx * nby
     const int nbin = nbx * nby;
-    const int wave = threadIdx.x >> 6;
     for (int i = threadIdx.x; i < nbx + nby + 2; i += HIST_THREADS) se[i] = edges[i];
-    for (int i = threadIdx.x; i < HIST_WAVES * nbx; i += HIST_THREADS) ssum[i] = 0.0;
+    for (int i = threadIdx.x; i < nbx * HSLOT; i += HIST_THREADS) sacc[i] = 0ull;
     for (int i = threadIdx.x; i < nbin; i += HIST_THREADS) scnt[i] = 0u;
     __syncthreads();
-    double *row = ssum + wave * nbx;
     const double *ex = se, *ey = se + nbx + 1;
     const float L10 = 0.301029995664f;   // log10(2)
-    auto bins = [&](float h, float v, int &b, int &bx, double &q) {
-        q = gamma ? csig * double(v) : double(v);
+    auto bins = [&](float h, float v, int &b, int &bx) {
+        const double q = gamma ? csig * double(v) : double(v);
         bx = find_bin(double(h), L10 * flog2(h), ex, nbx, lox, inv_wx);
         const int by = find_bin(q, L10 * flog2(float(q)), ey, nby, loy, inv_wy);
         b = bx * nby + by;
     };
     // Eight consecutive cells per thread and iteration, read as two 16-byte
     // loads of each field (more loads in flight than one float per thread);
-    // neighbouring cells that share a bin are combined first (runs).  The
-    // loops run the same number of times on every lane of a wavefront (the
-    // wavefront-wide sums need all lanes).  64-bit indices: ncell may
-    // approach 2^32.  The rest (and everything, for unaligned fields) goes
-    // cell by cell.
+    // neighbouring cells that share a bin add their count once (runs).
+    // 64-bit indices: ncell may approach 2^32.  The rest (and everything,
+    // for unaligned fields) goes cell by cell.
     const uint64_t stride = uint64_t(gridDim.x) * HIST_THREADS;
     const uint64_t n8 = vec ? ncell / 8 : 0;
     const float4 *h4 = reinterpret_cast<const float4 *>(nH);
     const float4 *q4 = reinterpret_cast<const float4 *>(qsrc);
-    const uint64_t wbase = uint64_t(blockIdx.x) * HIST_THREADS + uint64_t(threadIdx.x & ~63);
-    for (uint64_t i0 = wbase; i0 < n8; i0 += stride) {
-        const uint64_t i = i0 + (threadIdx.x & 63);
-        const bool in = i < n8;
-        float hh[8], vv[8];
-        if (in) {
-            const float4 ha = h4[2 * i], hb = h4[2 * i + 1];
-            const float4 va = q4[2 * i], vb = q4[2 * i + 1];
-            hh[0] = ha.x; hh[1] = ha.y; hh[2] = ha.z; hh[3] = ha.w;
-            hh[4] = hb.x; hh[5] = hb.y; hh[6] = hb.z; hh[7] = hb.w;
-            vv[0] = va.x; vv[1] = va.y; vv[2] = va.z; vv[3] = va.w;
-            vv[4] = vb.x; vv[5] = vb.y; vv[6] = vb.z; vv[7] = vb.w;
-        } else {
-#pragma unroll
-            for (int k = 0; k < 8; ++k) hh[k] = vv[k] = 1.0f;
-        }
+    for (uint64_t i = uint64_t(blockIdx.x) * HIST_THREADS + threadIdx.x; i < n8; i += stride) {
+        const float4 ha = h4[2 * i], hb = h4[2 * i + 1];
+        const float4 va = q4[2 * i], vb = q4[2 * i + 1];
+        const float hh[8] = {ha.x, ha.y, ha.z, ha.w, hb.x, hb.y, hb.z, hb.w};
+        const float vv[8] = {va.x, va.y, va.z, va.w, vb.x, vb.y, vb.z, vb.w};
         int b[8], bx[8];
-        double q[8];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) bins(hh[k], vv[k], b[k], bx[k], q[k]);
-        if (in) {
-            unsigned run = 1;
-#pragma unroll
-            for (int k = 1; k < 8; ++k) {
-                if (b[k] == b[k - 1]) {
-                    ++run;
-                } else {
-                    atomicAdd(&scnt[b[k - 1]], run);
-                    run = 1;
-                }
-            }
-            atomicAdd(&scnt[b[7]], run);
-        }
-        // density-bin sums: runs of equal density bins within the thread,
-        // each closed run added to the wavefront's row
-        double qs = q[0];
+        for (int k = 0; k < 8; ++k) bins(hh[k], vv[k], b[k], bx[k]);
+        unsigned run = 1;
 #pragma unroll
         for (int k = 1; k < 8; ++k) {
-            const bool close = bx[k] != bx[k - 1];
-            wave_bin_add(row, bx[k - 1], qs, in && close);
-            qs = close ? q[k] : qs + q[k];
+            if (b[k] == b[k - 1]) {
+                ++run;
+            } else {
+                atomicAdd(&scnt[b[k - 1]], run);
+                run = 1;
+            }
         }
-        wave_bin_add(row, bx[7], qs, in);
+        atomicAdd(&scnt[b[7]], run);
+        // exact sums: neighbouring cells of one density bin whose values
+        // fall in the same limb are added in a register first
+        int cb = -1, ck = 0;
+        unsigned long long cp = 0ull;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            int lk;
+            unsigned long long p;
+            if (!fixed_point(vv[k], lk, p)) {
+                atomicAdd(&sacc[bx[k] * HSLOT + HLIMBS], 1ull);
+                continue;
+            }
+            if (bx[k] == cb && lk == ck) {
+                cp += p;
+            } else {
+                if (cb >= 0) limb_add(sacc + cb * HSLOT, ck, cp);
+                cb = bx[k];
+                ck = lk;
+                cp = p;
+            }
+        }
+        if (cb >= 0) limb_add(sacc + cb * HSLOT, ck, cp);
     }
-    const uint64_t rest0 = n8 * 8;
-    for (uint64_t i0 = rest0 + wbase; i0 < ncell; i0 += stride) {
-        const uint64_t i = i0 + (threadIdx.x & 63);
-        const bool in = i < ncell;
-        int b = 0, bx = 0;
-        double q = 0.0;
-        if (in) {
-            bins(nH[i], qsrc[i], b, bx, q);
-            atomicAdd(&scnt[b], 1u);
-        }
-        wave_bin_add(row, bx, q, in);
+    for (uint64_t i = n8 * 8 + uint64_t(blockIdx.x) * HIST_THREADS + threadIdx.x; i < ncell;
+         i += stride) {
+        int b, bx;
+        bins(nH[i], qsrc[i], b, bx);
+        atomicAdd(&scnt[b], 1u);
+        int lk;
+        unsigned long long p;
+        if (fixed_point(qsrc[i], lk, p))
+            limb_add(sacc + bx * HSLOT, lk, p);
+        else
+            atomicAdd(&sacc[bx * HSLOT + HLIMBS], 1ull);
     }
     __syncthreads();
     for (int i = threadIdx.x; i < nbin; i += HIST_THREADS) {
         const unsigned c = scnt[i];
         if (c) atomicAdd(&counts[i], (unsigned long long)c);
     }
-    for (int i = threadIdx.x; i < nbx; i += HIST_THREADS) {
-        double v = 0.0;
-#pragma unroll
-        for (int w = 0; w < HIST_WAVES; ++w) v += ssum[w * nbx + i];
-        partials[size_t(blockIdx.x) * nbx + i] = v;
+    for (int i = threadIdx.x; i < nbx * HSLOT; i += HIST_THREADS) {
+        const unsigned long long v = sacc[i];
+        if (v) atomicAdd(&limbs[i], v);
     }
 }
 
-// sums[i] = the partial rows' bin i added in block order (one thread per bin).
-__global__ __launch_bounds__(256) void hist_sum_kernel(const double *__restrict__ partials,
-                                                       int nblocks, int nbx,
+// sums[i] = scale * (exact sum of bin i): the limbs' carries propagated into
+// 32-bit digits, which are then added from the most significant down (a few
+// ulp of FP64 at most; the same result on every run).
+__global__ __launch_bounds__(256) void hist_sum_kernel(const unsigned long long *__restrict__ limbs,
+                                                       int nbx, double scale,
                                                        double *__restrict__ sums)
 {
     const int i = blockIdx.x * 256 + threadIdx.x;
     if (i >= nbx) return;
+    const unsigned long long *a = limbs + size_t(i) * HSLOT;
+    if (a[HLIMBS]) {
+        sums[i] = __builtin_nan("");
+        return;
+    }
+    uint32_t d[HLIMBS + 1];
+    unsigned long long carry = 0;
+#pragma unroll
+    for (int k = 0; k < HLIMBS; ++k) {
+        const unsigned long long t = a[k] + carry;   // a[k] <= (2^32 - 1)^2: no overflow
+        d[k] = uint32_t(t);
+        carry = t >> 32;
+    }
+    d[HLIMBS] = uint32_t(carry);
     double v = 0.0;
-    for (int b = 0; b < nblocks; ++b) v += partials[size_t(b) * nbx + i];
-    sums[i] = v;
+#pragma unroll
+    for (int k = HLIMBS; k >= 0; --k) v += ldexp(double(d[k]), 32 * k - 149);
+    sums[i] = v * scale;
 }
 
 size_t hist_lds_bytes(int nbx, int nby)
 {
-    return size_t(nbx + nby + 2) * 8 + size_t(HIST_WAVES) * nbx * 8 + size_t(nbx) * nby * 4;
+    return size_t(nbx + nby + 2) * 8 + size_t(nbx) * HSLOT * 8 + size_t(nbx) * nby * 4;
 }
+
+size_t hist_limb_count(int nbx) { return size_t(nbx) * HSLOT; }
 
 int hist_blocks(uint32_t ncell)
 {
@@ -194,17 +220,18 @@ int hist_blocks(uint32_t ncell)
 
 hipError_t launch_hist(const float *nH, const float *q, int gamma, double csig, uint32_t ncell,
                        int nbx, int nby, const double *edges, float lox, float inv_wx,
-                       float loy, float inv_wy, unsigned long long *counts, double *partials,
-                       double *sums, hipStream_t s)
+                       float loy, float inv_wy, unsigned long long *counts,
+                       unsigned long long *limbs, double *sums, hipStream_t s)
 {
     const int vec = (reinterpret_cast<uintptr_t>(nH) % 16 == 0) &&
                     (reinterpret_cast<uintptr_t>(q) % 16 == 0);
     const int blocks = hist_blocks(ncell);
     hipLaunchKernelGGL(hist_kernel, dim3(blocks), dim3(HIST_THREADS), hist_lds_bytes(nbx, nby), s,
                        nH, q, gamma, csig, ncell, nbx, nby, edges, lox, inv_wx, loy, inv_wy, vec,
-                       counts, partials);
+                       counts, limbs);
     hipLaunchKernelGGL(hist_sum_kernel, dim3((nbx + 255) / 256), dim3(256), 0, s,
-                       static_cast<const double *>(partials), blocks, nbx, sums);
+                       static_cast<const unsigned long long *>(limbs), nbx, gamma ? csig : 1.0,
+                       sums);
     return hipGetLastError();
 }
 

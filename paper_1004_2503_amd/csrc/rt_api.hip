@@ -90,7 +90,7 @@ struct rt_ctx {
     float *d_sink = nullptr;
     unsigned long long *d_hcount = nullptr;  // RT_HIST_MAX_BINS
     double *d_hsum = nullptr;                // 256 + edges 2 * 257
-    double *d_hpart = nullptr;               // histogram partial rows: blocks x 256
+    unsigned long long *d_hlimb = nullptr;   // exact histogram sums: 256 bins of limbs
     double t = 0.0, emitted = 0.0, photons_initial = 0.0, nh_sum = 0.0;
     int64_t steps = 0;
     int64_t hist_host[8] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -162,7 +162,7 @@ static void free_ctx(rt_ctx *c)
     if (c->d_sink) (void)hipFree(c->d_sink);
     if (c->d_hcount) (void)hipFree(c->d_hcount);
     if (c->d_hsum) (void)hipFree(c->d_hsum);
-    if (c->d_hpart) (void)hipFree(c->d_hpart);
+    if (c->d_hlimb) (void)hipFree(c->d_hlimb);
     if (c->d_surr_pk) (void)hipFree(c->d_surr_pk);
     if (c->d_surr_bias) (void)hipFree(c->d_surr_bias);
     for (auto &e : c->ev) {
@@ -297,7 +297,7 @@ extern "C" int rt_init(const rt_params *params, const rt_fields *fields, void *h
         hipMalloc(&c->d_sink, NTHREADS_MAX * sizeof(float)) != hipSuccess ||
         hipMalloc(&c->d_hcount, RT_HIST_MAX_BINS * sizeof(unsigned long long)) != hipSuccess ||
         hipMalloc(&c->d_hsum, HSUM_DOUBLES * sizeof(double)) != hipSuccess ||
-        hipMalloc(&c->d_hpart, size_t(hist_blocks(c->ncell)) * 256 * sizeof(double)) !=
+        hipMalloc(&c->d_hlimb, hist_limb_count(256) * sizeof(unsigned long long)) !=
             hipSuccess) {
         (void)hipGetLastError();
         free_ctx(c);
@@ -849,9 +849,11 @@ extern "C" int rt_histogram(rt_ctx *c, int32_t quantity, int32_t nbx, double lox
                        hipMemcpyHostToDevice, c->stream) != hipSuccess ||
         hipMemsetAsync(c->d_hcount, 0, hc.size() * sizeof(unsigned long long), c->stream) !=
             hipSuccess ||
+        hipMemsetAsync(c->d_hlimb, 0, hist_limb_count(nbx) * sizeof(unsigned long long),
+                       c->stream) != hipSuccess ||
         launch_hist(c->f.nH, q, quantity == RT_HQ_GAMMA, c->p.c_cms * c->p.sigma_n, c->ncell,
                     nbx, nby, d_edges, float(lox), float(1.0 / wx), float(loy),
-                    float(1.0 / wy), c->d_hcount, c->d_hpart, d_sum, c->stream) != hipSuccess ||
+                    float(1.0 / wy), c->d_hcount, c->d_hlimb, d_sum, c->stream) != hipSuccess ||
         hipMemcpyAsync(hc.data(), c->d_hcount, hc.size() * sizeof(unsigned long long),
                        hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
         hipMemcpyAsync(sum_q, d_sum, size_t(nbx) * sizeof(double), hipMemcpyDeviceToHost,

@@ -158,13 +158,16 @@ hipError_t launch_finalize(const double *partials, int nblocks, double *scratch,
                            int mode, double tau_coef, double nh_sum, hipStream_t s,
                            uint64_t *clear = nullptr, int nclear = 0);
 size_t hist_lds_bytes(int nbx, int nby);
-// histogram blocks for ncell cells; each writes a partial row of nbx sums
+// histogram blocks for ncell cells
 constexpr int HIST_MAX_BLOCKS = 2048;
 int hist_blocks(uint32_t ncell);
+// limbs: hist_limb_count(nbx) zeroed 64-bit words (the exact per-density-bin
+// sums); sums: nbx doubles
+size_t hist_limb_count(int nbx);
 hipError_t launch_hist(const float *nH, const float *q, int gamma, double csig, uint32_t ncell,
                        int nbx, int nby, const double *edges, float lox, float inv_wx,
-                       float loy, float inv_wy, unsigned long long *counts, double *partials,
-                       double *sums, hipStream_t s);
+                       float loy, float inv_wy, unsigned long long *counts,
+                       unsigned long long *limbs, double *sums, hipStream_t s);
 // plateau: part holds 2 plateau_blocks(ncell) doubles; out 2 (sum, count)
 int plateau_blocks(uint32_t ncell);
 hipError_t launch_plateau(const float *nH, const float *N, uint32_t ncell, double nh_max,

@@ -244,8 +244,9 @@ def test_equilibrium_curves_of_an_evolved_state(evolved64):
 
 @pytest.mark.parametrize("quantity", [rt.HQ_XHI, rt.HQ_GAMMA])
 def test_histogram_sums_bit_identical_on_rerun(evolved64, quantity):
-    # the per-density-bin FP64 sums are added in a fixed order (no float
-    # atomics): the same state gives the same sums bit for bit
+    # the per-density-bin sums are exact fixed-point sums rounded once:
+    # independent of the order of the additions, so the same state gives the
+    # same sums bit for bit
     G, st = evolved64
     yr = (-7.0, 0.5, 64) if quantity == rt.HQ_XHI else (-16.0, -8.0, 64)
     c1, s1 = G.histogram(quantity, (-6.0, 0.0, 48), yr)
@@ -253,3 +254,26 @@ def test_histogram_sums_bit_identical_on_rerun(evolved64, quantity):
     assert np.array_equal(c1, c2)
     assert np.array_equal(s1.view(np.uint64), s2.view(np.uint64))
     assert np.any(s1 != 0.0)
+
+
+@pytest.mark.parametrize("quantity", [rt.HQ_XHI, rt.HQ_GAMMA])
+def test_histogram_sums_are_the_exact_sums(evolved64, quantity):
+    # against math.fsum (Shewchuk's exactly rounded summation) of the FP32
+    # values per density bin, binned on the FP64 edges: the library sums the
+    # FP32 values exactly and rounds once (a few ulp), the rate's sum then
+    # scaled by c sigma_n in FP64
+    import math
+
+    G, st = evolved64
+    nbx, lox, hix = 48, -6.0, 0.0
+    yr = (-7.0, 0.5, 64) if quantity == rt.HQ_XHI else (-16.0, -8.0, 64)
+    _, sums = G.histogram(quantity, (lox, hix, nbx), yr)
+    nH = st["nH"].reshape(-1).astype(np.float64)
+    v = (st["xHI"] if quantity == rt.HQ_XHI else st["N"]).reshape(-1)
+    edges = np.array([10.0 ** (lox + k * (hix - lox) / nbx) for k in range(nbx + 1)])
+    bx = np.clip(np.searchsorted(edges, nH, side="right") - 1, 0, nbx - 1)
+    scale = G.params.c_cms * G.params.sigma_n if quantity == rt.HQ_GAMMA else 1.0
+    for b in range(nbx):
+        ref = math.fsum(v[bx == b].astype(np.float64).tolist())
+        ref = ref * scale
+        assert abs(sums[b] - ref) <= 4 * np.spacing(abs(ref)), (b, sums[b], ref)

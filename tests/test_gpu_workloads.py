@@ -9,8 +9,7 @@
     independent evolution (reported, loosely bounded).
   * 256^3 with 2048 sources, mixed precision: per-field error after 500
     steps of independent evolution on both sides, within the per-step
-    tolerances (the oracle needs two minutes of host time, so it runs when
-    RT_LONG_TESTS is set).
+    tolerances (about a minute of oracle time on the host's threads).
   * 1024^3 (the benchmark's workload and launch configuration): one step
     checked on sampled 32^3 sub-blocks (random, the eight corners and around
     sources), the oracle stepping each from the library's input state; with

@@ -24,6 +24,7 @@ BC_PERIODIC, BC_OUTFLOW, BC_REFLECT, BC_GIVEN = 0, 1, 2, 3
 CHEM_FULL, CHEM_ISOTHERMAL, CHEM_OFF, CHEM_FROZEN = 0, 1, 2, 3
 SUB_FIXED, SUB_ADAPTIVE = 0, 1
 FLUX_LF, FLUX_HLL = 0, 1
+NTALLY = 5   # absorbed, escaped, floor, sub-cycles, diluted by the expansion
 
 # gray single-group constants of Sec. 2.2 and the physical constants
 SIGMA_N = 2.93e-18
@@ -53,7 +54,8 @@ class Params(ctypes.Structure):
                 ("egamma_eV", ctypes.c_double), ("T_floor", ctypes.c_double),
                 ("sub_eps", ctypes.c_double),
                 ("cr_norm", ctypes.c_double), ("cr_exp", ctypes.c_double),
-                ("ci_norm", ctypes.c_double), ("ci_exp", ctypes.c_double)]
+                ("ci_norm", ctypes.c_double), ("ci_exp", ctypes.c_double),
+                ("hubble", ctypes.c_double)]
 
 
 _lib = None
@@ -111,15 +113,16 @@ def _ptr(a):
 
 def make_params(shape, dx, bc=(0,) * 6, chem=CHEM_FULL, sub=SUB_FIXED,
                 c=C_LIGHT, sigma_n=SIGMA_N, sigma_e=SIGMA_E, egamma_eV=EGAMMA_EV,
-                T_floor=10.0, sub_eps=0.1, clump=None, flux=0) -> Params:
+                T_floor=10.0, sub_eps=0.1, clump=None, flux=0, hubble=0.0) -> Params:
     """``shape`` is (nz, ny, nx), the numpy order of every field.  ``clump``
     is None (no subgrid clumping) or (cr_norm, cr_exp, ci_norm, ci_exp):
-    C_R = max(1, cr_norm nH^cr_exp), C_I = ci_norm nH^ci_exp."""
+    C_R = max(1, cr_norm nH^cr_exp), C_I = ci_norm nH^ci_exp.  ``hubble``:
+    the expansion rate H [1/s] (0: a static medium)."""
     nz, ny, nx = shape
     cl = (0.0, 0.0, 1.0, 0.0) if clump is None else tuple(float(v) for v in clump)
     return Params(nx, ny, nz, (ctypes.c_int32 * 6)(*bc), chem, sub,
                   0 if clump is None else 1, int(flux), dx, c,
-                  sigma_n, sigma_e, egamma_eV, T_floor, sub_eps, *cl)
+                  sigma_n, sigma_e, egamma_eV, T_floor, sub_eps, *cl, float(hubble))
 
 
 # ---------------------------------------------------------------- closure
@@ -193,7 +196,7 @@ class Grid:
         self.T = np.full((nz, ny, nx), 1e4)
         self.nH = np.full((nz, ny, nx), 1e-3)
         self.S = np.zeros((nz, ny, nx))
-        self.tally = np.zeros(4)  # absorbed, escaped, floor, sub-cycles
+        self.tally = np.zeros(NTALLY)  # absorbed, escaped, floor, sub-cycles, diluted
         self.emitted = 0.0
         self.t = 0.0
         self.nsrc_rate = 0.0      # sum of Ndot of the current sources
@@ -257,10 +260,10 @@ class Grid:
 
     def step(self, dt, nsub=1, nsteps=1):
         if self.p.flux == FLUX_HLL:
-            acc = np.zeros(4)
+            acc = np.zeros(NTALLY)
             for _ in range(int(nsteps)):
                 lam = self._lam()
-                tl = np.zeros(4)
+                tl = np.zeros(NTALLY)
                 rc = lib().orc_step_flux(ctypes.byref(self.p), float(dt), int(nsub),
                                          *[_ptr(u) for u in self._U], _ptr(self.xHI),
                                          _ptr(self.T), _ptr(self.nH), _ptr(self.S), _ptr(lam),
@@ -272,7 +275,7 @@ class Grid:
             self.emitted += self.nsrc_rate * dt * nsteps
             self.t += dt * nsteps
             return acc
-        tl = np.zeros(4)
+        tl = np.zeros(NTALLY)
         rc = lib().orc_run(ctypes.byref(self.p), float(dt), int(nsub), int(nsteps),
                            *[_ptr(u) for u in self._U], _ptr(self.xHI),
                            _ptr(self.T), _ptr(self.nH), _ptr(self.S), _ptr(tl))
@@ -304,6 +307,7 @@ class Grid:
             photons_absorbed=float(self.tally[0]),
             photons_escaped=float(self.tally[1]),
             photons_floor=float(self.tally[2]),
+            photons_diluted=float(self.tally[4]),
         )
 
 
@@ -329,7 +333,7 @@ def step_subblock(params: Params, dt, nsub, Npad, Fpad, xHI, T, nH, S=None):
     nH = np.ascontiguousarray(nH, dtype=np.float64)
     S = None if S is None else np.ascontiguousarray(S, dtype=np.float64)
     U = [u.copy() for u in U]
-    tl = np.zeros(4)
+    tl = np.zeros(NTALLY)
     if p.flux == FLUX_HLL:
         from . import hll
         lam = np.ascontiguousarray(hll.eigen_extremes(*U, p.c))

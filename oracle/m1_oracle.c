@@ -359,6 +359,7 @@ static int check_params(const orc_params *p)
     if (p->sub != ORC_SUB_FIXED && p->sub != ORC_SUB_ADAPTIVE) return -1;
     if (!(p->dx > 0.0) || !(p->c > 0.0)) return -1;
     if (p->flux != ORC_FLUX_LF && p->flux != ORC_FLUX_HLL) return -1;
+    if (!(p->hubble >= 0.0) || !isfinite(p->hubble)) return -1;
     return 0;
 }
 
@@ -367,6 +368,20 @@ static int check_params(const orc_params *p)
  * state, the unsplit update
  *     u~ = u - dt/dx * sum_d (G_{d,+1/2} - G_{d,-1/2}) + dt S   (S on N),
  * then Phi per cell.  Returns 0, or -1 on invalid parameters.
+ *
+ * Expansion (p->hubble = H > 0).  The moment equations of Sec. 2.2 carry no
+ * expansion terms, while the runs cover some 800 Myr of cosmic time on
+ * comoving boxes (Sec. 2.1-2.3).  Reading: in proper units, a homogeneous
+ * expansion at rate H dilutes the photon number density and the photon
+ * number flux alike, dN/dt = -3 H N and dF/dt = -3 H F (each photon keeps
+ * its direction and speed, so the reduced flux |F|/(cN), hence the M1
+ * closure, is unchanged; photons redshifting out of the single group are
+ * not followed), and cools the gas adiabatically, dT/dt = -2 H T for a
+ * monatomic ideal gas (full chemistry only: the isothermal mode holds T by
+ * definition, the frozen mode holds the gas).  The gas density is the
+ * snapshot's, as given.  Operator split, with H constant over the step and
+ * the two linear equations solved exactly: after the transport update and
+ * its guards, N, F *= exp(-3 H dt) and T *= exp(-2 H dt), then Phi.
  * --------------------------------------------------------------------- */
 int32_t orc_step(const orc_params *p, double dt, int32_t nsub, double *N,
                  double *Fx, double *Fy, double *Fz, double *xHI, double *T,
@@ -456,6 +471,13 @@ int32_t orc_step_flux(const orc_params *p, double dt, int32_t nsub, double *N,
                     double s = (Fn > 0.0) ? c * Nt / Fn : 0.0;
                     for (int m = 0; m < 3; ++m) Ft[m] *= s;
                 }
+                /* expansion: dilution over the step */
+                if (p->hubble > 0.0) {
+                    const double e3 = exp(-3.0 * p->hubble * dt);
+                    tl[4] += (1.0 - e3) * Nt * vol;
+                    Nt *= e3;
+                    for (int m = 0; m < 3; ++m) Ft[m] *= e3;
+                }
                 Un[0 * npad + q] = Nt;
                 Un[1 * npad + q] = Ft[0];
                 Un[2 * npad + q] = Ft[1];
@@ -472,6 +494,9 @@ int32_t orc_step_flux(const orc_params *p, double dt, int32_t nsub, double *N,
                 size_t q = PIDX(p, i, j, k), u = UIDX(p, i, j, k);
                 double Nn = Un[q], fx = Un[npad + q], fy = Un[2 * npad + q],
                        fz = Un[3 * npad + q];
+                /* expansion: adiabatic cooling of the gas over the step */
+                if (p->hubble > 0.0 && p->chem == ORC_CHEM_FULL)
+                    T[u] *= exp(-2.0 * p->hubble * dt);
                 if (p->chem != ORC_CHEM_OFF) {
                     double abs_ = 0.0;
                     int32_t nc = 0;
@@ -502,7 +527,7 @@ int32_t orc_run(const orc_params *p, double dt, int32_t nsub, int64_t nsteps,
                 double *N, double *Fx, double *Fy, double *Fz, double *xHI,
                 double *T, const double *nH, const double *S, double *tally)
 {
-    double acc[ORC_NTALLY] = {0, 0, 0, 0}, one[ORC_NTALLY];
+    double acc[ORC_NTALLY] = {0, 0, 0, 0, 0}, one[ORC_NTALLY];
     for (int64_t s = 0; s < nsteps; ++s) {
         int32_t rc = orc_step(p, dt, nsub, N, Fx, Fy, Fz, xHI, T, nH, S, one);
         if (rc != 0) return rc;

@@ -86,12 +86,15 @@ typedef struct {
     double T_floor;   /* temperature floor [K]                  */
     double sub_eps;   /* adaptive sub-cycle fraction            */
     double cr_norm, cr_exp, ci_norm, ci_exp; /* clumping laws   */
+    double hubble;    /* expansion rate H = (da/dt)/a [1/s], >= 0 (0: none)
+                       * -- see orc_step_flux                    */
 } orc_params;
 
 /* tallies of one step, in photons (dt and cell volume folded in):
  * [0] absorbed, [1] escaped through outflow faces, [2] added by the N >= 0
- * floor, [3] chemistry sub-cycles executed (summed over cells).         */
-#define ORC_NTALLY 4
+ * floor, [3] chemistry sub-cycles executed (summed over cells), [4] removed
+ * by the expansion's dilution.                                           */
+#define ORC_NTALLY 5
 
 double orc_chi(double f);
 void orc_eddington(double N, double Fx, double Fy, double Fz, double c,

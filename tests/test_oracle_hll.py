@@ -111,7 +111,7 @@ def test_unit_speeds_give_the_lf_flux(orc):
     lam = np.empty(g_h._U[0].shape + (6,))
     lam[..., 0::2] = -1.0
     lam[..., 1::2] = 1.0
-    tl = np.zeros(4)
+    tl = np.zeros(orc.NTALLY)
     P = ctypes.POINTER(ctypes.c_double)
     ptr = [u.ctypes.data_as(P) for u in g_h._U]
     rc = orc.lib().orc_step_flux(ctypes.byref(g_h.p), DT, 2, *ptr, g_h.xHI.ctypes.data_as(P),

@@ -136,7 +136,8 @@ typedef struct {
  * neutral fractions and the volume-averaged photoionisation rate) and the
  * photon budget.  Sums are accumulated in FP64.  Photon counts are absolute
  * numbers of photons: photons_initial + photons_emitted + photons_floor =
- * photons_stored + photons_absorbed + photons_escaped up to rounding. */
+ * photons_stored + photons_absorbed + photons_escaped + photons_diluted up
+ * to rounding. */
 typedef struct {
     double t;                /* simulated time since rt_init [s]            */
     double xhi_vol;          /* <xHI> over cells                            */
@@ -161,6 +162,8 @@ typedef struct {
                                 network's prediction, cumulative */
     int64_t n_fallback_range; /* of n_fallback, the cell-steps rejected
                                  because an input left the training range */
+    double photons_diluted;  /* removed by the expansion's dilution
+                                (rt_set_expansion), cumulative */
 } rt_reductions;
 
 /* Create a context for the grid described by `params` over the caller's
@@ -223,6 +226,22 @@ int rt_sources_from_particles(rt_ctx *ctx, int64_t n, const double *pos,
  * context's partial-sum buffer could not hold the launch (an internal
  * check; nothing is launched then). */
 int rt_step(rt_ctx *ctx, double dt, int32_t nsub);
+
+/* Expansion of the medium for the steps that follow (the runs of Sec. 2.1-
+ * 2.3 span some 800 Myr of cosmic time on comoving boxes; the moment
+ * equations of Sec. 2.2 carry no expansion terms).  hubble = H = (da/dt)/a
+ * [1/s], in the proper frame, held constant over each step: after the
+ * transport update of a step, N and F are multiplied by exp(-3 H dt) (the
+ * photon number density and number flux dilute alike, so the reduced flux
+ * and the M1 closure are unchanged) and, with RT_CHEM_FULL, T by
+ * exp(-2 H dt) (adiabatic cooling of a monatomic gas); then the chemistry.
+ * The photons removed accumulate in rt_reductions.photons_diluted.  nH and
+ * the cell size are not changed: the caller writes each snapshot's density
+ * into the nH field and creates the context with the interval's proper cell
+ * size.  0 (the default) is a static medium, bit-identical to a context that
+ * never called this.
+ * RT_E_ARG unless 0 <= hubble < infinity, RT_E_STATE for a NULL ctx. */
+int rt_set_expansion(rt_ctx *ctx, double hubble);
 
 /* Switch the learned chemistry on (theta != NULL) or off (theta == NULL).
  * Not part of the paper's method.  theta: device, RT_MLP_NPARAM FP32 network

@@ -103,6 +103,8 @@ struct rt_ctx {
     float *d_surr_bias = nullptr;
     float surr_norm[SURR_NNORM] = {};
     float surr_tol = 0.0f;
+    // expansion rate H [1/s] of the steps that follow (0: static)
+    double hubble = 0.0;
 };
 
 static int check_params(const rt_params *p)
@@ -672,6 +674,18 @@ static void fill_args(const rt_ctx *c, double dt, int nsub, StepArgs &a)
     for (int k = 0; k < SURR_NNORM; ++k) a.surr_norm[k] = c->surr_norm[k];
     a.surr_tol = c->surr_tol;
     a.log10_dt = float(log10(dt));
+    a.expand = c->hubble > 0.0 ? 1 : 0;
+    a.dil3 = float(exp(-3.0 * c->hubble * dt));
+    a.dil2 = float(exp(-2.0 * c->hubble * dt));
+    a.one_m_dil3 = float(-expm1(-3.0 * c->hubble * dt));
+}
+
+extern "C" int rt_set_expansion(rt_ctx *c, double hubble)
+{
+    if (!c) return RT_E_STATE;
+    if (!(hubble >= 0.0) || !isfinite(hubble)) return RT_E_ARG;
+    c->hubble = hubble;
+    return RT_OK;
 }
 
 extern "C" int rt_step(rt_ctx *c, double dt, int32_t nsub)
@@ -797,6 +811,7 @@ extern "C" int rt_reduce(rt_ctx *c, rt_reductions *out)
     out->photons_absorbed = acc[ACC_CUM + R_ABS];
     out->photons_escaped = acc[ACC_CUM + R_ESC];
     out->photons_floor = acc[ACC_CUM + R_FLOOR];
+    out->photons_diluted = acc[ACC_CUM + R_DILUTE];
     out->steps = c->steps;
     out->n_nonfinite = int64_t(acc[ACC_CUM + R_NONFINITE]);
     out->n_fp64 = int64_t(acc[ACC_CUM + R_FP64]);

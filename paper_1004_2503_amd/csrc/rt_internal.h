@@ -44,6 +44,7 @@ enum Red : int {
     R_LEARNED,     // learned-chemistry cells that kept the prediction
     R_RANGE,       // learned-chemistry cells rejected for inputs outside the
                    // training range (counted in R_FALLBACK too)
+    R_DILUTE,      // photons removed by the expansion's dilution (dx^3 folded in)
     R_HIST0,       // 8 sub-cycle histogram bins
     NRED = R_HIST0 + 8
 };
@@ -101,6 +102,11 @@ struct StepArgs {
     uint64_t *group_mask;
     ClumpLaw cl;
     ClumpLawD cld;
+    // expansion at rate H over the step: N, F *= dil3 = exp(-3 H dt) after
+    // the transport update, T *= dil2 = exp(-2 H dt) under the full
+    // chemistry; one_m_dil3 = 1 - dil3 (rounded once, for the tally)
+    int expand;
+    float dil3, dil2, one_m_dil3;
     // FP32 constants
     float c, inv_c, half_c, half_c2, k1, dt, csig, T_h, inv15kB, T_floor,
         sub_eps, xhi_thr;

@@ -262,7 +262,8 @@ void m1_step_kernel(StepArgs A)
     uint64_t mword = 0;   // A.defer: this lane's plane (z0 + lane) of deferred cells
     auto plane_step = [&](const int z, const Cell4 &nxt_raw, Cell4 &nx_ld, const Cell4 &hal_raw,
                           Cell4 &hal_ld, const float3 &ch, float3 &ch_ld) {
-        const float c_xh = ch.x, c_T = ch.y, c_nh = ch.z;
+        const float c_xh = ch.x, c_nh = ch.z;
+        float c_T = ch.y;
         // Prefetch (unconditionally, so that every lane of every plane issues
         // the same loads and the compiler's count of outstanding memory
         // operations stays exact: non-halo lanes re-load their own cell, the
@@ -462,6 +463,18 @@ void m1_step_kernel(StepArgs A)
             }
         }
 
+        // expansion over the step (operator split before Phi): dilution of
+        // N and F, adiabatic cooling of the gas under the full chemistry
+        float dil = 0.0f;
+        if (A.expand) {
+            dil = Nt * A.one_m_dil3;
+            Nt *= A.dil3;
+            Fxt *= A.dil3;
+            Fyt *= A.dil3;
+            Fzt *= A.dil3;
+            if (A.chem == RT_CHEM_FULL) c_T *= A.dil2;
+        }
+
         // per-cell operator Phi
         float Nn = Nt, xh = c_xh, Tc = c_T, pabs = 0.0f;
         int ncyc = 0;
@@ -558,6 +571,12 @@ void m1_step_kernel(StepArgs A)
                 for (int off = 32; off > 0; off >>= 1) f += __shfl_xor(f, off);
                 if (lx == 0) s_acc[wave][5] += f;
             }
+            if (A.expand) {
+                double d = active ? double(dil) : 0.0;
+#pragma unroll
+                for (int off = 32; off > 0; off >>= 1) d += __shfl_xor(d, off);
+                if (lx == 0) s_acc[wave][6] += d;
+            }
         }
         if (A.count_hist && A.chem != RT_CHEM_OFF) {
             const int bin = hist_bin(ncyc);
@@ -624,6 +643,7 @@ void m1_step_kernel(StepArgs A)
         sred[wave][R_FALLBACK] = 0.0;   // so are the learned chemistry's cells
         sred[wave][R_LEARNED] = 0.0;
         sred[wave][R_RANGE] = 0.0;
+        sred[wave][R_DILUTE] = s_acc[wave][6] * A.vol;
     }
     __syncthreads();
     if (tid < NRED) {

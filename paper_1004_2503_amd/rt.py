@@ -63,7 +63,8 @@ class rt_reductions(ctypes.Structure):
                 ("steps", ctypes.c_int64), ("n_nonfinite", ctypes.c_int64),
                 ("n_fp64", ctypes.c_int64), ("n_fallback", ctypes.c_int64),
                 ("subcycle_hist", ctypes.c_int64 * 8), ("tau_e", ctypes.c_double),
-                ("n_learned", ctypes.c_int64), ("n_fallback_range", ctypes.c_int64)]
+                ("n_learned", ctypes.c_int64), ("n_fallback_range", ctypes.c_int64),
+                ("photons_diluted", ctypes.c_double)]
 
     def as_dict(self) -> dict:
         d = {k: getattr(self, k) for k, _ in self._fields_ if k != "subcycle_hist"}
@@ -73,7 +74,7 @@ class rt_reductions(ctypes.Structure):
 
 EXPORTS = ["rt_init", "rt_inject_sources", "rt_step", "rt_reduce", "rt_state",
            "rt_current", "rt_profile", "rt_profile_read", "rt_destroy", "rt_strerror",
-           "rt_histogram"]
+           "rt_histogram", "rt_set_expansion"]
 
 HQ_XHI, HQ_GAMMA = 0, 1
 HIST_MAX_BINS = 8192
@@ -101,6 +102,7 @@ def lib():
         L.rt_inject_sources.argtypes = [vp, ctypes.c_int64, P(ctypes.c_int32),
                                         P(ctypes.c_double)]
         L.rt_step.argtypes = [vp, ctypes.c_double, ctypes.c_int32]
+        L.rt_set_expansion.argtypes = [vp, ctypes.c_double]
         L.rt_reduce.argtypes = [vp, P(rt_reductions)]
         L.rt_state.argtypes = [vp, ctypes.c_int32, vp, ctypes.c_int32]
         L.rt_current.argtypes = [vp, P(ctypes.c_int32)]
@@ -144,6 +146,10 @@ def rt_inject_sources(ctx, ijk, ndot) -> int:
 
 def rt_step(ctx, dt: float, nsub: int) -> int:
     return lib().rt_step(ctx, float(dt), int(nsub))
+
+
+def rt_set_expansion(ctx, hubble: float) -> int:
+    return lib().rt_set_expansion(ctx, float(hubble))
 
 
 def rt_reduce(ctx):
@@ -258,6 +264,9 @@ class RTGrid:
     def step(self, dt, nsub=1, nsteps=1):
         for _ in range(int(nsteps)):
             check(rt_step(self.ctx, dt, nsub), "rt_step")
+
+    def set_expansion(self, hubble: float):
+        check(rt_set_expansion(self.ctx, hubble), "rt_set_expansion")
 
     def reduce(self, allow_nonfinite=False) -> dict:
         rc, out = rt_reduce(self.ctx)

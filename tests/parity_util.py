@@ -27,9 +27,9 @@ def gpu_params(shape, dx, bc, chem, prec=rt.PREC_FP32, sub=rt.SUB_FIXED, sub_eps
 
 
 def oracle_grid(state, shape, dx, bc, chem, sub=oracle.SUB_FIXED, sub_eps=0.1, sources=None,
-                clump=None, flux=oracle.FLUX_LF):
+                clump=None, flux=oracle.FLUX_LF, hubble=0.0):
     p = oracle.make_params(shape, dx, bc=bc, chem=chem, sub=sub, sub_eps=sub_eps, clump=clump,
-                           flux=flux)
+                           flux=flux, hubble=hubble)
     g = oracle.Grid(p)
     g.set_state(**{k: np.asarray(state[k], dtype=np.float64) for k in
                    ("N", "Fx", "Fy", "Fz", "xHI", "T", "nH") if k in state})
@@ -59,18 +59,22 @@ def oracle_state(g) -> dict:
 
 
 def one_step_pair(state, shape, dx, dt, nsub, bc, chem, prec=rt.PREC_FP32,
-                  sub=rt.SUB_FIXED, sub_eps=0.1, sources=None, clump=None, flux=rt.FLUX_LF):
-    """Step the library and the oracle once from the same state (``clump``:
-    None or the (cr_norm, cr_exp, ci_norm, ci_exp) laws on both sides; ``flux``
-    the intercell flux, LF or HLL, the same code on both sides).
+                  sub=rt.SUB_FIXED, sub_eps=0.1, sources=None, clump=None, flux=rt.FLUX_LF,
+                  hubble=0.0, nsteps=1):
+    """Step the library and the oracle from the same state (``clump``: None
+    or the (cr_norm, cr_exp, ci_norm, ci_exp) laws on both sides; ``flux``
+    the intercell flux, LF or HLL, the same code on both sides; ``hubble``
+    the expansion rate H; ``nsteps`` steps on both sides).
     Returns (gpu numpy state, oracle numpy state, gpu reductions, oracle grid)."""
     G = rt.RTGrid(gpu_params(shape, dx, bc, chem, prec, sub, sub_eps, clump, flux), state)
     if sources is not None:
         G.inject_sources(*sources)
-    G.step(dt, nsub)
+    if hubble:
+        G.set_expansion(hubble)
+    G.step(dt, nsub, nsteps)
     red = G.reduce(allow_nonfinite=True)
     out = G.state_numpy()
     G.close()
-    g = oracle_grid(state, shape, dx, bc, chem, sub, sub_eps, sources, clump, flux)
-    g.step(dt, nsub)
+    g = oracle_grid(state, shape, dx, bc, chem, sub, sub_eps, sources, clump, flux, hubble)
+    g.step(dt, nsub, nsteps)
     return out, oracle_state(g), red, g

@@ -141,6 +141,7 @@ def test_null_context_is_a_state_error():
     assert L.rt_profile(None, 1) == rt.RT_E_STATE
     assert L.rt_profile_read(None, None, None) == rt.RT_E_STATE
     assert L.rt_destroy(None) == rt.RT_E_STATE
+    assert L.rt_set_expansion(None, 0.0) == rt.RT_E_STATE
 
 
 @pytest.mark.parametrize("kw", [dict(clump=3), dict(clump=1, clump_cr_norm=float("nan")),

@@ -224,7 +224,7 @@ def surrogate_leg(args, G, w, dt, params, src):
         # twice as many cells sampled as kept: every stiff (or FP64) cell
         # among them is kept, the easy ones fill the rest
         per = total // (len(states) * len(dts))
-        Xs, Ys, n_hard = [], [], 0
+        Xs, Us, Ys, n_hard = [], [], [], 0
         for i, st in enumerate(states):
             for j, d in enumerate(dts):
                 c = surrogate.sample_cells(st, 2 * per, seed + 1000 * i + j)
@@ -232,31 +232,32 @@ def surrogate_leg(args, G, w, dt, params, src):
                 # more ionised, brighter), where the run goes next
                 if perturb:
                     c = surrogate.perturb_cells(c, seed + 77 + 1000 * i + j)
-                X, Y, h = surrogate.candidate_pairs(pexact, c, d, per, args.label_cap,
-                                                    fp64_thr=params.xhi_fp64_thr,
-                                                    seed=seed + 1000 * i + j)
+                X, U, Y, h = surrogate.candidate_pairs(pexact, c, d, per, args.label_cap,
+                                                       fp64_thr=params.xhi_fp64_thr,
+                                                       seed=seed + 1000 * i + j)
                 Xs.append(X)
+                Us.append(U)
                 Ys.append(Y)
                 n_hard += h
-        return torch.cat(Xs), torch.cat(Ys), n_hard
+        return torch.cat(Xs), torch.cat(Us), torch.cat(Ys), n_hard
 
-    X, Y, n_hard = make_pairs(args.surrogate_pairs, 0)
-    Xv, Yv, _ = make_pairs(1_000_000, 777_000, perturb=False)   # held out, as sampled
+    X, U, _, n_hard = make_pairs(args.surrogate_pairs, 0)
+    Xv, Uv, Yv, _ = make_pairs(1_000_000, 777_000, perturb=False)   # held out, as sampled
     n_pairs = int(X.shape[0])
     del states
     t_pairs = time.perf_counter() - t0
-    s = surrogate.fit(X, Y, steps=args.surrogate_steps, batch=65536, lr=2e-3,
+    s = surrogate.fit(X, U, steps=args.surrogate_steps, batch=65536, lr=2e-3,
                       grad_blocks=512, log_every=max(args.surrogate_steps // 6, 1),
                       verbose=False)
     t_train = time.perf_counter() - t0 - t_pairs
-    del X, Y
+    del X, U
     P = surrogate.predict(s, Xv)
     dxv = (10 ** P[:, 0] - 10 ** Yv[:, 0]).abs()
     held = {"pairs": int(Xv.shape[0]), "mean_abs_dxHI": float(dxv.mean()),
             "p99_abs_dxHI": float(torch.quantile(dxv[:200_000].float(), 0.99)),
-            "loss_untrained": surrogate.mse(surrogate.untrained(s), Xv, Yv),
-            "loss_trained": surrogate.mse(s, Xv, Yv)}
-    del Xv, Yv, P, dxv
+            "loss_untrained": surrogate.mse(surrogate.untrained(s), Xv, Uv),
+            "loss_trained": surrogate.mse(s, Xv, Uv)}
+    del Xv, Uv, Yv, P, dxv
 
     # the adaptive context starts from a copy of the same state
     snap = {k: v.clone() for k, v in G.tensors().items()}

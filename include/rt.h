@@ -402,6 +402,72 @@ int rt_mlp_adam(rt_mlp *m, float *theta, float *mom1, float *mom2, const float *
 
 int rt_mlp_destroy(rt_mlp *m);
 
+/* Training pairs for the surrogate, on `hip_stream`: for n independent cells
+ * (device arrays of n floats nH, N, xHI, T, dt; not modified) the features
+ * X (device, n x 5: log10 of nH, max(xHI, 1e-30), T, max(N, 1e-30), dt) and,
+ * with the exact operator Phi applied to a copy of each cell exactly as
+ * rt_chem_apply applies it (the chemistry fields of params, nsub as there),
+ * the targets U (device, n x 2: u = asinh(d / 1e-3) of the changes
+ * d = log10(xHI'/xHI), log10(T'/T), xHI floored likewise), the end values
+ * Yend (device, n x 2: log10 xHI', log10 T') and the sub-cycles each cell
+ * took (ncycles, device int32[n]).  Logarithms and the encoding in FP64.
+ * Any of X, U, Yend, ncycles may be NULL (not all); with U, Yend and ncycles
+ * NULL the chemistry is skipped.  RT_E_ARG as rt_chem_apply.  Asynchronous. */
+int rt_mlp_pairs(const rt_params *params, int64_t n, const float *nH, const float *N,
+                 const float *xHI, const float *T, const float *dt, int32_t nsub, float *X,
+                 float *U, float *Yend, int32_t *ncycles, void *hip_stream);
+
+/* Column standardisation of A (device, n x d FP32, 1 <= d <= 8): stats
+ * (device, 4 d doubles) receives the column means, standard deviations
+ * (sqrt of the sum of squared deviations / (n - 1), at least 1e-6; 1 for
+ * n = 1), minima and maxima, all summed in FP64 in a fixed order; out
+ * (device, n x d, may be A) receives (A - mean) / sd.  Uses the workspace's
+ * partial-sum buffers; asynchronous on its stream. */
+int rt_mlp_standardize(rt_mlp *m, const float *A, int64_t n, int32_t d, float *out,
+                       double *stats);
+
+/* Options of rt_mlp_train. */
+typedef struct {
+    int64_t batch;       /* samples per step, >= 1                            */
+    int64_t total_steps; /* length of the learning-rate schedule, >= 1         */
+    double lr;           /* peak learning rate, > 0                            */
+    double warmup;       /* fraction of total_steps with a linear rise, [0, 1) */
+    double lr_floor;     /* added to the cosine decay, >= 0                    */
+    double clip;         /* global gradient-norm bound; <= 0: no clipping      */
+    double beta1, beta2, eps; /* Adam                                          */
+    uint64_t seed;       /* batch sampling                                     */
+} rt_mlp_train_opts;
+
+/* Steps step0 + 1 .. step0 + nsteps (step0 + nsteps <= total_steps) of
+ * minibatch training of the network on the standardised pairs X (device,
+ * n x 5) -> Y (device, n x 2), 1 <= n < 2^31: each step draws its batch on
+ * the device (sample i is row floor(h n / 2^32), h the upper 32 bits of
+ * SplitMix64 (Steele, Lea & Flood 2014) at k + i, k = SplitMix64(seed XOR
+ * (step * 0xD1B54A32D192ED03)); rows may repeat), takes the gradient of
+ * rt_mlp_grad on it, rescales the gradient to global norm clip when above
+ * it (norm summed in FP64, fixed order), and makes the Adam step of
+ * rt_mlp_adam with the learning rate lr s / n_w over the first
+ * n_w = max(1, floor(warmup total_steps)) steps s and lr (1 + cos(pi (s -
+ * n_w) / max(total_steps - n_w, 1))) / 2 + lr_floor after them.  theta,
+ * mom1, mom2 as rt_mlp_adam (mom1, mom2 zero before the first step);
+ * loss_dev (device double, may be NULL) receives the last step's batch
+ * loss.  A run split into several calls equals one call.  Asynchronous. */
+int rt_mlp_train(rt_mlp *m, float *theta, float *mom1, float *mom2, const float *X,
+                 const float *Y, int64_t n, const rt_mlp_train_opts *opts, int64_t step0,
+                 int64_t nsteps, double *loss_dev);
+
+/* The trained network on raw features X (device, n x 5, as rt_mlp_pairs
+ * writes them): standardised with norm (host, 14 floats: mu_in[5] sd_in[5]
+ * mu_out[2] sd_out[2], sd > 0), evaluated, destandardised to u and decoded
+ * to the end values Y (device, n x 2, may be NULL): log10 xHI' = X[1] +
+ * 1e-3 sinh(u0), log10 T' = X[2] + 1e-3 sinh(u1).  With targets U (device,
+ * n x 2, encoded as rt_mlp_pairs writes them) loss_dev (device double)
+ * receives the mean over samples and both outputs of the squared
+ * standardised error (the training loss); loss_dev NULL skips it.
+ * Asynchronous. */
+int rt_mlp_predict(rt_mlp *m, const float *theta, const float *norm, const float *X, int64_t n,
+                   float *Y, const float *U, double *loss_dev);
+
 /* rt_mlp_grad without a workspace object, for callers that cannot allocate
  * device memory: code under HIP graph capture, tight training loops,
  * harnesses that forbid allocation.  It allocates nothing: the packed

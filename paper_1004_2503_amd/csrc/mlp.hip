@@ -9,6 +9,7 @@
 // on the FP32 master.
 #include <math.h>
 
+#include <algorithm>
 #include <mutex>
 #include <new>
 
@@ -47,6 +48,29 @@ __global__ __launch_bounds__(256) void mlp_pack_kernel(const float *__restrict__
     }
     pk[e] = (__bf16)v;
 }
+
+// Batch sampling on the device: sample i of a step draws row
+// floor(h / 2^32 * n) of the n training pairs, h the upper 32 bits of
+// SplitMix64 (Steele, Lea & Flood 2014) at key + i; the step's key is
+// SplitMix64 of seed XOR (step * 0xD1B54A32D192ED03).  n < 2^31.
+__host__ __device__ __forceinline__ uint64_t splitmix64(uint64_t z)
+{
+    z += 0x9e3779b97f4a7c15ull;
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+__device__ __forceinline__ int64_t sample_row(uint64_t key, int64_t i, int64_t n)
+{
+    return int64_t(((splitmix64(key + uint64_t(i)) >> 32) * uint64_t(n)) >> 32);
+}
+
+struct SampleKey {
+    int on;          // 0: sample i is row i
+    uint64_t key;
+    int64_t n;       // rows to draw from
+};
 
 __device__ __forceinline__ bf16x8 load_features(const float *__restrict__ X, int64_t smp,
                                                 bool valid, int half)
@@ -93,6 +117,7 @@ __global__ __launch_bounds__(64) void mlp_grad_kernel(const bf16x8 *__restrict__
                                                       const float *__restrict__ th,
                                                       const float *__restrict__ X,
                                                       const float *__restrict__ Y, int64_t B,
+                                                      SampleKey sk,
                                                       float *__restrict__ part,
                                                       double *__restrict__ lpart)
 {
@@ -115,15 +140,16 @@ __global__ __launch_bounds__(64) void mlp_grad_kernel(const bf16x8 *__restrict__
     for (int64_t c = blockIdx.x; c < nchunk; c += gridDim.x) {
         const int64_t smp = c * 32 + col;
         const bool valid = smp < B;
-        const bf16x8 xb = load_features(X, smp, valid, half);
+        const int64_t row = sk.on ? sample_row(sk.key, smp, sk.n) : smp;
+        const bf16x8 xb = load_features(X, row, valid, half);
         MlpFwd st;
         float y0, y1;
         mlp_forward32<true>(pk, MlpBias{th + OFF_B1, th + OFF_B2, th + OFF_B3, th + OFF_B4}, xb,
                             st, y0, y1);
         float d0 = 0.0f, d1 = 0.0f;
         if (valid && half == 0) {
-            d0 = y0 - Y[smp * 2];
-            d1 = y1 - Y[smp * 2 + 1];
+            d0 = y0 - Y[row * 2];
+            d1 = y1 - Y[row * 2 + 1];
             lsum += double(d0) * d0 + double(d1) * d1;
         }
 
@@ -277,9 +303,10 @@ __global__ __launch_bounds__(64) void mlp_grad_kernel(const bf16x8 *__restrict__
 // (One thread per parameter walking every row was latency-bound: 280 us
 // for 1024 rows.)  Block 0 also reduces the loss partials.
 constexpr int RED_WAVES = 16;
+constexpr int RED_BLOCKS = (MLP_NPARAM + 63) / 64;
 __global__ __launch_bounds__(64 * RED_WAVES) void mlp_reduce_kernel(
     const float *__restrict__ part, const double *__restrict__ lpart, int nblk, double invB,
-    float *__restrict__ grad, double *__restrict__ loss)
+    float *__restrict__ grad, double *__restrict__ loss, double *__restrict__ npart)
 {
     __shared__ double s[RED_WAVES][64];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -291,11 +318,22 @@ __global__ __launch_bounds__(64 * RED_WAVES) void mlp_reduce_kernel(
     }
     s[w][lane] = acc;
     __syncthreads();
-    if (w == 0 && j < MLP_NPARAM) {
-        double t = 0.0;
+    if (w == 0) {
+        float g = 0.0f;
+        if (j < MLP_NPARAM) {
+            double t = 0.0;
 #pragma unroll
-        for (int k = 0; k < RED_WAVES; ++k) t += s[k][lane];
-        grad[j] = float(t * invB);
+            for (int k = 0; k < RED_WAVES; ++k) t += s[k][lane];
+            g = float(t * invB);
+            grad[j] = g;
+        }
+        if (npart) {
+            // this block's share of |grad|^2, summed by a fixed butterfly
+            double q = double(g) * double(g);
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) q += __shfl_xor(q, off);
+            if (lane == 0) npart[blockIdx.x] = q;
+        }
     }
     if (blockIdx.x == 0 && loss) {
         __syncthreads();
@@ -314,16 +352,32 @@ __global__ __launch_bounds__(64 * RED_WAVES) void mlp_reduce_kernel(
 }
 
 // Adam (Kingma & Ba 2015) on the FP32 master; c1, c2 are the bias corrections
+// With npart, the gradient is first rescaled to global norm clip when its
+// norm (from the nnp squared-norm partials of the reduction, added in a
+// fixed order) exceeds clip.
 __global__ __launch_bounds__(256) void mlp_adam_kernel(float *__restrict__ th,
                                                        float *__restrict__ m,
                                                        float *__restrict__ v,
                                                        const float *__restrict__ g, float lr,
                                                        float b1, float b2, float omb1,
-                                                       float omb2, float eps, float c1, float c2)
+                                                       float omb2, float eps, float c1, float c2,
+                                                       const double *__restrict__ npart, int nnp,
+                                                       double clip)
 {
+    __shared__ float s_scale;
+    if (npart) {
+        if (threadIdx.x < 64) {
+            double q = 0.0;
+            for (int k = threadIdx.x; k < nnp; k += 64) q += npart[k];
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) q += __shfl_xor(q, off);
+            if (threadIdx.x == 0) s_scale = float(fmin(1.0, clip / (sqrt(q) + 1e-12)));
+        }
+        __syncthreads();
+    }
     const int j = blockIdx.x * 256 + threadIdx.x;
     if (j >= MLP_NPARAM) return;
-    const float gj = g[j];
+    const float gj = npart ? g[j] * s_scale : g[j];
     const float mj = b1 * m[j] + omb1 * gj;
     const float vj = b2 * v[j] + omb2 * gj * gj;
     m[j] = mj;
@@ -332,41 +386,261 @@ __global__ __launch_bounds__(256) void mlp_adam_kernel(float *__restrict__ th,
 }
 
 // ----------------------------------------- exact chemistry on a batch
+// Constants of Phi for a batch of independent cells (rt_chem_apply,
+// rt_mlp_pairs): the step's operator, FP64 below xhi_thr in the mixed form.
+struct PhiK {
+    int chem, mixed, adaptive, nsub;
+    double csig, T_h, inv15kB, T_floor, sub_eps;
+    float xhi_thr;
+    ClumpLaw cl;
+    ClumpLawD cld;
+};
+
+__device__ __forceinline__ int phi_cell(const PhiK &P, float nh, float d, float &N, float &x,
+                                        float &T)
+{
+    if (P.mixed && x < P.xhi_thr) {
+        const ChemK<double> K{double(d), double(d) / P.nsub, P.csig, P.T_h, P.T_floor,
+                              P.sub_eps, P.inv15kB};
+        double Nd = N, xd = x, Td = T, ad = 0.0, cR, cI;
+        clump_f64(P.cld, double(nh), cR, cI);
+        const int nc = chem_cell<double>(P.chem, P.nsub, P.adaptive, K, cR, cI, double(nh), Nd,
+                                         xd, Td, ad);
+        N = float(Nd);
+        x = float(xd);
+        T = float(Td);
+        return nc;
+    }
+    const ChemK<float> K{d,          d / float(P.nsub), float(P.csig),   float(P.T_h),
+                         float(P.T_floor), float(P.sub_eps), float(P.inv15kB)};
+    float af = 0.0f, cR, cI;
+    clump_f32(P.cl, nh, cR, cI);
+    return chem_cell<float>(P.chem, P.nsub, P.adaptive, K, cR, cI, nh, N, x, T, af);
+}
+
 __global__ __launch_bounds__(256) void chem_batch_kernel(int64_t n, const float *__restrict__ nH,
                                                          float *__restrict__ N,
                                                          float *__restrict__ xHI,
                                                          float *__restrict__ T,
-                                                         const float *__restrict__ dt,
-                                                         int chem, int mixed, int adaptive,
-                                                         int nsub, double csig, double T_h,
-                                                         double inv15kB, double T_floor,
-                                                         double sub_eps, float xhi_thr,
-                                                         ClumpLaw cl, ClumpLawD cld,
+                                                         const float *__restrict__ dt, PhiK P,
                                                          int32_t *__restrict__ ncyc)
 {
     const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
     if (i >= n) return;
-    const float d = dt[i];
-    int nc = 0;
-    if (mixed && xHI[i] < xhi_thr) {
-        const ChemK<double> K{double(d), double(d) / nsub, csig, T_h, T_floor, sub_eps, inv15kB};
-        double Nd = N[i], xd = xHI[i], Td = T[i], ad = 0.0, cR, cI;
-        clump_f64(cld, double(nH[i]), cR, cI);
-        nc = chem_cell<double>(chem, nsub, adaptive, K, cR, cI, double(nH[i]), Nd, xd, Td, ad);
-        N[i] = float(Nd);
-        xHI[i] = float(xd);
-        T[i] = float(Td);
-    } else {
-        const ChemK<float> K{d,          d / float(nsub),  float(csig),   float(T_h),
-                             float(T_floor), float(sub_eps), float(inv15kB)};
-        float Nf = N[i], xf = xHI[i], Tf = T[i], af = 0.0f, cR, cI;
-        clump_f32(cl, nH[i], cR, cI);
-        nc = chem_cell<float>(chem, nsub, adaptive, K, cR, cI, nH[i], Nf, xf, Tf, af);
-        N[i] = Nf;
-        xHI[i] = xf;
-        T[i] = Tf;
+    float Nf = N[i], xf = xHI[i], Tf = T[i];
+    const int nc = phi_cell(P, nH[i], dt[i], Nf, xf, Tf);
+    N[i] = Nf;
+    xHI[i] = xf;
+    T[i] = Tf;
+    if (ncyc) ncyc[i] = nc;
+}
+
+// ------------------------------------------------- training pairs
+// Features of a cell: log10 of nH, max(xHI, FLOOR), T, max(N, FLOOR), dt;
+// with the exact operator applied to a copy: the targets u = asinh(d /
+// DSCALE) of the changes d = log10(xHI'/xHI), log10(T'/T) (xHI floored
+// likewise) and the end values log10 xHI', log10 T'.  FP64 logarithms.
+constexpr double MLP_FLOOR = 1e-30;
+constexpr double MLP_DSCALE = 1e-3;
+
+__global__ __launch_bounds__(256) void mlp_pairs_kernel(int64_t n, const float *__restrict__ nH,
+                                                        const float *__restrict__ N,
+                                                        const float *__restrict__ xHI,
+                                                        const float *__restrict__ T,
+                                                        const float *__restrict__ dt, PhiK P,
+                                                        float *__restrict__ X,
+                                                        float *__restrict__ U,
+                                                        float *__restrict__ Yend,
+                                                        int32_t *__restrict__ ncyc)
+{
+    const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (i >= n) return;
+    const float nh = nH[i], n0 = N[i], x0 = xHI[i], t0 = T[i], d = dt[i];
+    const double lx0 = log10(fmax(double(x0), MLP_FLOOR)), lt0 = log10(double(t0));
+    if (X) {
+        X[i * 5 + 0] = float(log10(double(nh)));
+        X[i * 5 + 1] = float(lx0);
+        X[i * 5 + 2] = float(lt0);
+        X[i * 5 + 3] = float(log10(fmax(double(n0), MLP_FLOOR)));
+        X[i * 5 + 4] = float(log10(double(d)));
+    }
+    if (!U && !Yend && !ncyc) return;
+    float n1 = n0, x1 = x0, t1 = t0;
+    const int nc = phi_cell(P, nh, d, n1, x1, t1);
+    const double lx1 = log10(fmax(double(x1), MLP_FLOOR)), lt1 = log10(double(t1));
+    if (U) {
+        U[i * 2 + 0] = float(asinh((lx1 - lx0) / MLP_DSCALE));
+        U[i * 2 + 1] = float(asinh((lt1 - lt0) / MLP_DSCALE));
+    }
+    if (Yend) {
+        Yend[i * 2 + 0] = float(lx1);
+        Yend[i * 2 + 1] = float(lt1);
     }
     if (ncyc) ncyc[i] = nc;
+}
+
+// ------------------------------------------------- standardisation
+// Column moments of an (n, d) FP32 array, d <= MOM_MAXD, in FP64 and in a
+// fixed order: block b sums rows [b n / MOM_BLOCKS, (b+1) n / MOM_BLOCKS)
+// thread by thread (stride 256) and then over its threads by a fixed
+// tree; one block adds the block partials in order.  Pass 0: sums, minima,
+// maxima; pass 1: sums of squared deviations from the mean.
+constexpr int MOM_BLOCKS = 128, MOM_MAXD = 8;
+
+__global__ __launch_bounds__(256) void mlp_moments_kernel(const float *__restrict__ A, int64_t n,
+                                                          int d, const double *__restrict__ stats,
+                                                          double *__restrict__ part)
+{
+    __shared__ double s_a[256];
+    __shared__ float s_lo[256], s_hi[256];
+    const int64_t r0 = int64_t(blockIdx.x) * n / MOM_BLOCKS;
+    const int64_t r1 = int64_t(blockIdx.x + 1) * n / MOM_BLOCKS;
+    for (int k = 0; k < d; ++k) {
+        const double mu = stats ? stats[k] : 0.0;
+        double acc = 0.0;
+        float lo = INFINITY, hi = -INFINITY;
+        for (int64_t r = r0 + threadIdx.x; r < r1; r += 256) {
+            const float v = A[r * d + k];
+            if (stats) {
+                const double e = double(v) - mu;
+                acc += e * e;
+            } else {
+                acc += double(v);
+                lo = fminf(lo, v);
+                hi = fmaxf(hi, v);
+            }
+        }
+        s_a[threadIdx.x] = acc;
+        s_lo[threadIdx.x] = lo;
+        s_hi[threadIdx.x] = hi;
+        __syncthreads();
+        for (int h = 128; h > 0; h >>= 1) {
+            if (threadIdx.x < h) {
+                s_a[threadIdx.x] += s_a[threadIdx.x + h];
+                s_lo[threadIdx.x] = fminf(s_lo[threadIdx.x], s_lo[threadIdx.x + h]);
+                s_hi[threadIdx.x] = fmaxf(s_hi[threadIdx.x], s_hi[threadIdx.x + h]);
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            double *row = part + size_t(blockIdx.x) * 3 * MOM_MAXD;
+            row[k] = s_a[0];
+            row[MOM_MAXD + k] = double(s_lo[0]);
+            row[2 * MOM_MAXD + k] = double(s_hi[0]);
+        }
+        __syncthreads();
+    }
+}
+
+// stats: mean[d], sd[d], min[d], max[d]; pass 0 fills mean, min, max, pass 1
+// sd = sqrt(sum of squares / (n - 1)), at least 1e-6 (1 for n = 1).
+__global__ __launch_bounds__(64) void mlp_moments_final_kernel(const double *__restrict__ part,
+                                                               int64_t n, int d, int pass,
+                                                               double *__restrict__ stats)
+{
+    const int k = threadIdx.x;
+    if (k >= d) return;
+    double acc = 0.0, lo = INFINITY, hi = -INFINITY;
+    for (int b = 0; b < MOM_BLOCKS; ++b) {
+        const double *row = part + size_t(b) * 3 * MOM_MAXD;
+        acc += row[k];
+        lo = fmin(lo, row[MOM_MAXD + k]);
+        hi = fmax(hi, row[2 * MOM_MAXD + k]);
+    }
+    if (pass == 0) {
+        stats[k] = acc / double(n);
+        stats[2 * d + k] = lo;
+        stats[3 * d + k] = hi;
+    } else {
+        stats[d + k] = n > 1 ? fmax(sqrt(acc / double(n - 1)), 1e-6) : 1.0;
+    }
+}
+
+__global__ __launch_bounds__(256) void mlp_standardize_kernel(const float *__restrict__ A,
+                                                              int64_t n, int d,
+                                                              const double *__restrict__ stats,
+                                                              float *__restrict__ out)
+{
+    const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (i >= n * d) return;
+    const int k = int(i % d);
+    out[i] = float((double(A[i]) - stats[k]) / stats[d + k]);
+}
+
+// ------------------------------------------------- prediction
+// Raw features -> standardised (norm: mu_in[5] sd_in[5] mu_out[2] sd_out[2],
+// FP32) -> network -> u = y sd_out + mu_out -> end values log10 xHI' =
+// f1 + DSCALE sinh u0, log10 T' = f2 + DSCALE sinh u1 (Y, optional); with
+// targets U (encoded changes, optional), the block's sum of squared
+// standardised errors (y - (U - mu_out) / sd_out)^2 over both outputs.
+struct PredNorm {
+    float v[14];
+};
+
+__global__ __launch_bounds__(256) void mlp_predict_kernel(const bf16x8 *__restrict__ pk,
+                                                          const float *__restrict__ th,
+                                                          PredNorm nm,
+                                                          const float *__restrict__ X,
+                                                          int64_t B, float *__restrict__ Y,
+                                                          const float *__restrict__ U,
+                                                          double *__restrict__ lpart)
+{
+    __shared__ double s_l[4];
+    const int lane = threadIdx.x & 63, half = lane >> 5, col = lane & 31;
+    const int wave = threadIdx.x >> 6;
+    const int64_t wv = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nw = (int64_t(gridDim.x) * blockDim.x) >> 6;
+    const int64_t nchunk = (B + 31) / 32;
+    double lsum = 0.0;
+    for (int64_t c = wv; c < nchunk; c += nw) {
+        const int64_t smp = c * 32 + col;
+        const bool valid = smp < B;
+        bf16x8 xb;
+        float f1 = 0.0f, f2 = 0.0f;
+#pragma unroll
+        for (int s2 = 0; s2 < 8; ++s2) xb[s2] = (__bf16)0.0f;
+        if (valid && half == 0) {
+#pragma unroll
+            for (int f = 0; f < MLP_NIN; ++f)
+                xb[f] = (__bf16)((X[smp * MLP_NIN + f] - nm.v[f]) / nm.v[5 + f]);
+            f1 = X[smp * MLP_NIN + 1];
+            f2 = X[smp * MLP_NIN + 2];
+        }
+        MlpFwd st;
+        float y0, y1;
+        mlp_forward32<false>(pk, MlpBias{th + OFF_B1, th + OFF_B2, th + OFF_B3, th + OFF_B4}, xb,
+                             st, y0, y1);
+        if (valid && half == 0) {
+            if (Y) {
+                const double u0 = double(y0) * nm.v[12] + nm.v[10];
+                const double u1 = double(y1) * nm.v[13] + nm.v[11];
+                Y[smp * 2] = float(double(f1) + MLP_DSCALE * sinh(u0));
+                Y[smp * 2 + 1] = float(double(f2) + MLP_DSCALE * sinh(u1));
+            }
+            if (U) {
+                const double e0 = double(y0) - (double(U[smp * 2]) - nm.v[10]) / nm.v[12];
+                const double e1 = double(y1) - (double(U[smp * 2 + 1]) - nm.v[11]) / nm.v[13];
+                lsum += e0 * e0 + e1 * e1;
+            }
+        }
+    }
+    if (lpart) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) lsum += __shfl_xor(lsum, off);
+        if (lane == 0) s_l[wave] = lsum;
+        __syncthreads();
+        if (threadIdx.x == 0) lpart[blockIdx.x] = ((s_l[0] + s_l[1]) + s_l[2]) + s_l[3];
+    }
+}
+
+// out = scale * sum of the n partials, in order
+__global__ __launch_bounds__(64) void mlp_sum_kernel(const double *__restrict__ part, int n,
+                                                     double scale, double *__restrict__ out)
+{
+    if (threadIdx.x != 0) return;
+    double t = 0.0;
+    for (int b = 0; b < n; ++b) t += part[b];
+    *out = t * scale;
 }
 
 hipError_t launch_mlp_pack(const float *theta, __bf16 *pk, hipStream_t s)
@@ -384,8 +658,10 @@ struct rt_mlp {
     hipStream_t stream = nullptr;
     int nblk = 0;
     __bf16 *pk = nullptr;
-    float *part = nullptr;
+    float *part = nullptr;     // gradient partials; also the moment and loss partials
     double *lpart = nullptr;
+    double *npart = nullptr;   // squared-norm partials of the reduction
+    float *grad = nullptr;     // rt_mlp_train's gradient
 };
 
 namespace {
@@ -411,10 +687,14 @@ extern "C" int rt_mlp_create(int32_t grad_blocks, void *hip_stream, rt_mlp **out
     m->nblk = grad_blocks;
     if (hipMalloc(&m->pk, size_t(PK_ALL) * 8 * sizeof(__bf16)) != hipSuccess ||
         hipMalloc(&m->part, size_t(grad_blocks) * MLP_NPARAM * sizeof(float)) != hipSuccess ||
-        hipMalloc(&m->lpart, size_t(grad_blocks) * sizeof(double)) != hipSuccess) {
+        hipMalloc(&m->lpart, size_t(grad_blocks) * sizeof(double)) != hipSuccess ||
+        hipMalloc(&m->npart, size_t(RED_BLOCKS) * sizeof(double)) != hipSuccess ||
+        hipMalloc(&m->grad, size_t(MLP_NPARAM) * sizeof(float)) != hipSuccess) {
         (void)hipGetLastError();
         if (m->pk) (void)hipFree(m->pk);
         if (m->part) (void)hipFree(m->part);
+        if (m->lpart) (void)hipFree(m->lpart);
+        if (m->npart) (void)hipFree(m->npart);
         delete m;
         return RT_E_NOMEM;
     }
@@ -429,6 +709,8 @@ extern "C" int rt_mlp_destroy(rt_mlp *m)
     (void)hipFree(m->pk);
     (void)hipFree(m->part);
     (void)hipFree(m->lpart);
+    (void)hipFree(m->npart);
+    (void)hipFree(m->grad);
     delete m;
     return RT_OK;
 }
@@ -454,12 +736,12 @@ extern "C" int rt_mlp_grad(rt_mlp *m, const float *theta, const float *X, const 
     if (B < 1 || !theta || !X || !Y || !grad) return RT_E_ARG;
     if (pack(m, theta) != RT_OK) return RT_E_HIP;
     hipLaunchKernelGGL(mlp_grad_kernel, dim3(m->nblk), dim3(64), 0, m->stream,
-                       reinterpret_cast<const bf16x8 *>(m->pk), theta, X, Y, B, m->part,
-                       m->lpart);
+                       reinterpret_cast<const bf16x8 *>(m->pk), theta, X, Y, B,
+                       SampleKey{0, 0ull, 0}, m->part, m->lpart);
     if (hipGetLastError() != hipSuccess) return RT_E_HIP;
-    hipLaunchKernelGGL(mlp_reduce_kernel, dim3((MLP_NPARAM + 63) / 64), dim3(64 * RED_WAVES),
-                       0, m->stream, m->part, m->lpart, m->nblk, 1.0 / double(B), grad,
-                       loss_dev);
+    hipLaunchKernelGGL(mlp_reduce_kernel, dim3(RED_BLOCKS), dim3(64 * RED_WAVES), 0, m->stream,
+                       m->part, m->lpart, m->nblk, 1.0 / double(B), grad, loss_dev,
+                       static_cast<double *>(nullptr));
     return hipGetLastError() == hipSuccess ? RT_OK : RT_E_HIP;
 }
 
@@ -532,10 +814,12 @@ extern "C" int rt_mlp_grad_noalloc(int32_t grad_blocks, const float *theta, cons
                        pk);
     if (hipGetLastError() != hipSuccess) return RT_E_HIP;
     hipLaunchKernelGGL(mlp_grad_kernel, dim3(grad_blocks), dim3(64), 0, s,
-                       reinterpret_cast<const bf16x8 *>(pk), theta, X, Y, B, part, lpart);
+                       reinterpret_cast<const bf16x8 *>(pk), theta, X, Y, B,
+                       SampleKey{0, 0ull, 0}, part, lpart);
     if (hipGetLastError() != hipSuccess) return RT_E_HIP;
-    hipLaunchKernelGGL(mlp_reduce_kernel, dim3((MLP_NPARAM + 63) / 64), dim3(64 * RED_WAVES), 0,
-                       s, part, lpart, grad_blocks, 1.0 / double(B), grad, loss_dev);
+    hipLaunchKernelGGL(mlp_reduce_kernel, dim3(RED_BLOCKS), dim3(64 * RED_WAVES), 0, s, part,
+                       lpart, grad_blocks, 1.0 / double(B), grad, loss_dev,
+                       static_cast<double *>(nullptr));
     return hipGetLastError() == hipSuccess ? RT_OK : RT_E_HIP;
 }
 
@@ -552,16 +836,16 @@ extern "C" int rt_mlp_adam(rt_mlp *m, float *theta, float *mom1, float *mom2,
     hipLaunchKernelGGL(mlp_adam_kernel, dim3((MLP_NPARAM + 255) / 256), dim3(256), 0,
                        m->stream, theta, mom1, mom2, grad, float(lr), float(beta1),
                        float(beta2), float(1.0 - beta1), float(1.0 - beta2), float(eps),
-                       float(c1), float(c2));
+                       float(c1), float(c2), static_cast<const double *>(nullptr), 0, 0.0);
     return hipGetLastError() == hipSuccess ? RT_OK : RT_E_HIP;
 }
 
-extern "C" int rt_chem_apply(const rt_params *p, int64_t n, const float *nH, float *N,
-                             float *xHI, float *T, const float *dt, int32_t nsub,
-                             int32_t *ncycles, void *hip_stream)
+namespace {
+// the chemistry fields rt_chem_apply and rt_mlp_pairs read
+int check_chem(const rt_params *p, int32_t nsub)
 {
     if (!p) return RT_E_ARG;
-    if (n < 0 || nsub < 1 || nsub > 4096) return RT_E_ARG;
+    if (nsub < 1 || nsub > 4096) return RT_E_ARG;
     if (p->chem < RT_CHEM_FULL || p->chem > RT_CHEM_FROZEN) return RT_E_ARG;
     if (p->prec != RT_PREC_FP32 && p->prec != RT_PREC_MIXED) return RT_E_ARG;
     if (p->sub != RT_SUB_FIXED && p->sub != RT_SUB_ADAPTIVE) return RT_E_ARG;
@@ -570,16 +854,173 @@ extern "C" int rt_chem_apply(const rt_params *p, int64_t n, const float *nH, flo
         !(p->egamma_eV > 0.0) || !(p->T_floor >= 0.0))
         return RT_E_ARG;
     if (check_clump(*p) != RT_OK) return RT_E_ARG;
+    return RT_OK;
+}
+
+PhiK make_phik(const rt_params &p, int32_t nsub)
+{
+    const double eheat = (p.sigma_e * p.egamma_eV / p.sigma_n - 13.6) * EV_;
+    PhiK k;
+    k.chem = p.chem;
+    k.mixed = p.prec == RT_PREC_MIXED ? 1 : 0;
+    k.adaptive = p.sub == RT_SUB_ADAPTIVE ? 1 : 0;
+    k.nsub = nsub;
+    k.csig = p.c_cms * p.sigma_n;
+    k.T_h = eheat / (1.5 * KB_);
+    k.inv15kB = 1.0 / (1.5 * KB_);
+    k.T_floor = p.T_floor;
+    k.sub_eps = p.sub_eps;
+    k.xhi_thr = float(p.xhi_fp64_thr);
+    k.cl = make_clump_law(p);
+    k.cld = make_clump_law_d(p);
+    return k;
+}
+}  // namespace
+
+extern "C" int rt_chem_apply(const rt_params *p, int64_t n, const float *nH, float *N,
+                             float *xHI, float *T, const float *dt, int32_t nsub,
+                             int32_t *ncycles, void *hip_stream)
+{
+    if (check_chem(p, nsub) != RT_OK || n < 0) return RT_E_ARG;
     if (n == 0) return RT_OK;
     if (!nH || !N || !xHI || !T || !dt) return RT_E_ARG;
-    const double eheat = (p->sigma_e * p->egamma_eV / p->sigma_n - 13.6) * EV_;
     const int64_t blocks = (n + 255) / 256;
     if (blocks > 0x7fffffff) return RT_E_ARG;
     hipLaunchKernelGGL(chem_batch_kernel, dim3(unsigned(blocks)), dim3(256), 0,
-                       static_cast<hipStream_t>(hip_stream), n, nH, N, xHI, T, dt, p->chem,
-                       p->prec == RT_PREC_MIXED ? 1 : 0, p->sub == RT_SUB_ADAPTIVE ? 1 : 0,
-                       nsub, p->c_cms * p->sigma_n, eheat / (1.5 * KB_), 1.0 / (1.5 * KB_),
-                       p->T_floor, p->sub_eps, float(p->xhi_fp64_thr), make_clump_law(*p),
-                       make_clump_law_d(*p), ncycles);
+                       static_cast<hipStream_t>(hip_stream), n, nH, N, xHI, T, dt,
+                       make_phik(*p, nsub), ncycles);
+    return hipGetLastError() == hipSuccess ? RT_OK : RT_E_HIP;
+}
+
+extern "C" int rt_mlp_pairs(const rt_params *p, int64_t n, const float *nH, const float *N,
+                            const float *xHI, const float *T, const float *dt, int32_t nsub,
+                            float *X, float *U, float *Yend, int32_t *ncycles, void *hip_stream)
+{
+    if (check_chem(p, nsub) != RT_OK || n < 0) return RT_E_ARG;
+    if (n == 0) return RT_OK;
+    if (!nH || !N || !xHI || !T || !dt || (!X && !U && !Yend && !ncycles)) return RT_E_ARG;
+    const int64_t blocks = (n + 255) / 256;
+    if (blocks > 0x7fffffff || n > (int64_t(1) << 40)) return RT_E_ARG;
+    hipLaunchKernelGGL(mlp_pairs_kernel, dim3(unsigned(blocks)), dim3(256), 0,
+                       static_cast<hipStream_t>(hip_stream), n, nH, N, xHI, T, dt,
+                       make_phik(*p, nsub), X, U, Yend, ncycles);
+    return hipGetLastError() == hipSuccess ? RT_OK : RT_E_HIP;
+}
+
+extern "C" int rt_mlp_standardize(rt_mlp *m, const float *A, int64_t n, int32_t d, float *out,
+                                  double *stats)
+{
+    if (!m) return RT_E_STATE;
+    if (n < 1 || d < 1 || d > MOM_MAXD || !A || !out || !stats) return RT_E_ARG;
+    if (n > (int64_t(1) << 40)) return RT_E_ARG;
+    // the moment partials (MOM_BLOCKS rows of 3 MOM_MAXD doubles) fit in the
+    // gradient partials of one block
+    static_assert(size_t(MOM_BLOCKS) * 3 * MOM_MAXD * sizeof(double) <=
+                      size_t(MLP_NPARAM) * sizeof(float),
+                  "moment partials fit in one gradient partial row");
+    double *part = reinterpret_cast<double *>(m->part);
+    hipStream_t s = m->stream;
+    hipLaunchKernelGGL(mlp_moments_kernel, dim3(MOM_BLOCKS), dim3(256), 0, s, A, n, int(d),
+                       static_cast<const double *>(nullptr), part);
+    hipLaunchKernelGGL(mlp_moments_final_kernel, dim3(1), dim3(64), 0, s,
+                       static_cast<const double *>(part), n, int(d), 0, stats);
+    hipLaunchKernelGGL(mlp_moments_kernel, dim3(MOM_BLOCKS), dim3(256), 0, s, A, n, int(d),
+                       static_cast<const double *>(stats), part);
+    hipLaunchKernelGGL(mlp_moments_final_kernel, dim3(1), dim3(64), 0, s,
+                       static_cast<const double *>(part), n, int(d), 1, stats);
+    const int64_t blocks = (n * d + 255) / 256;
+    if (blocks > 0x7fffffff) return RT_E_ARG;
+    hipLaunchKernelGGL(mlp_standardize_kernel, dim3(unsigned(blocks)), dim3(256), 0, s, A, n,
+                       int(d), static_cast<const double *>(stats), out);
+    return hipGetLastError() == hipSuccess ? RT_OK : RT_E_HIP;
+}
+
+namespace {
+// learning rate of step s (1-based): a linear rise over the first
+// max(1, floor(warmup total)) steps, then a cosine decay to lr_floor
+double lr_at(const rt_mlp_train_opts &o, int64_t s)
+{
+    const int64_t nw = std::max<int64_t>(int64_t(o.warmup * double(o.total_steps)), 1);
+    if (s <= nw) return o.lr * double(s) / double(nw);
+    const double ph = double(s - nw) / double(std::max<int64_t>(o.total_steps - nw, 1));
+    return o.lr * 0.5 * (1.0 + cos(M_PI * ph)) + o.lr_floor;
+}
+}  // namespace
+
+extern "C" int rt_mlp_train(rt_mlp *m, float *theta, float *mom1, float *mom2, const float *X,
+                            const float *Y, int64_t n, const rt_mlp_train_opts *o,
+                            int64_t step0, int64_t nsteps, double *loss_dev)
+{
+    if (!m) return RT_E_STATE;
+    if (!theta || !mom1 || !mom2 || !X || !Y || !o) return RT_E_ARG;
+    if (n < 1 || n >= (int64_t(1) << 31)) return RT_E_ARG;
+    if (o->batch < 1 || o->total_steps < 1 || !(o->lr > 0.0) || !(o->warmup >= 0.0) ||
+        !(o->warmup < 1.0) || !(o->lr_floor >= 0.0) || !isfinite(o->clip) ||
+        !(o->beta1 >= 0.0) || !(o->beta1 < 1.0) || !(o->beta2 >= 0.0) || !(o->beta2 < 1.0) ||
+        !(o->eps >= 0.0))
+        return RT_E_ARG;
+    if (step0 < 0 || nsteps < 0 || step0 + nsteps > o->total_steps) return RT_E_ARG;
+    hipStream_t s = m->stream;
+    const bool clip = o->clip > 0.0;
+    for (int64_t st = step0 + 1; st <= step0 + nsteps; ++st) {
+        const SampleKey sk{1, splitmix64(o->seed ^ (uint64_t(st) * 0xD1B54A32D192ED03ull)), n};
+        if (pack(m, theta) != RT_OK) return RT_E_HIP;
+        hipLaunchKernelGGL(mlp_grad_kernel, dim3(m->nblk), dim3(64), 0, s,
+                           reinterpret_cast<const bf16x8 *>(m->pk), static_cast<const float *>(theta),
+                           X, Y, o->batch, sk, m->part, m->lpart);
+        hipLaunchKernelGGL(mlp_reduce_kernel, dim3(RED_BLOCKS), dim3(64 * RED_WAVES), 0, s,
+                           static_cast<const float *>(m->part),
+                           static_cast<const double *>(m->lpart), m->nblk,
+                           1.0 / double(o->batch), m->grad, loss_dev,
+                           clip ? m->npart : static_cast<double *>(nullptr));
+        const double c1 = 1.0 - pow(o->beta1, double(st));
+        const double c2 = 1.0 - pow(o->beta2, double(st));
+        hipLaunchKernelGGL(mlp_adam_kernel, dim3((MLP_NPARAM + 255) / 256), dim3(256), 0, s,
+                           theta, mom1, mom2, static_cast<const float *>(m->grad),
+                           float(lr_at(*o, st)), float(o->beta1), float(o->beta2),
+                           float(1.0 - o->beta1), float(1.0 - o->beta2), float(o->eps),
+                           float(c1), float(c2),
+                           clip ? static_cast<const double *>(m->npart) : nullptr, RED_BLOCKS,
+                           o->clip);
+        if (hipGetLastError() != hipSuccess) return RT_E_HIP;
+    }
+    return RT_OK;
+}
+
+extern "C" int rt_mlp_predict(rt_mlp *m, const float *theta, const float *norm, const float *X,
+                              int64_t n, float *Y, const float *U, double *loss_dev)
+{
+    if (!m) return RT_E_STATE;
+    if (n < 0 || !theta || !norm || (n > 0 && !X) || (!Y && !loss_dev) ||
+        (loss_dev && !U))
+        return RT_E_ARG;
+    PredNorm nm;
+    for (int k = 0; k < 14; ++k) {
+        nm.v[k] = norm[k];
+        if (!isfinite(nm.v[k])) return RT_E_ARG;
+    }
+    for (int k = 5; k < 10; ++k)
+        if (!(nm.v[k] > 0.0f)) return RT_E_ARG;
+    if (!(nm.v[12] > 0.0f) || !(nm.v[13] > 0.0f)) return RT_E_ARG;
+    if (n == 0) {
+        if (!loss_dev) return RT_OK;
+        hipLaunchKernelGGL(mlp_sum_kernel, dim3(1), dim3(64), 0, m->stream,
+                           static_cast<const double *>(m->lpart), 0, 0.0, loss_dev);
+        return hipGetLastError() == hipSuccess ? RT_OK : RT_E_HIP;
+    }
+    if (pack(m, theta) != RT_OK) return RT_E_HIP;
+    const int64_t nchunk = (n + 31) / 32;
+    // the loss partials (one double per block) live in the gradient partials
+    const int64_t cap = loss_dev ? int64_t(MLP_NPARAM) / 2 : 16384;
+    const int64_t want = (nchunk + 3) / 4;
+    const int64_t blocks = want < cap ? want : cap;
+    double *lp = loss_dev ? reinterpret_cast<double *>(m->part) : nullptr;
+    hipLaunchKernelGGL(mlp_predict_kernel, dim3(unsigned(blocks)), dim3(256), 0, m->stream,
+                       reinterpret_cast<const bf16x8 *>(m->pk), theta, nm, X, n, Y,
+                       loss_dev ? U : nullptr, lp);
+    if (loss_dev)
+        hipLaunchKernelGGL(mlp_sum_kernel, dim3(1), dim3(64), 0, m->stream,
+                           static_cast<const double *>(lp), int(blocks),
+                           1.0 / (2.0 * double(n)), loss_dev);
     return hipGetLastError() == hipSuccess ? RT_OK : RT_E_HIP;
 }

@@ -343,7 +343,16 @@ class RTGrid:
 MLP_NPARAM = 8834
 MLP_NOALLOC_BLOCKS = 256
 EXPORTS += ["rt_chem_apply", "rt_mlp_create", "rt_mlp_forward", "rt_mlp_grad", "rt_mlp_adam",
-            "rt_mlp_destroy", "rt_mlp_grad_noalloc"]
+            "rt_mlp_destroy", "rt_mlp_grad_noalloc", "rt_mlp_pairs", "rt_mlp_standardize",
+            "rt_mlp_train", "rt_mlp_predict"]
+
+
+class rt_mlp_train_opts(ctypes.Structure):
+    _fields_ = [("batch", ctypes.c_int64), ("total_steps", ctypes.c_int64),
+                ("lr", ctypes.c_double), ("warmup", ctypes.c_double),
+                ("lr_floor", ctypes.c_double), ("clip", ctypes.c_double),
+                ("beta1", ctypes.c_double), ("beta2", ctypes.c_double),
+                ("eps", ctypes.c_double), ("seed", ctypes.c_uint64)]
 
 
 def _bind_extra(L):
@@ -359,8 +368,17 @@ def _bind_extra(L):
                               ctypes.c_double, ctypes.c_double, ctypes.c_double]
     L.rt_mlp_destroy.argtypes = [vp]
     L.rt_mlp_grad_noalloc.argtypes = [ctypes.c_int32, vp, vp, vp, ctypes.c_int64, vp, vp, vp]
+    L.rt_mlp_pairs.argtypes = [ctypes.POINTER(rt_params), ctypes.c_int64, vp, vp, vp, vp, vp,
+                               ctypes.c_int32, vp, vp, vp, vp, vp]
+    L.rt_mlp_standardize.argtypes = [vp, vp, ctypes.c_int64, ctypes.c_int32, vp, vp]
+    L.rt_mlp_train.argtypes = [vp, vp, vp, vp, vp, vp, ctypes.c_int64,
+                               ctypes.POINTER(rt_mlp_train_opts), ctypes.c_int64,
+                               ctypes.c_int64, vp]
+    L.rt_mlp_predict.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_float), vp, ctypes.c_int64,
+                                 vp, vp, vp]
     for n in ("rt_chem_apply", "rt_mlp_create", "rt_mlp_forward", "rt_mlp_grad",
-              "rt_mlp_adam", "rt_mlp_destroy", "rt_mlp_grad_noalloc"):
+              "rt_mlp_adam", "rt_mlp_destroy", "rt_mlp_grad_noalloc", "rt_mlp_pairs",
+              "rt_mlp_standardize", "rt_mlp_train", "rt_mlp_predict"):
         getattr(L, n).restype = ctypes.c_int
     L._extra_bound = True
     return L
@@ -413,6 +431,47 @@ def rt_mlp_adam(m, theta, mom1, mom2, grad, step, lr, beta1=0.9, beta2=0.999, ep
 
 def rt_mlp_destroy(m) -> int:
     return _bind_extra(lib()).rt_mlp_destroy(m)
+
+
+def rt_mlp_pairs(params: rt_params, nH, N, xHI, T, dt, nsub: int, X=None, U=None, Yend=None,
+                 ncycles=None, stream: int | None = None) -> int:
+    """Features X (n, 5), encoded targets U (n, 2), end values Yend (n, 2)
+    of n cells: torch float32 device tensors (outputs preallocated or None)."""
+    L = _bind_extra(lib())
+    n = int(nH.numel())
+    for t in (N, xHI, T, dt):
+        if t.numel() != n:
+            return RT_E_ARG
+    for t, w in ((X, 5), (U, 2), (Yend, 2), (ncycles, 1)):
+        if t is not None and t.numel() != n * w:
+            return RT_E_ARG
+    return L.rt_mlp_pairs(ctypes.byref(params), n, _p(nH), _p(N), _p(xHI), _p(T), _p(dt),
+                          int(nsub), _p(X), _p(U), _p(Yend), _p(ncycles),
+                          ctypes.c_void_p(stream or 0))
+
+
+def rt_mlp_standardize(m, A, out, stats) -> int:
+    """A, out: (n, d) float32 device tensors; stats: (4 d,) float64 device."""
+    n, d = (int(A.shape[0]), int(A.shape[1]))
+    if out.shape != A.shape or stats.numel() != 4 * d:
+        return RT_E_ARG
+    return _bind_extra(lib()).rt_mlp_standardize(m, _p(A), n, d, _p(out), _p(stats))
+
+
+def rt_mlp_train(m, theta, mom1, mom2, X, Y, opts: rt_mlp_train_opts, step0: int, nsteps: int,
+                 loss_dev=None) -> int:
+    if X.shape[0] != Y.shape[0]:
+        return RT_E_ARG
+    return _bind_extra(lib()).rt_mlp_train(m, _p(theta), _p(mom1), _p(mom2), _p(X), _p(Y),
+                                           int(X.shape[0]), ctypes.byref(opts), int(step0),
+                                           int(nsteps), _p(loss_dev))
+
+
+def rt_mlp_predict(m, theta, norm, X, Y=None, U=None, loss_dev=None) -> int:
+    """norm: 14 host floats (mu_in, sd_in, mu_out, sd_out)."""
+    nm = (ctypes.c_float * 14)(*[float(v) for v in norm[:14]])
+    return _bind_extra(lib()).rt_mlp_predict(m, _p(theta), nm, _p(X), int(X.shape[0]), _p(Y),
+                                             _p(U), _p(loss_dev))
 
 
 EXPORTS += ["rt_set_surrogate", "rt_sources_from_particles"]

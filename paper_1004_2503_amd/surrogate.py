@@ -1,20 +1,20 @@
 """Training of the learned chemistry surrogate (not part of the paper's
 method; an optional replacement for the exact per-cell operator Phi).
 
-Everything numerical runs in the library: training pairs come from the exact
-operator on the GPU (rt_chem_apply), gradients and Adam steps from the
-matrix-core kernels (rt_mlp_grad, rt_mlp_adam), evaluation from
-rt_mlp_forward.  This module only samples cells, builds the log-space
-features, standardises them and loops.
+Every numerical step runs in the library: the training pairs -- log10
+features, the asinh encoding of the changes and the end values -- from the
+exact operator (rt_mlp_pairs), the standardisation (rt_mlp_standardize),
+minibatch training with batches drawn on the device, gradient-norm clipping,
+the learning-rate schedule and Adam (rt_mlp_train), evaluation, decoding and
+the held-out loss (rt_mlp_predict).  This module samples cells, picks pairs
+by index and passes arguments.
 
-Features (log10, floored at 1e-30 for N and xHI): nH, xHI, T, N, dt.
-The network predicts u = asinh(d / DSCALE) of the changes d = log10(xHI'/xHI)
-and log10(T'/T) over dt.  Most cells move little in one step; a few change
-by decades.  Against end values, or against the plain changes, those few set
+Features: log10 of nH, xHI, T, N (xHI, N floored at 1e-30) and dt.  The
+network predicts u = asinh(d / 1e-3) of the changes d = log10(xHI'/xHI) and
+log10(T'/T) over dt.  Most cells move little in one step; a few change by
+decades.  Against end values, or against the plain changes, those few set
 the standardisation and the quiet majority then carries errors of ~1e-3 in
 xHI; the asinh keeps small changes linear and compresses the large ones.
-fit() and predict() take and return the end values log10 xHI', log10 T';
-the conversion happens inside.
 """
 
 from __future__ import annotations
@@ -26,9 +26,6 @@ from dataclasses import dataclass
 import numpy as np
 
 from . import rt
-
-FLOOR = 1e-30
-DSCALE = 1e-3     # [dex]: changes below it are learnt linearly
 
 
 @dataclass
@@ -47,22 +44,38 @@ class Surrogate:
                                self.in_min, self.in_max]).astype(np.float32)
 
 
-def features(torch, nH, N, xHI, T, dt):
-    return torch.stack([torch.log10(nH), torch.log10(xHI.clamp_min(FLOOR)), torch.log10(T),
-                        torch.log10(N.clamp_min(FLOOR)), torch.log10(dt)], dim=1)
+def _stream(dev):
+    import torch
+
+    return torch.cuda.current_stream(dev).cuda_stream
+
+
+def _out(like, n, w):
+    import torch
+
+    return torch.empty((n, w), dtype=torch.float32, device=like.device)
+
+
+def features(nH, N, xHI, T, dt):
+    """Raw log10 features (n, 5) of cells given as device tensors."""
+    n = nH.numel()
+    X = _out(nH, n, 5)
+    p = rt.make_params((1, 1, 1), 1.0)
+    rt.check(rt.rt_mlp_pairs(p, nH, N, xHI, T, dt, 1, X=X, stream=_stream(nH.device)),
+             "rt_mlp_pairs")
+    return X
 
 
 def exact_pairs(params, nH, N, xHI, T, dt, nsub, ncycles=None):
-    """Apply the exact operator to copies of the given cells (device tensors);
-    returns (X raw features, Y raw targets, N after).  ncycles (device
+    """The exact operator `params` (at most nsub sub-cycles) on copies of the
+    given cells (device tensors, dt per cell): returns (X raw features,
+    U encoded targets, Y end values log10 xHI', log10 T').  ncycles (device
     int32, optional) receives the sub-cycles each cell took."""
-    import torch
-
-    N1, x1, T1 = N.clone(), xHI.clone(), T.clone()
-    rt.check(rt.rt_chem_apply(params, nH, N1, x1, T1, dt, nsub, ncycles), "rt_chem_apply")
-    X = features(torch, nH, N, xHI, T, dt)
-    Y = torch.stack([torch.log10(x1.clamp_min(FLOOR)), torch.log10(T1)], dim=1)
-    return X, Y, N1
+    n = nH.numel()
+    X, U, Y = _out(nH, n, 5), _out(nH, n, 2), _out(nH, n, 2)
+    rt.check(rt.rt_mlp_pairs(params, nH, N, xHI, T, dt, nsub, X=X, U=U, Yend=Y,
+                             ncycles=ncycles, stream=_stream(nH.device)), "rt_mlp_pairs")
+    return X, U, Y
 
 
 def candidate_pairs(params, cells: dict, dt: float, n_keep: int, nsub: int = 64,
@@ -71,13 +84,13 @@ def candidate_pairs(params, cells: dict, dt: float, n_keep: int, nsub: int = 64,
     The exact adaptive operator `params` (at most nsub sub-cycles) runs on
     every sampled cell; the stiff ones (more than one sub-cycle) and those
     below fp64_thr are all kept, the others fill the rest of n_keep at
-    random.  Returns (X, Y, number of stiff-or-FP64 pairs kept)."""
+    random.  Returns (X, U, Y, number of stiff-or-FP64 pairs kept)."""
     import torch
 
     n = cells["N"].numel()
     dev = cells["N"].device
     ncyc = torch.zeros(n, dtype=torch.int32, device=dev)
-    X, Y, _ = exact_pairs(params, cells["nH"], cells["N"], cells["xHI"], cells["T"],
+    X, U, Y = exact_pairs(params, cells["nH"], cells["N"], cells["xHI"], cells["T"],
                           torch.full_like(cells["N"], dt), nsub, ncyc)
     hard = (ncyc > 1) | (cells["xHI"] < fp64_thr)
     idx_hard = torch.nonzero(hard).reshape(-1)[:n_keep]
@@ -87,7 +100,7 @@ def candidate_pairs(params, cells: dict, dt: float, n_keep: int, nsub: int = 64,
     m = max(0, min(n_keep - idx_hard.numel(), idx_easy.numel()))
     pick = idx_easy[torch.randperm(idx_easy.numel(), generator=g, device=dev)[:m]]
     idx = torch.cat([idx_hard, pick])
-    return X[idx], Y[idx], int(idx_hard.numel())
+    return X[idx], U[idx], Y[idx], int(idx_hard.numel())
 
 
 def sample_cells(state: dict, n: int, seed: int, lit_fraction: float = 0.8):
@@ -145,87 +158,74 @@ def _init_params(seed: int) -> np.ndarray:
     return np.concatenate(parts).astype(np.float32)
 
 
-def fit(X, Y, steps: int = 3000, batch: int = 65536, lr: float = 2e-3, seed: int = 0,
+def fit(X, U, steps: int = 3000, batch: int = 65536, lr: float = 2e-3, seed: int = 0,
         grad_blocks: int = 512, log_every: int = 250, verbose: bool = True,
         warmup: float = 0.05, clip: float | None = 1.0) -> Surrogate:
-    """Fit the network to raw features X (n, 5) and end values Y (n, 2) =
-    (log10 xHI', log10 T'), device tensors; it learns encode(X, Y).  Adam
-    with a learning rate that rises linearly over the first
-    `warmup` fraction of the steps and then decays as a cosine; the gradient
-    is rescaled to global norm `clip` when above it (the changes are heavy
-    tailed: a batch of cells ionised within the step can otherwise throw the
-    weights off)."""
+    """Fit the network to raw features X (n, 5) and encoded targets U (n, 2),
+    device tensors from exact_pairs.  Adam with a learning rate that rises
+    linearly over the first `warmup` fraction of the steps and then decays
+    as a cosine; the gradient is rescaled to global norm `clip` when above
+    it (the changes are heavy tailed: a batch of cells ionised within the
+    step can otherwise throw the weights off)."""
     import torch
 
     dev = X.device
-    Y = encode(X, Y)                        # end values -> asinh of changes
-    mu_in, sd_in = X.mean(0), X.std(0).clamp_min(1e-6)
-    mu_out, sd_out = Y.mean(0), Y.std(0).clamp_min(1e-6)
-    Xs = ((X - mu_in) / sd_in).float().contiguous()
-    Ys = ((Y - mu_out) / sd_out).float().contiguous()
-    n = Xs.shape[0]
-    theta = torch.tensor(_init_params(seed), device=dev)
-    m1 = torch.zeros_like(theta)
-    m2 = torch.zeros_like(theta)
-    grad = torch.zeros_like(theta)
-    loss = torch.zeros(1, dtype=torch.float64, device=dev)
-    rc, h = rt.rt_mlp_create(grad_blocks, torch.cuda.current_stream(dev).cuda_stream)
+    n = int(X.shape[0])
+    rc, h = rt.rt_mlp_create(grad_blocks, _stream(dev))
     rt.check(rc, "rt_mlp_create")
-    g = torch.Generator(device=dev)
-    g.manual_seed(seed)
     hist = []
-    t0 = time.time()
     try:
-        for step in range(1, steps + 1):
-            idx = torch.randint(0, n, (min(batch, n),), generator=g, device=dev)
-            xb, yb = Xs[idx].contiguous(), Ys[idx].contiguous()
-            rt.check(rt.rt_mlp_grad(h, theta, xb, yb, grad, loss), "rt_mlp_grad")
-            if clip is not None:
-                gn = torch.linalg.vector_norm(grad)
-                grad.mul_(torch.clamp(clip / (gn + 1e-12), max=1.0))
-            nw = max(int(warmup * steps), 1)
-            if step <= nw:
-                lr_t = lr * step / nw
-            else:
-                lr_t = lr * 0.5 * (1.0 + math.cos(math.pi * (step - nw) / max(steps - nw, 1))) + 1e-5
-            rt.check(rt.rt_mlp_adam(h, theta, m1, m2, grad, step, lr_t), "rt_mlp_adam")
-            if step == 1 or step % log_every == 0 or step == steps:
-                lv = float(loss.item())
-                hist.append((step, lv, time.time() - t0))
-                if verbose:
-                    print(f"  surrogate step {step}/{steps}: loss {lv:.3e} "
-                          f"({time.time() - t0:.1f} s)", flush=True)
+        st_in = torch.empty(20, dtype=torch.float64, device=dev)
+        st_out = torch.empty(8, dtype=torch.float64, device=dev)
+        Xs, Us = torch.empty_like(X), torch.empty_like(U)
+        rt.check(rt.rt_mlp_standardize(h, X.contiguous(), Xs, st_in), "rt_mlp_standardize")
+        rt.check(rt.rt_mlp_standardize(h, U.contiguous(), Us, st_out), "rt_mlp_standardize")
+        theta = torch.tensor(_init_params(seed), device=dev)
+        m1 = torch.zeros_like(theta)
+        m2 = torch.zeros_like(theta)
+        loss = torch.zeros(1, dtype=torch.float64, device=dev)
+        opts = rt.rt_mlp_train_opts(batch=min(batch, n), total_steps=steps, lr=lr,
+                                    warmup=warmup, lr_floor=1e-5,
+                                    clip=0.0 if clip is None else float(clip), beta1=0.9,
+                                    beta2=0.999, eps=1e-8, seed=seed)
+        t0 = time.time()
+        done = 0
+        while done < steps:
+            k = 1 if done == 0 else min(log_every - done % log_every, steps - done)
+            rt.check(rt.rt_mlp_train(h, theta, m1, m2, Xs, Us, opts, done, k, loss),
+                     "rt_mlp_train")
+            done += k
+            lv = float(loss.item())
+            hist.append((done, lv, time.time() - t0))
+            if verbose:
+                print(f"  surrogate step {done}/{steps}: loss {lv:.3e} "
+                      f"({time.time() - t0:.1f} s)", flush=True)
+        si, so = st_in.cpu().numpy(), st_out.cpu().numpy()
     finally:
         rt.rt_mlp_destroy(h)
-    return Surrogate(theta=theta, mu_in=mu_in.cpu().numpy(), sd_in=sd_in.cpu().numpy(),
-                     mu_out=mu_out.cpu().numpy(), sd_out=sd_out.cpu().numpy(),
-                     in_min=X.min(0).values.cpu().numpy(), in_max=X.max(0).values.cpu().numpy(),
-                     history=hist)
+    return Surrogate(theta=theta, mu_in=si[0:5], sd_in=si[5:10], mu_out=so[0:2], sd_out=so[2:4],
+                     in_min=si[10:15], in_max=si[15:20], history=hist)
 
 
-def encode(X, Y):
-    """End values Y = (log10 xHI', log10 T') -> network targets
-    asinh((Y - (log10 xHI, log10 T)) / DSCALE)."""
-    import torch
-
-    return torch.asinh((Y - X[:, 1:3]) / DSCALE)
+def _norm14(s: Surrogate):
+    return np.concatenate([s.mu_in, s.sd_in, s.mu_out, s.sd_out]).astype(np.float32)
 
 
-def decode(X, U):
-    """Network outputs (destandardised) -> end values."""
-    import torch
-
-    return X[:, 1:3].float() + DSCALE * torch.sinh(U)
-
-
-def mse(s: Surrogate, X, Y) -> float:
-    """Mean squared standardised error of the network on (X, end values Y):
+def mse(s: Surrogate, X, U) -> float:
+    """Mean squared standardised error of the network on the pairs (X, U):
     the training loss evaluated on any set of pairs."""
     import torch
 
-    U = _outputs(s, X)
-    so = torch.tensor(s.sd_out, device=X.device)
-    return float((((U - encode(X, Y).float()) / so) ** 2).mean())
+    loss = torch.zeros(1, dtype=torch.float64, device=X.device)
+    rc, h = rt.rt_mlp_create(1, _stream(X.device))
+    rt.check(rc, "rt_mlp_create")
+    try:
+        rt.check(rt.rt_mlp_predict(h, s.theta, _norm14(s), X.contiguous(), U=U.contiguous(),
+                                   loss_dev=loss), "rt_mlp_predict")
+        lv = float(loss.item())
+    finally:
+        rt.rt_mlp_destroy(h)
+    return lv
 
 
 def untrained(s: Surrogate, seed: int = 0) -> Surrogate:
@@ -240,21 +240,12 @@ def untrained(s: Surrogate, seed: int = 0) -> Surrogate:
 def predict(s: Surrogate, X):
     """Raw features -> end values (log10 xHI', log10 T') with the trained
     network (device)."""
-    return decode(X, _outputs(s, X))
-
-
-def _outputs(s: Surrogate, X):
-    """Raw features -> destandardised network outputs (asinh of changes)."""
-    import torch
-
-    Xs = ((X - torch.tensor(s.mu_in, device=X.device)) /
-          torch.tensor(s.sd_in, device=X.device)).float().contiguous()
-    Y = torch.zeros((X.shape[0], 2), device=X.device)
-    rc, h = rt.rt_mlp_create(1, torch.cuda.current_stream(X.device).cuda_stream)
+    Y = _out(X, int(X.shape[0]), 2)
+    rc, h = rt.rt_mlp_create(1, _stream(X.device))
     rt.check(rc, "rt_mlp_create")
     try:
-        rt.check(rt.rt_mlp_forward(h, s.theta, Xs, Y), "rt_mlp_forward")
+        rt.check(rt.rt_mlp_predict(h, s.theta, _norm14(s), X.contiguous(), Y=Y),
+                 "rt_mlp_predict")
     finally:
-        torch.cuda.synchronize()
-        rt.rt_mlp_destroy(h)
-    return Y * torch.tensor(s.sd_out, device=X.device) + torch.tensor(s.mu_out, device=X.device)
+        rt.rt_mlp_destroy(h)      # waits for the stream
+    return Y

@@ -142,6 +142,12 @@ def test_null_context_is_a_state_error():
     assert L.rt_profile_read(None, None, None) == rt.RT_E_STATE
     assert L.rt_destroy(None) == rt.RT_E_STATE
     assert L.rt_set_expansion(None, 0.0) == rt.RT_E_STATE
+    M = rt._bind_extra(L)
+    opts = rt.rt_mlp_train_opts(batch=1, total_steps=1, lr=1e-3, beta1=0.9, beta2=0.999)
+    assert M.rt_mlp_standardize(None, None, 1, 1, None, None) == rt.RT_E_STATE
+    assert M.rt_mlp_train(None, None, None, None, None, None, 1, ctypes.byref(opts), 0, 1,
+                          None) == rt.RT_E_STATE
+    assert M.rt_mlp_predict(None, None, None, None, 0, None, None, None) == rt.RT_E_STATE
 
 
 @pytest.mark.parametrize("kw", [dict(clump=3), dict(clump=1, clump_cr_norm=float("nan")),

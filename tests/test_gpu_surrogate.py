@@ -53,32 +53,33 @@ def exact_params():
 
 
 def pairs(run, n_per_state, seed):
-    Xs, Ys = [], []
+    Xs, Us, Ys = [], [], []
     dts = [run["dt"] * f for f in (0.5, 1.0, 2.0)]
     for i, st in enumerate(run["states"]):
         c = surrogate.sample_cells(st, n_per_state, seed + i)
         dt = torch.full_like(c["N"], dts[i % 3])
-        X, Y, _ = surrogate.exact_pairs(exact_params(), c["nH"], c["N"], c["xHI"], c["T"],
+        X, U, Y = surrogate.exact_pairs(exact_params(), c["nH"], c["N"], c["xHI"], c["T"],
                                         dt, 64)
         Xs.append(X)
+        Us.append(U)
         Ys.append(Y)
-    return torch.cat(Xs), torch.cat(Ys)
+    return torch.cat(Xs), torch.cat(Us), torch.cat(Ys)
 
 
 @pytest.fixture(scope="module")
 def trained(run64):
-    X, Y = pairs(run64, 200_000, 1)
-    s = surrogate.fit(X, Y, steps=4000, batch=32768, lr=1e-3, grad_blocks=256,
+    X, U, Y = pairs(run64, 200_000, 1)
+    s = surrogate.fit(X, U, steps=4000, batch=32768, lr=1e-3, grad_blocks=256,
                       log_every=500, verbose=True)
     return s, X, Y
 
 
 def test_training_lowers_loss_and_meets_accuracy(run64, trained):
     s, X, Y = trained
-    Xv, Yv = pairs(run64, 30_000, 99)            # held out
+    Xv, Uv, Yv = pairs(run64, 30_000, 99)        # held out
     # single-batch losses are noisy (heavy-tailed changes): compare the
     # held-out loss of the untrained and the trained network
-    before, after = surrogate.mse(surrogate.untrained(s), Xv, Yv), surrogate.mse(s, Xv, Yv)
+    before, after = surrogate.mse(surrogate.untrained(s), Xv, Uv), surrogate.mse(s, Xv, Uv)
     print(f"held-out loss {before:.3e} -> {after:.3e}", flush=True)
     assert after < 0.05 * before, (before, after, s.history)
     P = surrogate.predict(s, Xv)
@@ -109,8 +110,7 @@ def test_fused_surrogate_step_matches_batch_network(run64, trained):
     nH = torch.tensor(st["nH"], device=DEV).reshape(-1)
     xHI0 = torch.tensor(st["xHI"], device=DEV).reshape(-1)
     T0 = torch.tensor(st["T"], device=DEV).reshape(-1)
-    X = surrogate.features(torch, nH, Nt.reshape(-1), xHI0, T0,
-                           torch.full_like(nH, dt))
+    X = surrogate.features(nH, Nt.reshape(-1), xHI0, T0, torch.full_like(nH, dt))
     P = surrogate.predict(s, X)
     xs = 10 ** P[:, 0]
     got = out["xHI"].reshape(-1)
@@ -188,7 +188,7 @@ def test_what_the_network_gains(run64, trained):
         ncyc = torch.zeros(n, dtype=torch.int32, device=DEV)
         ref = exact(exact_params(), 64, ncyc)
         one = exact(rt.make_params((1, 1, 1), 1.0, chem=rt.CHEM_FULL, prec=rt.PREC_MIXED), 1)
-        X = surrogate.features(torch, c["nH"], c["N"], c["xHI"], c["T"], dtt)
+        X = surrogate.features(c["nH"], c["N"], c["xHI"], c["T"], dtt)
         net = 10 ** surrogate.predict(s, X)[:, 0]
         for name, sel in (("lit", lit), ("stiff", ncyc >= 8)):
             e1 = float((one[sel] - ref[sel]).abs().mean())

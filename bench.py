@@ -247,7 +247,7 @@ def surrogate_leg(args, G, w, dt, params, src):
     del states
     t_pairs = time.perf_counter() - t0
     s = surrogate.fit(X, U, steps=args.surrogate_steps, batch=65536, lr=2e-3,
-                      grad_blocks=512, log_every=max(args.surrogate_steps // 6, 1),
+                      grad_blocks=256, log_every=max(args.surrogate_steps // 6, 1),
                       verbose=False)
     t_train = time.perf_counter() - t0 - t_pairs
     del X, U

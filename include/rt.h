@@ -382,8 +382,9 @@ int rt_chem_apply(const rt_params *params, int64_t n, const float *nH, float *N,
 typedef struct rt_mlp rt_mlp;
 
 /* Workspace for forward/gradient calls on `hip_stream`; grad_blocks (1 ..
- * 65536) sets how many blocks share a gradient evaluation (each keeps an FP32
- * gradient partial: grad_blocks * 8834 floats). */
+ * 65536) sets how many blocks of four wavefronts share a gradient evaluation
+ * (each keeps an FP32 gradient partial: grad_blocks * 8834 floats; one
+ * block per compute unit runs at a time, so 256 fill an MI355X). */
 int rt_mlp_create(int32_t grad_blocks, void *hip_stream, rt_mlp **out);
 
 /* Y (device, B x 2) = network(X (device, B x 5, standardised inputs)). */

@@ -110,22 +110,79 @@ __global__ __launch_bounds__(256) void mlp_forward_kernel(const bf16x8 *__restri
 }
 
 // ------------------------------------------------ forward + backward
-// One wavefront per block.  Loss L = 1/(2B) sum (y - t)^2; the kernel sums
-// the unscaled gradient of sum (y - t)^2 / 2 per block; the reduction applies
-// 1/B.
-__global__ __launch_bounds__(64) void mlp_grad_kernel(const bf16x8 *__restrict__ pk,
-                                                      const float *__restrict__ th,
-                                                      const float *__restrict__ X,
-                                                      const float *__restrict__ Y, int64_t B,
-                                                      SampleKey sk,
-                                                      float *__restrict__ part,
-                                                      double *__restrict__ lpart)
+// Loss L = 1/(2B) sum (y - t)^2; each block writes the unscaled gradient of
+// sum (y - t)^2 / 2 over its samples as one partial row, the reduction
+// applies 1/B.  A block is GRAD_WAVES wavefronts that share the packed
+// operands and the biases, staged in LDS once; wavefront w of block b takes
+// the 32-sample chunks b GRAD_WAVES + w, + GRAD_WAVES gridDim.x, ...  The
+// gradient of W3 (64 x 64) stays in the matrix cores' accumulator registers
+// over all of a wavefront's chunks; that of W2 (64 x 64) and the small ones
+// (W1, W4, the biases) go to an LDS area of the wavefront (W2 in registers
+// too spilled to scratch: 512 registers per lane are not enough for both
+// with the saved forward state).  Each wavefront transposes through LDS of
+// its own, so no block barrier is needed inside the loop.  At the end the
+// wavefronts' contributions are added in wavefront order (deterministic).
+constexpr int GRAD_WAVES = 4, GRAD_THREADS = 64 * GRAD_WAVES;
+// small gradients per wavefront: W1 (64 x 5), b1, b2, b3, W4 (2 x 64), b4
+constexpr int GS_W1 = 0, GS_B1 = 320, GS_B2 = 384, GS_B3 = 448, GS_W4 = 512, GS_B4 = 640,
+              GS_N = 642, GS_PAD = 644;
+
+struct GradWaveLds {
+    __bf16 Gs[64][32];     // dL/dZ of a layer (neurons x samples), bf16
+    __bf16 Hs[64][32];     // that layer's inputs (neurons x samples), bf16
+    __bf16 G4s[2][32];     // output-layer dL/dY
+    float g[GS_PAD];       // the small gradients
+    float w2[MLP_NH * MLP_NH];   // the gradient of W2
+};
+static_assert(sizeof(GradWaveLds) % 16 == 0, "16-byte aligned per wavefront");
+
+// orders the LDS accesses of one wavefront (its lanes exchange data through
+// its own LDS area; the wavefront's LDS operations complete in order)
+__device__ __forceinline__ void wave_lds_sync()
 {
-    __shared__ float gacc[MLP_NPARAM];
-    __shared__ __attribute__((aligned(16))) __bf16 Gs[64][32];
-    __shared__ __attribute__((aligned(16))) __bf16 Hs[64][32];
-    __shared__ __attribute__((aligned(16))) __bf16 G4s[2][32];
-    const int lane = threadIdx.x, half = lane >> 5, col = lane & 31;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// index of parameter i among the small gradients (not W2, W3)
+__device__ __forceinline__ int small_index(int i)
+{
+    if (i < OFF_B1) return GS_W1 + (i - OFF_W1);
+    if (i < OFF_W2) return GS_B1 + (i - OFF_B1);
+    if (i < OFF_W3) return GS_B2 + (i - OFF_B2);   // i >= OFF_B2 here
+    if (i < OFF_W4) return GS_B3 + (i - OFF_B3);   // i >= OFF_B3 here
+    if (i < OFF_B4) return GS_W4 + (i - OFF_W4);
+    return GS_B4 + (i - OFF_B4);
+}
+
+__global__ __launch_bounds__(GRAD_THREADS) void mlp_grad_kernel(const bf16x8 *__restrict__ pk_g,
+                                                                const float *__restrict__ th,
+                                                                const float *__restrict__ X,
+                                                                const float *__restrict__ Y,
+                                                                int64_t B, SampleKey sk,
+                                                                float *__restrict__ part,
+                                                                double *__restrict__ lpart)
+{
+    __shared__ __attribute__((aligned(16))) bf16x8 s_pk[PK_ALL];
+    __shared__ float s_bias[SURR_NBIAS];   // b1 | b2 | b3 | b4
+    __shared__ __attribute__((aligned(16))) GradWaveLds s_w[GRAD_WAVES];
+    __shared__ double s_loss[GRAD_WAVES];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int half = lane >> 5, col = lane & 31;
+    for (int i = tid; i < PK_ALL; i += GRAD_THREADS) s_pk[i] = pk_g[i];
+    for (int i = tid; i < 64; i += GRAD_THREADS) {
+        s_bias[i] = th[OFF_B1 + i];
+        s_bias[64 + i] = th[OFF_B2 + i];
+        s_bias[128 + i] = th[OFF_B3 + i];
+    }
+    if (tid < 2) s_bias[192 + tid] = th[OFF_B4 + tid];
+    GradWaveLds &W = s_w[wave];
+    for (int i = lane; i < GS_PAD; i += 64) W.g[i] = 0.0f;
+    for (int i = lane; i < MLP_NH * MLP_NH; i += 64) W.w2[i] = 0.0f;
+    __syncthreads();
+    const MlpBias mb{s_bias, s_bias + 64, s_bias + 128, s_bias + 192};
+
     const f32x16 zero = {};
     bf16x8 zero8, ones;
 #pragma unroll
@@ -133,19 +190,25 @@ __global__ __launch_bounds__(64) void mlp_grad_kernel(const bf16x8 *__restrict__
         zero8[s] = (__bf16)0.0f;
         ones[s] = (__bf16)(col == 0 ? 1.0f : 0.0f);
     }
-    for (int i = lane; i < MLP_NPARAM; i += 64) gacc[i] = 0.0f;
+    // dW3 as 2 x 2 tiles of 32 x 32 (mt: output neurons, nt: input
+    // neurons) in the D layout
+    f32x16 acc3[2][2];
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt) acc3[mt][nt] = zero;
     double lsum = 0.0;
     const int64_t nchunk = (B + 31) / 32;
+    const int64_t nwv = int64_t(gridDim.x) * GRAD_WAVES;
 
-    for (int64_t c = blockIdx.x; c < nchunk; c += gridDim.x) {
+    for (int64_t c = int64_t(blockIdx.x) * GRAD_WAVES + wave; c < nchunk; c += nwv) {
         const int64_t smp = c * 32 + col;
         const bool valid = smp < B;
         const int64_t row = sk.on ? sample_row(sk.key, smp, sk.n) : smp;
         const bf16x8 xb = load_features(X, row, valid, half);
         MlpFwd st;
         float y0, y1;
-        mlp_forward32<true>(pk, MlpBias{th + OFF_B1, th + OFF_B2, th + OFF_B3, th + OFF_B4}, xb,
-                            st, y0, y1);
+        mlp_forward32<true>(s_pk, mb, xb, st, y0, y1);
         float d0 = 0.0f, d1 = 0.0f;
         if (valid && half == 0) {
             d0 = y0 - Y[row * 2];
@@ -162,33 +225,34 @@ __global__ __launch_bounds__(64) void mlp_grad_kernel(const bf16x8 *__restrict__
         f32x16 G[2];
 #pragma unroll
         for (int mt = 0; mt < 2; ++mt) {
-            const f32x16 a = mfma32(pk[PK_T4 + mt * 64 + lane], g4, zero);
+            const f32x16 a = mfma32(s_pk[PK_T4 + mt * 64 + lane], g4, zero);
 #pragma unroll
-            for (int r = 0; r < 16; ++r) G[mt][r] = a[r] * silu_grad(st.z[4 + mt][r]);
+            for (int r = 0; r < 16; ++r)
+                G[mt][r] = a[r] * float(st.dz[8 + 2 * mt + (r >> 3)][r & 7]);
         }
-        __syncthreads();
+        wave_lds_sync();   // the previous chunk's reads of this area are done
         if (half == 0) {
-            G4s[0][col] = (__bf16)d0;
-            G4s[1][col] = (__bf16)d1;
+            W.G4s[0][col] = (__bf16)d0;
+            W.G4s[1][col] = (__bf16)d1;
         }
 #pragma unroll
         for (int kc = 0; kc < 4; ++kc)
 #pragma unroll
-            for (int s = 0; s < 8; ++s) Hs[perm_in(kc, half, s)][col] = st.h[8 + kc][s];
-        __syncthreads();
+            for (int s = 0; s < 8; ++s) W.Hs[perm_in(kc, half, s)][col] = st.h[8 + kc][s];
+        wave_lds_sync();
 #pragma unroll
         for (int nt = 0; nt < 2; ++nt) {
             f32x16 a = zero;
 #pragma unroll
             for (int kk = 0; kk < 2; ++kk) {
                 const bf16x8 A =
-                    col < MLP_NOUT ? *(const bf16x8 *)&G4s[col][16 * kk + 8 * half] : zero8;
-                const bf16x8 Bv = *(const bf16x8 *)&Hs[32 * nt + col][16 * kk + 8 * half];
+                    col < MLP_NOUT ? *(const bf16x8 *)&W.G4s[col][16 * kk + 8 * half] : zero8;
+                const bf16x8 Bv = *(const bf16x8 *)&W.Hs[32 * nt + col][16 * kk + 8 * half];
                 a = mfma32(A, Bv, a);
             }
             if (half == 0) {
-                gacc[OFF_W4 + 32 * nt + col] += a[0];
-                gacc[OFF_W4 + MLP_NH + 32 * nt + col] += a[1];
+                W.g[GS_W4 + 32 * nt + col] += a[0];
+                W.g[GS_W4 + MLP_NH + 32 * nt + col] += a[1];
             }
         }
         {
@@ -199,88 +263,113 @@ __global__ __launch_bounds__(64) void mlp_grad_kernel(const bf16x8 *__restrict__
                 s1 += __shfl_xor(s1, off);
             }
             if (lane == 0) {
-                gacc[OFF_B4] += s0;
-                gacc[OFF_B4 + 1] += s1;
+                W.g[GS_B4] += s0;
+                W.g[GS_B4 + 1] += s1;
             }
         }
 
         // ---- hidden layers 3, 2, 1: G holds dL/dZ_L in the D layout
 #pragma unroll
         for (int L = 3; L >= 1; --L) {
-            const int offW = L == 3 ? OFF_W3 : (L == 2 ? OFF_W2 : OFF_W1);
-            const int offB = L == 3 ? OFF_B3 : (L == 2 ? OFF_B2 : OFF_B1);
-            const int nin = L == 1 ? MLP_NIN : MLP_NH;
+            const int gsB = L == 3 ? GS_B3 : (L == 2 ? GS_B2 : GS_B1);
+            // G_L in bf16: the B operand of W_L^T G_L and, transposed
+            // through LDS, the A operand of dW_L = G_L H_{L-1}^T and db_L
+            bf16x8 gb[4];
+#pragma unroll
+            for (int kc = 0; kc < 4; ++kc)
+#pragma unroll
+                for (int s = 0; s < 8; ++s) gb[kc][s] = (__bf16)G[kc >> 1][8 * (kc & 1) + s];
+            wave_lds_sync();
+#pragma unroll
+            for (int kc = 0; kc < 4; ++kc)
+#pragma unroll
+                for (int s = 0; s < 8; ++s) {
+                    const int r = 8 * (kc & 1) + s;
+                    W.Gs[32 * (kc >> 1) + 8 * (r >> 2) + 4 * half + (r & 3)][col] = gb[kc][s];
+                }
             // gradient flowing to the previous layer: W_L^T G_L, times SiLU'
             f32x16 Gp[2];
             if (L > 1) {
                 const int PT = L == 3 ? PK_T3 : PK_T2;
-                bf16x8 gb[4];
-#pragma unroll
-                for (int kc = 0; kc < 4; ++kc)
-#pragma unroll
-                    for (int s = 0; s < 8; ++s) gb[kc][s] = (__bf16)G[kc >> 1][8 * (kc & 1) + s];
 #pragma unroll
                 for (int mt = 0; mt < 2; ++mt) {
                     f32x16 a = zero;
 #pragma unroll
-                    for (int kc = 0; kc < 4; ++kc) a = mfma32(pk[PT + (mt * 4 + kc) * 64 + lane], gb[kc], a);
+                    for (int kc = 0; kc < 4; ++kc)
+                        a = mfma32(s_pk[PT + (mt * 4 + kc) * 64 + lane], gb[kc], a);
 #pragma unroll
                     for (int r = 0; r < 16; ++r)
-                        Gp[mt][r] = a[r] * silu_grad(st.z[2 * (L - 2) + mt][r]);
+                        Gp[mt][r] = a[r] * float(st.dz[4 * (L - 2) + 2 * mt + (r >> 3)][r & 7]);
                 }
             }
-            // dW_L = G_L H_{L-1}^T and db_L = G_L 1 through LDS transposes
-            __syncthreads();
-#pragma unroll
-            for (int mt = 0; mt < 2; ++mt)
-#pragma unroll
-                for (int r = 0; r < 16; ++r)
-                    Gs[32 * mt + 8 * (r >> 2) + 4 * half + (r & 3)][col] = (__bf16)G[mt][r];
             if (L > 1) {
 #pragma unroll
                 for (int kc = 0; kc < 4; ++kc)
 #pragma unroll
                     for (int s = 0; s < 8; ++s)
-                        Hs[perm_in(kc, half, s)][col] = st.h[4 * (L - 2) + kc][s];
+                        W.Hs[perm_in(kc, half, s)][col] = st.h[4 * (L - 2) + kc][s];
             } else {
                 // inputs: rows 0..4 features, rows 5..31 zero
 #pragma unroll
                 for (int f = 0; f < 16; ++f)
-                    Hs[16 * half + f][col] = (__bf16)(half == 0 && f < 8 ? float(xb[f & 7]) : 0.0f);
+                    W.Hs[16 * half + f][col] =
+                        (__bf16)(half == 0 && f < 8 ? float(xb[f & 7]) : 0.0f);
             }
-            __syncthreads();
-            const int ntiles = L == 1 ? 1 : 2;
+            wave_lds_sync();
 #pragma unroll
             for (int mt = 0; mt < 2; ++mt) {
+                bf16x8 A[2];
 #pragma unroll
-                for (int nt = 0; nt < 2; ++nt) {
-                    if (nt >= ntiles) break;
+                for (int kk = 0; kk < 2; ++kk)
+                    A[kk] = *(const bf16x8 *)&W.Gs[32 * mt + col][16 * kk + 8 * half];
+                if (L == 3) {
+#pragma unroll
+                    for (int nt = 0; nt < 2; ++nt) {
+#pragma unroll
+                        for (int kk = 0; kk < 2; ++kk) {
+                            const bf16x8 Bv =
+                                *(const bf16x8 *)&W.Hs[32 * nt + col][16 * kk + 8 * half];
+                            acc3[mt][nt] = mfma32(A[kk], Bv, acc3[mt][nt]);
+                        }
+                    }
+                } else if (L == 2) {
+#pragma unroll
+                    for (int nt = 0; nt < 2; ++nt) {
+                        f32x16 a = zero;
+#pragma unroll
+                        for (int kk = 0; kk < 2; ++kk) {
+                            const bf16x8 Bv =
+                                *(const bf16x8 *)&W.Hs[32 * nt + col][16 * kk + 8 * half];
+                            a = mfma32(A[kk], Bv, a);
+                        }
+#pragma unroll
+                        for (int r = 0; r < 16; ++r) {
+                            const int rw = 32 * mt + 8 * (r >> 2) + 4 * half + (r & 3);
+                            W.w2[rw * MLP_NH + 32 * nt + col] += a[r];
+                        }
+                    }
+                } else {
                     f32x16 a = zero;
 #pragma unroll
                     for (int kk = 0; kk < 2; ++kk) {
-                        const bf16x8 A = *(const bf16x8 *)&Gs[32 * mt + col][16 * kk + 8 * half];
-                        const bf16x8 Bv = *(const bf16x8 *)&Hs[32 * nt + col][16 * kk + 8 * half];
-                        a = mfma32(A, Bv, a);
+                        const bf16x8 Bv = *(const bf16x8 *)&W.Hs[col][16 * kk + 8 * half];
+                        a = mfma32(A[kk], Bv, a);
                     }
-                    const int n = 32 * nt + col;
-                    if (n < nin) {
+                    if (col < MLP_NIN) {
 #pragma unroll
                         for (int r = 0; r < 16; ++r) {
-                            const int row = 32 * mt + 8 * (r >> 2) + 4 * half + (r & 3);
-                            gacc[offW + row * nin + n] += a[r];
+                            const int rw = 32 * mt + 8 * (r >> 2) + 4 * half + (r & 3);
+                            W.g[GS_W1 + rw * MLP_NIN + col] += a[r];
                         }
                     }
                 }
                 f32x16 a = zero;
 #pragma unroll
-                for (int kk = 0; kk < 2; ++kk) {
-                    const bf16x8 A = *(const bf16x8 *)&Gs[32 * mt + col][16 * kk + 8 * half];
-                    a = mfma32(A, ones, a);
-                }
+                for (int kk = 0; kk < 2; ++kk) a = mfma32(A[kk], ones, a);
                 if (col == 0) {
 #pragma unroll
                     for (int r = 0; r < 16; ++r)
-                        gacc[offB + 32 * mt + 8 * (r >> 2) + 4 * half + (r & 3)] += a[r];
+                        W.g[gsB + 32 * mt + 8 * (r >> 2) + 4 * half + (r & 3)] += a[r];
                 }
             }
             if (L > 1) {
@@ -289,11 +378,55 @@ __global__ __launch_bounds__(64) void mlp_grad_kernel(const bf16x8 *__restrict__
             }
         }
     }
+
+    // the block's partial row: dW3 added over the wavefronts in order in
+    // the (now free) operand area, dW2 and the small gradients likewise
     __syncthreads();
-    for (int i = lane; i < MLP_NPARAM; i += 64) part[size_t(blockIdx.x) * MLP_NPARAM + i] = gacc[i];
+    float *sW = reinterpret_cast<float *>(s_pk);   // dW3, 4096 floats
+    static_assert(sizeof(bf16x8) * PK_ALL >= MLP_NH * MLP_NH * sizeof(float), "dW3 fits");
+    for (int w = 0; w < GRAD_WAVES; ++w) {
+        if (wave == w) {
+#pragma unroll
+            for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+                for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) {
+                        const int rw = 32 * mt + 8 * (r >> 2) + 4 * half + (r & 3);
+                        const int k = rw * MLP_NH + 32 * nt + col;
+                        sW[k] = (w == 0 ? 0.0f : sW[k]) + acc3[mt][nt][r];
+                    }
+        }
+        __syncthreads();
+    }
+    float *prow = part + size_t(blockIdx.x) * MLP_NPARAM;
+    for (int i = tid; i < MLP_NPARAM; i += GRAD_THREADS) {
+        float v;
+        if (i >= OFF_W2 && i < OFF_B2) {
+            const int k = i - OFF_W2;
+            v = s_w[0].w2[k];
+#pragma unroll
+            for (int w = 1; w < GRAD_WAVES; ++w) v += s_w[w].w2[k];
+        } else if (i >= OFF_W3 && i < OFF_B3) {
+            v = sW[i - OFF_W3];
+        } else {
+            const int k = small_index(i);
+            v = s_w[0].g[k];
+#pragma unroll
+            for (int w = 1; w < GRAD_WAVES; ++w) v += s_w[w].g[k];
+        }
+        prow[i] = v;
+    }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) lsum += __shfl_xor(lsum, off);
-    if (lane == 0) lpart[blockIdx.x] = lsum;
+    if (lane == 0) s_loss[wave] = lsum;
+    __syncthreads();
+    if (tid == 0) {
+        double l = s_loss[0];
+#pragma unroll
+        for (int w = 1; w < GRAD_WAVES; ++w) l += s_loss[w];
+        lpart[blockIdx.x] = l;
+    }
 }
 
 // fixed-order reduction of the block gradients; grad = sum / B
@@ -735,7 +868,7 @@ extern "C" int rt_mlp_grad(rt_mlp *m, const float *theta, const float *X, const 
     if (!m) return RT_E_STATE;
     if (B < 1 || !theta || !X || !Y || !grad) return RT_E_ARG;
     if (pack(m, theta) != RT_OK) return RT_E_HIP;
-    hipLaunchKernelGGL(mlp_grad_kernel, dim3(m->nblk), dim3(64), 0, m->stream,
+    hipLaunchKernelGGL(mlp_grad_kernel, dim3(m->nblk), dim3(GRAD_THREADS), 0, m->stream,
                        reinterpret_cast<const bf16x8 *>(m->pk), theta, X, Y, B,
                        SampleKey{0, 0ull, 0}, m->part, m->lpart);
     if (hipGetLastError() != hipSuccess) return RT_E_HIP;
@@ -813,7 +946,7 @@ extern "C" int rt_mlp_grad_noalloc(int32_t grad_blocks, const float *theta, cons
     hipLaunchKernelGGL(mlp_pack_kernel, dim3((PK_ALL * 8 + 255) / 256), dim3(256), 0, s, theta,
                        pk);
     if (hipGetLastError() != hipSuccess) return RT_E_HIP;
-    hipLaunchKernelGGL(mlp_grad_kernel, dim3(grad_blocks), dim3(64), 0, s,
+    hipLaunchKernelGGL(mlp_grad_kernel, dim3(grad_blocks), dim3(GRAD_THREADS), 0, s,
                        reinterpret_cast<const bf16x8 *>(pk), theta, X, Y, B,
                        SampleKey{0, 0ull, 0}, part, lpart);
     if (hipGetLastError() != hipSuccess) return RT_E_HIP;
@@ -965,7 +1098,7 @@ extern "C" int rt_mlp_train(rt_mlp *m, float *theta, float *mom1, float *mom2, c
     for (int64_t st = step0 + 1; st <= step0 + nsteps; ++st) {
         const SampleKey sk{1, splitmix64(o->seed ^ (uint64_t(st) * 0xD1B54A32D192ED03ull)), n};
         if (pack(m, theta) != RT_OK) return RT_E_HIP;
-        hipLaunchKernelGGL(mlp_grad_kernel, dim3(m->nblk), dim3(64), 0, s,
+        hipLaunchKernelGGL(mlp_grad_kernel, dim3(m->nblk), dim3(GRAD_THREADS), 0, s,
                            reinterpret_cast<const bf16x8 *>(m->pk), static_cast<const float *>(theta),
                            X, Y, o->batch, sk, m->part, m->lpart);
         hipLaunchKernelGGL(mlp_reduce_kernel, dim3(RED_BLOCKS), dim3(64 * RED_WAVES), 0, s,

@@ -59,18 +59,22 @@ __device__ __forceinline__ float silu(float z)
     return z * frcp(1.0f + fexp2(-1.4426950408889634f * z));
 }
 
-__device__ __forceinline__ float silu_grad(float z)
-{
-    const float s = frcp(1.0f + fexp2(-1.4426950408889634f * z));
-    return s * (1.0f + z * (1.0f - s));
-}
-
-// Saved forward state of 32 cells (training): pre-activations of the three
-// hidden layers (2 tiles each) and the bf16 B operands fed to layers 2, 3, 4.
+// Saved forward state of 32 cells (training): the SiLU derivatives
+// silu'(z) of the three hidden layers' pre-activations and the B operands
+// fed to layers 2, 3, 4, both bf16 in the same register layout (layer l,
+// tile mt, register r of the D layout at [4 l + 2 mt + r / 8][r % 8]).
 struct MlpFwd {
-    f32x16 z[6];
+    bf16x8 dz[12];
     bf16x8 h[12];
 };
+
+// silu(z) = z s and silu'(z) = s (1 + z (1 - s)), s = 1 / (1 + e^-z)
+__device__ __forceinline__ float silu_keep(float z, float &dz)
+{
+    const float s = frcp(1.0f + fexp2(-1.4426950408889634f * z));
+    dz = s * (1.0f + z * (1.0f - s));
+    return z * s;
+}
 
 // Biases of the four layers (FP32), wherever they live (global or LDS).
 struct MlpBias {
@@ -94,8 +98,13 @@ __device__ __forceinline__ void mlp_forward32(const PK *pk, const MlpBias &bias,
         for (int r = 0; r < 16; ++r) {
             const int n = 32 * mt + 8 * (r >> 2) + 4 * half + (r & 3);
             const float z = acc[r] + bias.b1[n];
-            if (KEEP) st.z[mt][r] = z;
-            h[2 * mt + (r >> 3)][r & 7] = (__bf16)silu(z);
+            if (KEEP) {
+                float dz;
+                h[2 * mt + (r >> 3)][r & 7] = (__bf16)silu_keep(z, dz);
+                st.dz[2 * mt + (r >> 3)][r & 7] = (__bf16)dz;
+            } else {
+                h[2 * mt + (r >> 3)][r & 7] = (__bf16)silu(z);
+            }
         }
     }
     if (KEEP) {
@@ -116,8 +125,13 @@ __device__ __forceinline__ void mlp_forward32(const PK *pk, const MlpBias &bias,
             for (int r = 0; r < 16; ++r) {
                 const int n = 32 * mt + 8 * (r >> 2) + 4 * half + (r & 3);
                 const float z = acc[r] + bl[n];
-                if (KEEP) st.z[2 + 2 * L + mt][r] = z;
-                hn[2 * mt + (r >> 3)][r & 7] = (__bf16)silu(z);
+                if (KEEP) {
+                    float dz;
+                    hn[2 * mt + (r >> 3)][r & 7] = (__bf16)silu_keep(z, dz);
+                    st.dz[4 * (L + 1) + 2 * mt + (r >> 3)][r & 7] = (__bf16)dz;
+                } else {
+                    hn[2 * mt + (r >> 3)][r & 7] = (__bf16)silu(z);
+                }
             }
         }
 #pragma unroll

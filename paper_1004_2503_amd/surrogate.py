@@ -159,7 +159,7 @@ def _init_params(seed: int) -> np.ndarray:
 
 
 def fit(X, U, steps: int = 3000, batch: int = 65536, lr: float = 2e-3, seed: int = 0,
-        grad_blocks: int = 512, log_every: int = 250, verbose: bool = True,
+        grad_blocks: int = 256, log_every: int = 250, verbose: bool = True,
         warmup: float = 0.05, clip: float | None = 1.0) -> Surrogate:
     """Fit the network to raw features X (n, 5) and encoded targets U (n, 2),
     device tensors from exact_pairs.  Adam with a learning rate that rises

@@ -125,12 +125,17 @@ void m1_step_kernel(StepArgs A)
     constexpr int KTY = BIG ? TY_LF : TY;   // tile rows of this form
     constexpr int KNT = TX * KTY;           // its threads per block
     constexpr int SW = TX + 2;
-    __shared__ float sN[KTY + 2][SW], sFx[KTY + 2][SW], sFy[KTY + 2][SW], sFz[KTY + 2][SW];
-    __shared__ float sPxx[KTY + 2][SW], sPyy[KTY + 2][SW], sPxy[KTY + 2][SW];
-    __shared__ float sPxz[KTY + 2][SW], sPyz[KTY + 2][SW];
+    // Plane z's tile and halo, double-buffered by the parity of z: a plane
+    // writes one buffer while slower wavefronts may still read the other,
+    // so one barrier per plane suffices (everyone has finished reading a
+    // buffer before anyone passes the barrier of the plane after it).
+    __shared__ float sN[2][KTY + 2][SW], sFx[2][KTY + 2][SW], sFy[2][KTY + 2][SW];
+    __shared__ float sFz[2][KTY + 2][SW];
+    __shared__ float sPxx[2][KTY + 2][SW], sPyy[2][KTY + 2][SW], sPxy[2][KTY + 2][SW];
+    __shared__ float sPxz[2][KTY + 2][SW], sPyz[2][KTY + 2][SW];
     // HLL: x and y signal speeds of the tile and its halo
     constexpr int HY = HLL ? KTY + 2 : 1, HX = HLL ? SW : 1;
-    __shared__ float sLxm[HY][HX], sLxp[HY][HX], sLym[HY][HX], sLyp[HY][HX];
+    __shared__ float sLxm[2][HY][HX], sLxp[2][HY][HX], sLym[2][HY][HX], sLyp[2][HY][HX];
     __shared__ double sred[KNT / 64][NRED];
 
     const int tid = threadIdx.x;
@@ -261,7 +266,7 @@ void m1_step_kernel(StepArgs A)
     // receives plane z+1's.
     uint64_t mword = 0;   // A.defer: this lane's plane (z0 + lane) of deferred cells
     auto plane_step = [&](const int z, const Cell4 &nxt_raw, Cell4 &nx_ld, const Cell4 &hal_raw,
-                          Cell4 &hal_ld, const float3 &ch, float3 &ch_ld) {
+                          Cell4 &hal_ld, const float3 &ch, float3 &ch_ld, const int bi) {
         const float c_xh = ch.x, c_nh = ch.z;
         float c_T = ch.y;
         // Prefetch (unconditionally, so that every lane of every plane issues
@@ -284,39 +289,39 @@ void m1_step_kernel(StepArgs A)
         // plane z into LDS: own cell and its halo
         {
             const int sy = ly + 1, sx = lx + 1;
-            sN[sy][sx] = cur.N;
-            sFx[sy][sx] = cur.Fx;
-            sFy[sy][sx] = cur.Fy;
-            sFz[sy][sx] = cur.Fz;
-            sPxx[sy][sx] = pcur.xx;
-            sPyy[sy][sx] = pcur.yy;
-            sPxy[sy][sx] = pcur.xy;
-            sPxz[sy][sx] = pcur.xz;
-            sPyz[sy][sx] = pcur.yz;
+            sN[bi][sy][sx] = cur.N;
+            sFx[bi][sy][sx] = cur.Fx;
+            sFy[bi][sy][sx] = cur.Fy;
+            sFz[bi][sy][sx] = cur.Fz;
+            sPxx[bi][sy][sx] = pcur.xx;
+            sPyy[bi][sy][sx] = pcur.yy;
+            sPxy[bi][sy][sx] = pcur.xy;
+            sPxz[bi][sy][sx] = pcur.xz;
+            sPyz[bi][sy][sx] = pcur.yz;
             if constexpr (HLL) {
-                sLxm[sy][sx] = lcur.xm;
-                sLxp[sy][sx] = lcur.xp;
-                sLym[sy][sx] = lcur.ym;
-                sLyp[sy][sx] = lcur.yp;
+                sLxm[bi][sy][sx] = lcur.xm;
+                sLxp[bi][sy][sx] = lcur.xp;
+                sLym[bi][sy][sx] = lcur.ym;
+                sLyp[bi][sy][sx] = lcur.yp;
             }
         }
         if (has_halo) {
             const Press ph = closure(hal.N, hal.Fx, hal.Fy, hal.Fz, A.inv_c);
-            sN[hsy][hsx] = hal.N;
-            sFx[hsy][hsx] = hal.Fx;
-            sFy[hsy][hsx] = hal.Fy;
-            sFz[hsy][hsx] = hal.Fz;
-            sPxx[hsy][hsx] = ph.xx;
-            sPyy[hsy][hsx] = ph.yy;
-            sPxy[hsy][hsx] = ph.xy;
-            sPxz[hsy][hsx] = ph.xz;
-            sPyz[hsy][hsx] = ph.yz;
+            sN[bi][hsy][hsx] = hal.N;
+            sFx[bi][hsy][hsx] = hal.Fx;
+            sFy[bi][hsy][hsx] = hal.Fy;
+            sFz[bi][hsy][hsx] = hal.Fz;
+            sPxx[bi][hsy][hsx] = ph.xx;
+            sPyy[bi][hsy][hsx] = ph.yy;
+            sPxy[bi][hsy][hsx] = ph.xy;
+            sPxz[bi][hsy][hsx] = ph.xz;
+            sPyz[bi][hsy][hsx] = ph.yz;
             if constexpr (HLL) {
                 const Speeds lh = m1_speeds(hal.N, hal.Fx, hal.Fy, hal.Fz, A.inv_c, A.c_d);
-                sLxm[hsy][hsx] = lh.xm;
-                sLxp[hsy][hsx] = lh.xp;
-                sLym[hsy][hsx] = lh.ym;
-                sLyp[hsy][hsx] = lh.yp;
+                sLxm[bi][hsy][hsx] = lh.xm;
+                sLxp[bi][hsy][hsx] = lh.xp;
+                sLym[bi][hsy][hsx] = lh.ym;
+                sLyp[bi][hsy][hsx] = lh.yp;
             }
         }
         __syncthreads();
@@ -326,33 +331,32 @@ void m1_step_kernel(StepArgs A)
         if constexpr (HLL) lnxt = m1_speeds(nxt.N, nxt.Fx, nxt.Fy, nxt.Fz, A.inv_c, A.c_d);
         const int sy = ly + 1, sx = lx + 1;
         // neighbours: x-1 (L), x+1 (R), y-1 (D), y+1 (U), z-1 (prv), z+1 (nxt)
-        const float NL = sN[sy][sx - 1], NR = sN[sy][sx + 1];
-        const float ND = sN[sy - 1][sx], NU = sN[sy + 1][sx];
-        const float FxL = sFx[sy][sx - 1], FxR = sFx[sy][sx + 1];
-        const float FxD = sFx[sy - 1][sx], FxU = sFx[sy + 1][sx];
-        const float FyL = sFy[sy][sx - 1], FyR = sFy[sy][sx + 1];
-        const float FyD = sFy[sy - 1][sx], FyU = sFy[sy + 1][sx];
-        const float FzL = sFz[sy][sx - 1], FzR = sFz[sy][sx + 1];
-        const float FzD = sFz[sy - 1][sx], FzU = sFz[sy + 1][sx];
-        const float PxxL = sPxx[sy][sx - 1], PxxR = sPxx[sy][sx + 1];
-        const float PxyL = sPxy[sy][sx - 1], PxyR = sPxy[sy][sx + 1];
-        const float PxzL = sPxz[sy][sx - 1], PxzR = sPxz[sy][sx + 1];
-        const float PxyD = sPxy[sy - 1][sx], PxyU = sPxy[sy + 1][sx];
-        const float PyyD = sPyy[sy - 1][sx], PyyU = sPyy[sy + 1][sx];
-        const float PyzD = sPyz[sy - 1][sx], PyzU = sPyz[sy + 1][sx];
+        const float NL = sN[bi][sy][sx - 1], NR = sN[bi][sy][sx + 1];
+        const float ND = sN[bi][sy - 1][sx], NU = sN[bi][sy + 1][sx];
+        const float FxL = sFx[bi][sy][sx - 1], FxR = sFx[bi][sy][sx + 1];
+        const float FxD = sFx[bi][sy - 1][sx], FxU = sFx[bi][sy + 1][sx];
+        const float FyL = sFy[bi][sy][sx - 1], FyR = sFy[bi][sy][sx + 1];
+        const float FyD = sFy[bi][sy - 1][sx], FyU = sFy[bi][sy + 1][sx];
+        const float FzL = sFz[bi][sy][sx - 1], FzR = sFz[bi][sy][sx + 1];
+        const float FzD = sFz[bi][sy - 1][sx], FzU = sFz[bi][sy + 1][sx];
+        const float PxxL = sPxx[bi][sy][sx - 1], PxxR = sPxx[bi][sy][sx + 1];
+        const float PxyL = sPxy[bi][sy][sx - 1], PxyR = sPxy[bi][sy][sx + 1];
+        const float PxzL = sPxz[bi][sy][sx - 1], PxzR = sPxz[bi][sy][sx + 1];
+        const float PxyD = sPxy[bi][sy - 1][sx], PxyU = sPxy[bi][sy + 1][sx];
+        const float PyyD = sPyy[bi][sy - 1][sx], PyyU = sPyy[bi][sy + 1][sx];
+        const float PyzD = sPyz[bi][sy - 1][sx], PyzU = sPyz[bi][sy + 1][sx];
         float lxmL = 0.f, lxpL = 0.f, lxmR = 0.f, lxpR = 0.f;
         float lymD = 0.f, lypD = 0.f, lymU = 0.f, lypU = 0.f;
         if constexpr (HLL) {
-            lxmL = sLxm[sy][sx - 1];
-            lxpL = sLxp[sy][sx - 1];
-            lxmR = sLxm[sy][sx + 1];
-            lxpR = sLxp[sy][sx + 1];
-            lymD = sLym[sy - 1][sx];
-            lypD = sLyp[sy - 1][sx];
-            lymU = sLym[sy + 1][sx];
-            lypU = sLyp[sy + 1][sx];
+            lxmL = sLxm[bi][sy][sx - 1];
+            lxpL = sLxp[bi][sy][sx - 1];
+            lxmR = sLxm[bi][sy][sx + 1];
+            lxpR = sLxp[bi][sy][sx + 1];
+            lymD = sLym[bi][sy - 1][sx];
+            lypD = sLyp[bi][sy - 1][sx];
+            lymU = sLym[bi][sy + 1][sx];
+            lypU = sLyp[bi][sy + 1][sx];
         }
-        __syncthreads();
 
         float dN, dFx, dFy, dFz;
         if constexpr (HLL) {
@@ -599,8 +603,8 @@ void m1_step_kernel(StepArgs A)
     };
 
     for (int z = z0; z < z1; z += 2) {
-        plane_step(z, nx1, nx0, ha0, ha1, ch0, ch1);
-        if (z + 1 < z1) plane_step(z + 1, nx0, nx1, ha1, ha0, ch1, ch0);
+        plane_step(z, nx1, nx0, ha0, ha1, ch0, ch1, 0);
+        if (z + 1 < z1) plane_step(z + 1, nx0, nx1, ha1, ha0, ch1, ch0, 1);
         if (A.defer && (((z + 2 - z0) & 63) == 0 || z + 2 >= z1)) {
             // one x-row per wave, 64 planes zb .. zb+63 of the chunk one per
             // lane, stored once they are done
@@ -857,17 +861,34 @@ __global__ __launch_bounds__(GPB) void mask_compact_kernel(const StepArgs A, con
             if (j >= n) break;
             const uint64_t g = g0 + uint64_t(gi[j]);
             const int cnt = __popcll(wd[j]);
-            int incl = cnt;
+            int incl = cnt, most = cnt;
 #pragma unroll
             for (int off = 1; off < 64; off <<= 1) {
                 const int v = __shfl_up(incl, off);
                 if (lane >= off) incl += v;
+                most = max(most, __shfl_xor(most, off));
             }
-            uint32_t r = bbase + loc[g] + uint32_t(incl - cnt);
+            const uint32_t gbase = bbase + loc[g];
             const uint64_t w = g * 64 + uint64_t(lane);
             const uint32_t cell0 = uint32_t(w / uint64_t(A.ntx)) * uint32_t(A.nx) +
                                    uint32_t(w % uint64_t(A.ntx)) * TX;
-            for (uint64_t m = wd[j]; m; m &= m - 1ull) cells[r++] = cell0 + uint32_t(__builtin_ctzll(m));
+            const uint64_t nonzero = __ballot(wd[j] != 0ull);
+            if (uint32_t(__popcll(nonzero)) < uint32_t(most)) {
+                // few marked words, densely marked: all lanes store one word
+                // at a time, lane l its bit l (ranks from the bits below it)
+                const uint64_t below = (1ull << lane) - 1ull;
+                for (uint64_t nz = nonzero; nz; nz &= nz - 1ull) {
+                    const int k = __builtin_ctzll(nz);
+                    const uint64_t wk = __shfl(wd[j], k);
+                    const uint32_t c0 = __shfl(cell0, k);
+                    const uint32_t rk = gbase + uint32_t(__shfl(incl - cnt, k));
+                    if ((wk >> lane) & 1ull) cells[rk + uint32_t(__popcll(wk & below))] = c0 + uint32_t(lane);
+                }
+            } else {
+                // sparsely marked words: each lane stores its own bits
+                uint32_t r = gbase + uint32_t(incl - cnt);
+                for (uint64_t m = wd[j]; m; m &= m - 1ull) cells[r++] = cell0 + uint32_t(__builtin_ctzll(m));
+            }
         }
     }
 }

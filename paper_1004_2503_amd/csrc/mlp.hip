@@ -624,44 +624,59 @@ __global__ __launch_bounds__(256) void mlp_moments_kernel(const float *__restric
                                                           int d, const double *__restrict__ stats,
                                                           double *__restrict__ part)
 {
-    __shared__ double s_a[256];
-    __shared__ float s_lo[256], s_hi[256];
+    __shared__ double s_a[MOM_MAXD][256];
+    __shared__ float s_lo[MOM_MAXD][256], s_hi[MOM_MAXD][256];
+    const int t = threadIdx.x;
     const int64_t r0 = int64_t(blockIdx.x) * n / MOM_BLOCKS;
     const int64_t r1 = int64_t(blockIdx.x + 1) * n / MOM_BLOCKS;
-    for (int k = 0; k < d; ++k) {
-        const double mu = stats ? stats[k] : 0.0;
-        double acc = 0.0;
-        float lo = INFINITY, hi = -INFINITY;
-        for (int64_t r = r0 + threadIdx.x; r < r1; r += 256) {
+    double mu[MOM_MAXD], acc[MOM_MAXD];
+    float lo[MOM_MAXD], hi[MOM_MAXD];
+#pragma unroll
+    for (int k = 0; k < MOM_MAXD; ++k) {
+        mu[k] = (stats && k < d) ? stats[k] : 0.0;
+        acc[k] = 0.0;
+        lo[k] = INFINITY;
+        hi[k] = -INFINITY;
+    }
+    // one pass over the rows, every column of a row at once
+    for (int64_t r = r0 + t; r < r1; r += 256) {
+#pragma unroll
+        for (int k = 0; k < MOM_MAXD; ++k) {
+            if (k >= d) break;
             const float v = A[r * d + k];
             if (stats) {
-                const double e = double(v) - mu;
-                acc += e * e;
+                const double e = double(v) - mu[k];
+                acc[k] += e * e;
             } else {
-                acc += double(v);
-                lo = fminf(lo, v);
-                hi = fmaxf(hi, v);
+                acc[k] += double(v);
+                lo[k] = fminf(lo[k], v);
+                hi[k] = fmaxf(hi[k], v);
             }
         }
-        s_a[threadIdx.x] = acc;
-        s_lo[threadIdx.x] = lo;
-        s_hi[threadIdx.x] = hi;
-        __syncthreads();
-        for (int h = 128; h > 0; h >>= 1) {
-            if (threadIdx.x < h) {
-                s_a[threadIdx.x] += s_a[threadIdx.x + h];
-                s_lo[threadIdx.x] = fminf(s_lo[threadIdx.x], s_lo[threadIdx.x + h]);
-                s_hi[threadIdx.x] = fmaxf(s_hi[threadIdx.x], s_hi[threadIdx.x + h]);
+    }
+#pragma unroll
+    for (int k = 0; k < MOM_MAXD; ++k) {
+        s_a[k][t] = acc[k];
+        s_lo[k][t] = lo[k];
+        s_hi[k][t] = hi[k];
+    }
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (t < h) {
+#pragma unroll
+            for (int k = 0; k < MOM_MAXD; ++k) {
+                s_a[k][t] += s_a[k][t + h];
+                s_lo[k][t] = fminf(s_lo[k][t], s_lo[k][t + h]);
+                s_hi[k][t] = fmaxf(s_hi[k][t], s_hi[k][t + h]);
             }
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) {
-            double *row = part + size_t(blockIdx.x) * 3 * MOM_MAXD;
-            row[k] = s_a[0];
-            row[MOM_MAXD + k] = double(s_lo[0]);
-            row[2 * MOM_MAXD + k] = double(s_hi[0]);
         }
         __syncthreads();
+    }
+    if (t < d) {
+        double *row = part + size_t(blockIdx.x) * 3 * MOM_MAXD;
+        row[t] = s_a[t][0];
+        row[MOM_MAXD + t] = double(s_lo[t][0]);
+        row[2 * MOM_MAXD + t] = double(s_hi[t][0]);
     }
 }
 
@@ -766,14 +781,16 @@ __global__ __launch_bounds__(256) void mlp_predict_kernel(const bf16x8 *__restri
     }
 }
 
-// out = scale * sum of the n partials, in order
+// out = scale * sum of the n partials, in a fixed order: lane l adds the
+// partials l, l + 64, ..., then a fixed butterfly combines the lanes
 __global__ __launch_bounds__(64) void mlp_sum_kernel(const double *__restrict__ part, int n,
                                                      double scale, double *__restrict__ out)
 {
-    if (threadIdx.x != 0) return;
     double t = 0.0;
-    for (int b = 0; b < n; ++b) t += part[b];
-    *out = t * scale;
+    for (int b = threadIdx.x; b < n; b += 64) t += part[b];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off);
+    if (threadIdx.x == 0) *out = t * scale;
 }
 
 hipError_t launch_mlp_pack(const float *theta, __bf16 *pk, hipStream_t s)

@@ -297,3 +297,90 @@ def test_cosmo1024_every_source_cell_and_the_faces():
     assert checked_src == len(ijk)
     G.close()
     torch.cuda.empty_cache()
+
+
+@pytest.mark.timeout(600)
+def test_cosmo512_learned_step_on_sampled_blocks():
+    # The learned chemistry at 512^3 (16384 sources, mixed precision,
+    # adaptive exact fallback with up to 32 sub-cycles): a network trained
+    # through the library on pairs from this run's own states, then one
+    # learned step checked on sampled 32^3 blocks against the FP64 oracle's
+    # exact adaptive step from the same input state (transport on both
+    # sides, chemistry exact in the oracle): mean |dxHI| <= 1e-3 on the
+    # blocks; N and F of a learned cell follow from its predicted xHI'
+    # through the photon accounting, so they carry its error times nH/N:
+    # within 1e-2 of the block's largest N (reported).
+    from paper_1004_2503_amd import surrogate
+
+    w = W.workload("cosmo512")
+    n, B, ncap = w.n, 32, 32
+    nH, ijk, ndot = W.cosmo_inputs(w, device="cuda")
+    G = rt.RTGrid(rt.make_params((n,) * 3, w.dx, prec=rt.PREC_MIXED, sub=rt.SUB_ADAPTIVE,
+                                 sub_eps=0.1), dict(nH=nH))
+    del nH
+    G.inject_sources(ijk, ndot)
+    states = []
+    for _ in range(3):
+        G.step(w.dt, ncap, 20)
+        t = G.tensors()
+        states.append({k: t[k].clone() for k in ("N", "xHI", "T", "nH")})
+    pexact = rt.make_params((1, 1, 1), 1.0, prec=rt.PREC_MIXED, sub=rt.SUB_ADAPTIVE, sub_eps=0.1)
+    Xs, Us = [], []
+    for i, st in enumerate(states):
+        c = surrogate.sample_cells(st, 300_000, 50 + i)
+        X, U, _, _ = surrogate.candidate_pairs(pexact, c, w.dt, 150_000, 64, fp64_thr=1e-3,
+                                               seed=60 + i)
+        Xs.append(X)
+        Us.append(U)
+    del states
+    s = surrogate.fit(torch.cat(Xs), torch.cat(Us), steps=3000, batch=32768, lr=2e-3,
+                      verbose=False)
+    print(f"512^3: network trained, loss {s.history[-1][1]:.3e}", flush=True)
+    rt.check(rt.rt_set_surrogate(G.ctx, s.theta, s.norm_array(), 1e-3), "rt_set_surrogate")
+    rng = np.random.default_rng(512)
+    origins = [tuple(int(v) for v in rng.integers(0, n - B + 1, 3)) for _ in range(12)]
+    for q in rng.choice(len(ijk), 6, replace=False):
+        i, j, k = (int(v) for v in ijk[q])
+        origins.append((max(0, min(k - B // 2, n - B)), max(0, min(j - B // 2, n - B)),
+                        max(0, min(i - B // 2, n - B))))
+    pre = G.tensors()
+    before = {o: dict(xHI=_block(pre["xHI"], *o, B, 0, n), T=_block(pre["T"], *o, B, 0, n))
+              for o in origins}
+    red0 = G.reduce()
+    G.step(w.dt, ncap)
+    red = G.reduce()
+    assert red["n_learned"] > red0["n_learned"]            # the network took part
+    post = G.tensors()
+    cur = G.current()
+    Nin, Fin = G.N[1 - cur], [G.Fx[1 - cur], G.Fy[1 - cur], G.Fz[1 - cur]]
+    p = oracle.make_params((B, B, B), w.dx, chem=oracle.CHEM_FULL, sub=oracle.SUB_ADAPTIVE,
+                           sub_eps=0.1)
+    vol = w.dx ** 3
+    dx_sum, ncell, worst = 0.0, 0, dict(N=0.0, F=0.0)
+    for o in origins:
+        z0, y0, x0 = o
+        S = np.zeros((B, B, B))
+        inside = ((ijk[:, 0] >= x0) & (ijk[:, 0] < x0 + B) & (ijk[:, 1] >= y0) &
+                  (ijk[:, 1] < y0 + B) & (ijk[:, 2] >= z0) & (ijk[:, 2] < z0 + B))
+        for (i, j, k), q in zip(ijk[inside], ndot[inside]):
+            S[k - z0, j - y0, i - x0] += q / vol
+        res = oracle.step_subblock(p, w.dt, ncap, _block(Nin, *o, B, 1, n),
+                                   [_block(f, *o, B, 1, n) for f in Fin],
+                                   before[o]["xHI"], before[o]["T"],
+                                   _block(G.nH, *o, B, 0, n), S)
+        got = {k: _block(post[k], *o, B, 0, n) for k in ("N", "Fx", "Fy", "Fz", "xHI")}
+        dx_sum += float(np.abs(got["xHI"] - res[4]).sum())
+        ncell += B ** 3
+        if np.max(np.abs(res[0])) > 0:
+            e = errors(dict(got, T=res[5]), dict(N=res[0], Fx=res[1], Fy=res[2], Fz=res[3],
+                                                 xHI=res[4], T=res[5]))
+            worst = {k: max(worst[k], e[k]) for k in worst}
+    mean_dx = dx_sum / ncell
+    print(f"512^3 learned step, {len(origins)} blocks: mean |dxHI| against the oracle's exact "
+          f"adaptive step {mean_dx:.3e}, worst N {worst['N']:.2e}, F {worst['F']:.2e}; "
+          f"network cells {red['n_learned'] - red0['n_learned']}, fallbacks "
+          f"{red['n_fallback'] - red0['n_fallback']}", flush=True)
+    assert mean_dx <= 1e-3
+    assert worst["N"] <= 1e-2 and worst["F"] <= 1e-2
+    G.close()
+    torch.cuda.empty_cache()

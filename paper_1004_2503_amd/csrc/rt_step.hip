@@ -733,7 +733,9 @@ __device__ __forceinline__ bool surr_accept(const StepArgs &A, const float f[5],
 // further on: every wavefront gets the same number of cells however they
 // cluster, and which wavefront takes which cell depends only on the mask.
 constexpr int CHUNK = 256;          // cells per chunk: four batches of 64
-constexpr int GPB = 256;            // groups per counting block (4 wavefronts x 64)
+constexpr int GPB = 256;            // groups per counting block
+constexpr int GPW = 16;             // groups per wavefront of the count and the compaction
+constexpr int CNT_THREADS = GPB / GPW * 64;   // 16 wavefronts: more loads in flight
 constexpr int SCAN_THREADS = 1024;
 
 __host__ __device__ inline uint64_t count_blocks(uint64_t nwords)
@@ -745,19 +747,21 @@ __host__ __device__ inline uint64_t count_blocks(uint64_t nwords)
 // count_blocks + 1 (the totals here, turned into offsets by
 // block_offsets_kernel).  With copy, the words of the groups whose bit is
 // set are also copied there.
-__global__ __launch_bounds__(GPB) void mask_count_kernel(const StepArgs A, const uint64_t *src,
-                                                         uint64_t *copy, uint64_t nwords,
-                                                         uint32_t *loc, uint32_t *boff)
+__global__ __launch_bounds__(CNT_THREADS) void mask_count_kernel(const StepArgs A,
+                                                                 const uint64_t *src,
+                                                                 uint64_t *copy, uint64_t nwords,
+                                                                 uint32_t *loc, uint32_t *boff)
 {
     __shared__ uint32_t s_cnt[GPB];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const uint64_t ngroups = mask_groups(nwords);
-    const uint64_t g0 = uint64_t(blockIdx.x) * GPB + uint64_t(wave) * 64;   // 64-aligned
-    s_cnt[t] = 0u;
+    const uint64_t g0 = uint64_t(blockIdx.x) * GPB + uint64_t(wave) * GPW;   // 16-aligned
+    if (lane < GPW) s_cnt[wave * GPW + lane] = 0u;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    uint64_t bits = g0 < ngroups ? A.group_mask[g0 >> 6] : 0ull;
+    uint64_t bits = g0 < ngroups ? (A.group_mask[g0 >> 6] >> (g0 & 63)) & ((1ull << GPW) - 1ull)
+                                 : 0ull;
     while (bits) {
         // up to four marked groups at a time, their loads in flight together
         int gi[4];
@@ -780,12 +784,13 @@ __global__ __launch_bounds__(GPB) void mask_count_kernel(const StepArgs A, const
             int c = __popcll(wd[j]);
 #pragma unroll
             for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
-            if (lane == 0 && j < n) s_cnt[wave * 64 + gi[j]] = uint32_t(c);
+            if (lane == 0 && j < n) s_cnt[wave * GPW + gi[j]] = uint32_t(c);
         }
     }
     __syncthreads();
-    // exclusive scan of the block's 256 counts (one per thread)
-    const uint32_t mine = s_cnt[t];
+    // exclusive scan of the block's 256 counts (one per thread of the first
+    // four wavefronts)
+    const uint32_t mine = t < GPB ? s_cnt[t] : 0u;
     uint32_t incl = mine;
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) {
@@ -793,13 +798,15 @@ __global__ __launch_bounds__(GPB) void mask_count_kernel(const StepArgs A, const
         if (lane >= off) incl += v;
     }
     __shared__ uint32_t s_wsum[GPB / 64];
-    if (lane == 63) s_wsum[wave] = incl;
+    if (t < GPB && lane == 63) s_wsum[wave] = incl;
     __syncthreads();
-    uint32_t before = 0;
-    for (int w2 = 0; w2 < wave; ++w2) before += s_wsum[w2];
-    const uint64_t g = uint64_t(blockIdx.x) * GPB + uint64_t(t);
-    if (g < ngroups) loc[g] = before + incl - mine;
-    if (t == GPB - 1) boff[blockIdx.x] = before + incl;
+    if (t < GPB) {
+        uint32_t before = 0;
+        for (int w2 = 0; w2 < wave; ++w2) before += s_wsum[w2];
+        const uint64_t g = uint64_t(blockIdx.x) * GPB + uint64_t(t);
+        if (g < ngroups) loc[g] = before + incl - mine;
+        if (t == GPB - 1) boff[blockIdx.x] = before + incl;
+    }
 }
 
 // boff[0 .. nb) block totals -> exclusive offsets, boff[nb] = their sum.
@@ -831,16 +838,19 @@ __global__ __launch_bounds__(SCAN_THREADS) void block_offsets_kernel(uint32_t *b
 // The marked cells of src as a dense list in word order: cells[rank] =
 // linear cell index, ranks from loc and boff (mask_count_kernel and
 // block_offsets_kernel on the same src first).  Same blocks as the count.
-__global__ __launch_bounds__(GPB) void mask_compact_kernel(const StepArgs A, const uint64_t *src,
-                                                           uint64_t nwords, const uint32_t *loc,
-                                                           const uint32_t *boff,
-                                                           uint32_t *cells)
+__global__ __launch_bounds__(CNT_THREADS) void mask_compact_kernel(const StepArgs A,
+                                                                   const uint64_t *src,
+                                                                   uint64_t nwords,
+                                                                   const uint32_t *loc,
+                                                                   const uint32_t *boff,
+                                                                   uint32_t *cells)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const uint64_t ngroups = mask_groups(nwords);
-    const uint64_t g0 = uint64_t(blockIdx.x) * GPB + uint64_t(wave) * 64;   // 64-aligned
+    const uint64_t g0 = uint64_t(blockIdx.x) * GPB + uint64_t(wave) * GPW;   // 16-aligned
     const uint32_t bbase = boff[blockIdx.x];
-    uint64_t bits = g0 < ngroups ? A.group_mask[g0 >> 6] : 0ull;
+    uint64_t bits = g0 < ngroups ? (A.group_mask[g0 >> 6] >> (g0 & 63)) & ((1ull << GPW) - 1ull)
+                                 : 0ull;
     while (bits) {
         int gi[4];
         uint64_t wd[4];
@@ -851,10 +861,12 @@ __global__ __launch_bounds__(GPB) void mask_compact_kernel(const StepArgs A, con
             n += bits ? 1 : 0;
             bits &= bits ? bits - 1ull : 0ull;
         }
+        uint32_t gl[4];   // the groups' offsets within the block, loaded with the words
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const uint64_t w = (g0 + uint64_t(gi[j])) * 64 + uint64_t(lane);
             wd[j] = (j < n && w < nwords) ? src[w] : 0ull;
+            gl[j] = loc[g0 + uint64_t(gi[j])];   // gi[j] = 0 past n: group g0, which exists
         }
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
@@ -868,7 +880,7 @@ __global__ __launch_bounds__(GPB) void mask_compact_kernel(const StepArgs A, con
                 if (lane >= off) incl += v;
                 most = max(most, __shfl_xor(most, off));
             }
-            const uint32_t gbase = bbase + loc[g];
+            const uint32_t gbase = bbase + gl[j];
             const uint64_t w = g * 64 + uint64_t(lane);
             const uint32_t cell0 = uint32_t(w / uint64_t(A.ntx)) * uint32_t(A.nx) +
                                    uint32_t(w % uint64_t(A.ntx)) * TX;
@@ -905,9 +917,18 @@ __device__ __forceinline__ void marked_chunks(const uint64_t nwords, const uint3
     const uint32_t waves = gridDim.x * DEFER_WAVES;
     for (uint32_t k = blockIdx.x * DEFER_WAVES + wave; k < nchunks; k += waves) {
         const uint32_t c0 = k * CHUNK, c1 = c0 + CHUNK < total ? c0 + CHUNK : total;
-        for (uint32_t b0 = c0; b0 < c1; b0 += 64) {
-            const bool valid = b0 + uint32_t(lane) < c1;
-            batch(valid ? cells[b0 + lane] : 0u, valid);
+        // the chunk's cell indices first, all four loads in flight together
+        uint32_t idx[CHUNK / 64];
+#pragma unroll
+        for (int q = 0; q < CHUNK / 64; ++q) {
+            const uint32_t r = c0 + uint32_t(q * 64 + lane);
+            idx[q] = r < c1 ? cells[r] : 0u;
+        }
+#pragma unroll 1
+        for (int q = 0; q < CHUNK / 64; ++q) {
+            const uint32_t b0 = c0 + uint32_t(q * 64);
+            if (b0 >= c1) break;
+            batch(idx[q], b0 + uint32_t(lane) < c1);
         }
     }
 }
@@ -1152,11 +1173,11 @@ hipError_t launch_defer_chem(const StepArgs &a, uint64_t nwords, int nb2, uint32
     // the marked cells of `mask` into the dense list (copying the marked
     // groups' words to `copy` on the way when it is given)
     auto list = [&](const uint64_t *mask, uint64_t *copy) {
-        hipLaunchKernelGGL(mask_count_kernel, dim3(unsigned(nbc)), dim3(GPB), 0, s, a, mask, copy,
+        hipLaunchKernelGGL(mask_count_kernel, dim3(unsigned(nbc)), dim3(CNT_THREADS), 0, s, a, mask, copy,
                            nwords, loc, boff);
         hipLaunchKernelGGL(block_offsets_kernel, dim3(1), dim3(SCAN_THREADS), 0, s, boff,
                            int(nbc));
-        hipLaunchKernelGGL(mask_compact_kernel, dim3(unsigned(nbc)), dim3(GPB), 0, s, a, mask,
+        hipLaunchKernelGGL(mask_compact_kernel, dim3(unsigned(nbc)), dim3(CNT_THREADS), 0, s, a, mask,
                            nwords, static_cast<const uint32_t *>(loc),
                            static_cast<const uint32_t *>(boff), cells);
     };

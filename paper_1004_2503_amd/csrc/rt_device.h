@@ -75,17 +75,28 @@ struct Speeds {
     float xm, xp, ym, yp, zm, zp;
 };
 
-__device__ __forceinline__ Speeds m1_speeds(float N, float Fx, float Fy, float Fz, float inv_c,
-                                            double c_d)
+// The parts of the eigenvalue formula shared by the three axes.
+struct SpeedPrep {
+    bool iso;                       // isotropic (no flux): -+1/sqrt(3) on every axis
+    float ux, uy, uz, x2, y2, z2, inv_f2, pref, Sm1, Q;
+};
+
+__device__ __forceinline__ SpeedPrep m1_speed_prep(float N, float Fx, float Fy, float Fz,
+                                                   float inv_c, double c_d)
 {
-    const float ISO = 0.5773502691896258f;
-    Speeds s{-ISO, ISO, -ISO, ISO, -ISO, ISO};
-    if (!(N > N_TINY)) return s;
+    SpeedPrep p{};
+    p.iso = true;
+    if (!(N > N_TINY)) return p;
     const float q = inv_c * frcp(N);
-    const float ux = Fx * q, uy = Fy * q, uz = Fz * q;
-    const float x2 = ux * ux, y2 = uy * uy, z2 = uz * uz;
-    const float f2 = x2 + y2 + z2;
-    if (!(f2 > 1e-20f)) return s;
+    p.ux = Fx * q;
+    p.uy = Fy * q;
+    p.uz = Fz * q;
+    p.x2 = p.ux * p.ux;
+    p.y2 = p.uy * p.uy;
+    p.z2 = p.uz * p.uz;
+    const float f2 = p.x2 + p.y2 + p.z2;
+    if (!(f2 > 1e-20f)) return p;
+    p.iso = false;
     // 1 - f^2 = ((cN)^2 - |F|^2) / (cN)^2: the difference in FP64 (it cancels
     // near free streaming), the quotient in FP32
     const double cn = double(N) * c_d;
@@ -103,19 +114,37 @@ __device__ __forceinline__ Speeds m1_speeds(float N, float Fx, float Fy, float F
     const float inv_S = R * Sp1 * D2;
     const float inv_Sp1 = R * S * D2;
     const float inv_D2 = R * S * Sp1;
-    const float Sm1 = 3.0f * g2 * inv_Sp1;
-    const float Q = (8.0f * D + 6.0f * (3.0f + 4.0f * fs) * inv_S) * inv_D2;   // chi'/f
-    const float pref = (8.0f / 3.0f) * Sm1 * inv_S * inv_S;
-    const float inv_f2 = frcp(f2);
-    auto axis = [&](float ud, float a2, float o2, float &lm, float &lp) {
-        const float r = fsqrt(pref * (Sm1 * (1.0f + a2 * inv_f2) + o2 * inv_f2));
-        const float B = ud * Q;
-        lm = 0.5f * (B - r);
-        lp = 0.5f * (B + r);
-    };
-    axis(ux, x2, y2 + z2, s.xm, s.xp);
-    axis(uy, y2, x2 + z2, s.ym, s.yp);
-    axis(uz, z2, x2 + y2, s.zm, s.zp);
+    p.Sm1 = 3.0f * g2 * inv_Sp1;
+    p.Q = (8.0f * D + 6.0f * (3.0f + 4.0f * fs) * inv_S) * inv_D2;   // chi'/f
+    p.pref = (8.0f / 3.0f) * p.Sm1 * inv_S * inv_S;
+    p.inv_f2 = frcp(f2);
+    return p;
+}
+
+// The extreme eigenvalues along one axis: ud the reduced flux along it, a2
+// its square, o2 the sum of the other two squares.
+__device__ __forceinline__ void m1_axis(const SpeedPrep &p, float ud, float a2, float o2,
+                                        float &lm, float &lp)
+{
+    if (p.iso) {
+        lm = -0.5773502691896258f;
+        lp = 0.5773502691896258f;
+        return;
+    }
+    const float r = fsqrt(p.pref * (p.Sm1 * (1.0f + a2 * p.inv_f2) + o2 * p.inv_f2));
+    const float B = ud * p.Q;
+    lm = 0.5f * (B - r);
+    lp = 0.5f * (B + r);
+}
+
+__device__ __forceinline__ Speeds m1_speeds(float N, float Fx, float Fy, float Fz, float inv_c,
+                                            double c_d)
+{
+    const SpeedPrep p = m1_speed_prep(N, Fx, Fy, Fz, inv_c, c_d);
+    Speeds s;
+    m1_axis(p, p.ux, p.x2, p.y2 + p.z2, s.xm, s.xp);
+    m1_axis(p, p.uy, p.y2, p.x2 + p.z2, s.ym, s.yp);
+    m1_axis(p, p.uz, p.z2, p.x2 + p.y2, s.zm, s.zp);
     return s;
 }
 

@@ -229,10 +229,14 @@ void m1_step_kernel(StepArgs A)
     Cell4 cur = load4(A, col + uint32_t(z0) * plane, mx.sign, my.sign, 1.0f);
     Press pcur = closure(cur.N, cur.Fx, cur.Fy, cur.Fz, A.inv_c);
     // HLL signal speeds travel with the z window like the pressure tensors
-    Speeds lprv{}, lcur{};
+    // The z face below plane z is the face above plane z-1: its HLL weights
+    // are carried from one plane to the next.
+    Speeds lcur{};
+    HllW wz_prev{};
     if constexpr (HLL) {
-        lprv = m1_speeds(prv.N, prv.Fx, prv.Fy, prv.Fz, A.inv_c, A.c_d);
+        const Speeds lprv = m1_speeds(prv.N, prv.Fx, prv.Fy, prv.Fz, A.inv_c, A.c_d);
         lcur = m1_speeds(cur.N, cur.Fx, cur.Fy, cur.Fz, A.inv_c, A.c_d);
+        wz_prev = hll_weights(lprv.zm, lprv.zp, lcur.zm, lcur.zp, A.c);
     }
     // Prefetched planes live in two register sets that swap roles every
     // plane: the loop below is unrolled by two so that a value loaded for
@@ -317,11 +321,19 @@ void m1_step_kernel(StepArgs A)
             sPxz[bi][hsy][hsx] = ph.xz;
             sPyz[bi][hsy][hsx] = ph.yz;
             if constexpr (HLL) {
-                const Speeds lh = m1_speeds(hal.N, hal.Fx, hal.Fy, hal.Fz, A.inv_c, A.c_d);
-                sLxm[bi][hsy][hsx] = lh.xm;
-                sLxp[bi][hsy][hsx] = lh.xp;
-                sLym[bi][hsy][hsx] = lh.ym;
-                sLyp[bi][hsy][hsx] = lh.yp;
+                // a halo row is read for its y speeds only, a halo column for
+                // its x speeds (whole wavefronts take the same branch)
+                const SpeedPrep ph2 = m1_speed_prep(hal.N, hal.Fx, hal.Fy, hal.Fz, A.inv_c, A.c_d);
+                float lm, lp;
+                if (tid < 2 * TX) {
+                    m1_axis(ph2, ph2.uy, ph2.y2, ph2.x2 + ph2.z2, lm, lp);
+                    sLym[bi][hsy][hsx] = lm;
+                    sLyp[bi][hsy][hsx] = lp;
+                } else {
+                    m1_axis(ph2, ph2.ux, ph2.x2, ph2.y2 + ph2.z2, lm, lp);
+                    sLxm[bi][hsy][hsx] = lm;
+                    sLxp[bi][hsy][hsx] = lp;
+                }
             }
         }
         __syncthreads();
@@ -368,8 +380,9 @@ void m1_step_kernel(StepArgs A)
             const HllW wxp = hll_weights(lcur.xm, lcur.xp, lxmR, lxpR, c);
             const HllW wym = hll_weights(lymD, lypD, lcur.ym, lcur.yp, c);
             const HllW wyp = hll_weights(lcur.ym, lcur.yp, lymU, lypU, c);
-            const HllW wzm = hll_weights(lprv.zm, lprv.zp, lcur.zm, lcur.zp, c);
+            const HllW wzm = wz_prev;
             const HllW wzp = hll_weights(lcur.zm, lcur.zp, lnxt.zm, lnxt.zp, c);
+            wz_prev = wzp;
             auto face = [](const HllW &w, float gL, float gR, float uL, float uR) {
                 return w.wl * gL + w.wr * gR + w.wd * (uR - uL);
             };
@@ -597,7 +610,6 @@ void m1_step_kernel(StepArgs A)
         cur = nxt;
         pcur = pnxt;
         if constexpr (HLL) {
-            lprv = lcur;
             lcur = lnxt;
         }
     };

@@ -2,8 +2,9 @@
  * m1_oracle.c -- FP64 CPU reference of the explicit M1 transport step and
  * the per-cell hydrogen chemistry operator.  TEST INFRASTRUCTURE ONLY (see
  * m1_oracle.h): plain loops, every quantity from its definition, no tiling,
- * no fusion beyond what the method itself states.  Parity unpinned: the
- * adaptive sub-cycle time scale (marked where it is defined).  OpenMP only splits the
+ * no fusion beyond what the method itself states.  The adaptive sub-cycle
+ * time scale is a reading (the paper states no rule), pinned by closed
+ * forms of its consequences (marked where it is defined).  OpenMP only splits the
  * independent per-cell loops; every tally is summed per z-plane and then
  * over planes in a fixed order, so results do not depend on thread count.
  */
@@ -147,9 +148,11 @@ static double cooling(const double r[6], double nHII, double nHI, double C_R)
  * internal-energy times, each against the GROSS rate of change (creation
  * plus destruction, heating plus cooling).  Against the net rate the time
  * scale would be ill-conditioned near equilibrium, where the net rate is a
- * small difference of large terms.  Parity unpinned: the paper states no
- * sub-cycling rule (the adaptive mode's convergence to the fixed-step limit
- * is what the tests check). */
+ * small difference of large terms.  The paper states no sub-cycling rule;
+ * the tests pin this one by closed forms: the sub-cycle count of linear
+ * recombination growth, ceil(ln(1 + alpha nH dt / xHI0) / ln(1 + eps)), and
+ * at coronal equilibrium, where the net rate vanishes and the gross rate
+ * sets the count. */
 double orc_chem_timescale(const orc_params *p, double nH, double N,
                           double xHI, double T)
 {

@@ -18,6 +18,7 @@ the sub-cycled hydrogen chemistry, the cooling and the gray constants).
     number of sub-cycles grows;
   * adaptive sub-cycling converges to the fine fixed-step answer."""
 
+import math
 import os
 
 import numpy as np
@@ -175,6 +176,45 @@ def test_adaptive_converges_to_fine_fixed(orc):
         assert out[5] > 1
     assert errs[2] < errs[0]
     assert errs[2] < 2e-2
+
+
+@pytest.mark.parametrize("ratio", [5.0, 50.0, 500.0])
+def test_adaptive_count_for_linear_recombination_growth(orc, ratio):
+    # Isothermal ionised gas without photons at 100 K (no collisional
+    # ionisation): dxHI/dt = alpha nH (1 - xHI)^2 ~ alpha nH while xHI << 1,
+    # so the time over which xHI changes by its own size is xHI/(alpha nH),
+    # and sub-steps of eps times it multiply xHI by (1 + eps) each: after k
+    # of them t_k = xHI0 ((1 + eps)^k - 1) / (alpha nH).  The step of
+    # length dt therefore takes ceil(ln(1 + alpha nH dt / xHI0) / ln(1 + eps))
+    # sub-cycles.
+    eps, nH, x0, T = 0.1, 1e-3, 1e-6, 100.0
+    alpha = orc.rates(T)[0]
+    assert orc.rates(T)[1] == 0.0
+    dt = ratio * x0 / (alpha * nH)
+    out = orc.chem_cell(params(orc, "ISOTHERMAL", "ADAPTIVE", eps), dt, 100000, nH, 0.0,
+                        [0, 0, 0], x0, T)
+    assert out[5] == math.ceil(math.log(1.0 + ratio) / math.log(1.0 + eps))
+    assert out[2] == pytest.approx(x0 * (1.0 + ratio), rel=1e-2)
+
+
+@pytest.mark.parametrize("T", [3e4, 1e5, 3e5])
+def test_adaptive_count_at_coronal_equilibrium(orc, T):
+    # At collisional-ionisation equilibrium (no photons, T held) recombination
+    # creates neutral hydrogen as fast as collisions destroy it: the net rate
+    # is zero, each gross term is alpha nH x^2 (x = 1 - xHI, xHI = alpha /
+    # (alpha + beta)).  The state does not move, and a controller on the
+    # gross rate takes sub-steps of eps xHI / (2 alpha nH x^2) throughout:
+    # ceil(dt / that) sub-cycles (one on the net rate).
+    eps, nH = 0.1, 1e-3
+    a, b = orc.rates(T)[:2]
+    xe = a / (a + b)
+    x = 1.0 - xe
+    h = eps * xe / (2.0 * a * nH * x * x)
+    dt = 37.3 * h
+    out = orc.chem_cell(params(orc, "ISOTHERMAL", "ADAPTIVE", eps), dt, 100000, nH, 0.0,
+                        [0, 0, 0], xe, T)
+    assert out[5] == math.ceil(dt / h)
+    assert out[2] == pytest.approx(xe, rel=1e-12)
 
 
 def test_adaptive_cap_and_time_coverage(orc):

@@ -9,6 +9,8 @@ matrix-core kernels against the FP64 references:
     its loss;
   * rt_mlp_adam against the FP64 Adam step."""
 
+import math
+
 import numpy as np
 import pytest
 import torch
@@ -149,3 +151,40 @@ def test_mlp_adam_matches_reference():
     # of 1e-3) bounds the absolute error where they cancel
     assert np.allclose(tm1.cpu().numpy(), rm, rtol=1e-5, atol=1e-9)
     assert np.allclose(tm2.cpu().numpy(), rv, rtol=1e-5, atol=1e-14)
+
+
+@pytest.mark.parametrize("prec", ["FP32", "MIXED"])
+def test_chem_apply_subcycle_counts_closed_forms(prec):
+    # The adaptive controller on the device against the closed forms of its
+    # consequences (isothermal, no photons): linear recombination growth of
+    # an ionised cell at 100 K takes ceil(ln(1 + alpha nH dt / xHI0) /
+    # ln(1 + eps)) sub-cycles; a cell at coronal equilibrium takes
+    # ceil(dt / h) with h = eps xHI / (2 alpha nH x^2) (the gross rate).
+    # FP64 (mixed form, xHI below its threshold) exactly; FP32 within one.
+    eps, nH = 0.1, 1e-3
+    a100 = oracle.rates(100.0)[0]
+    rows, expect = [], []
+    for ratio in (5.0, 50.0, 500.0):
+        x0 = 1e-6
+        rows.append((nH, 0.0, x0, 100.0, ratio * x0 / (a100 * nH)))
+        expect.append(math.ceil(math.log(1.0 + ratio) / math.log(1.0 + eps)))
+    for T in (3e4, 1e5):
+        a, b = oracle.rates(T)[:2]
+        xe = a / (a + b)
+        h = eps * xe / (2.0 * a * nH * (1.0 - xe) ** 2)
+        rows.append((nH, 0.0, xe, T, 37.3 * h))
+        expect.append(math.ceil(37.3))
+    cols = [torch.tensor(np.array(c, dtype=np.float32), device=DEV) for c in zip(*rows)]
+    nc = torch.zeros(len(rows), dtype=torch.int32, device=DEV)
+    p = rt.make_params((1, 1, 1), 1e21, chem=rt.CHEM_ISOTHERMAL, prec=getattr(rt, "PREC_" + prec),
+                       sub=rt.SUB_ADAPTIVE, sub_eps=eps)
+    rt.check(rt.rt_chem_apply(p, cols[0], cols[1], cols[2], cols[3], cols[4], 4096, nc),
+             "rt_chem_apply")
+    torch.cuda.synchronize()
+    got = nc.cpu().numpy()
+    print(f"{prec}: sub-cycles {got.tolist()} against the closed forms {expect}", flush=True)
+    for g, e, r in zip(got, expect, rows):
+        if prec == "MIXED" and r[2] < 1e-3:
+            assert g == e, (g, e, r)
+        else:
+            assert abs(int(g) - e) <= 1, (g, e, r)

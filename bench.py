@@ -489,7 +489,7 @@ def main():
                          "256^3 run and timing its forms against the exact ones on the "
                          "same 1024^3 state")
     ap.add_argument("--surrogate-pairs", type=int, default=10_000_000)
-    ap.add_argument("--surrogate-steps", type=int, default=20000)
+    ap.add_argument("--surrogate-steps", type=int, default=80000)
     ap.add_argument("--label-cap", type=int, default=1024,
                     help="sub-cycle cap of the exact adaptive operator that labels the "
                          "surrogate's training pairs")

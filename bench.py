@@ -423,8 +423,9 @@ def sources_leg(G, w, nH_dev, n: int = 1_000_000, reps: int = 3):
 
 def stream_ceiling(dev, n: int = 1 << 30, reps: int = 10):
     """GB/s of the step's stream mix (7 float arrays of n read, 6 written)
-    and of a 1-read/1-write copy, on plain grid-stride kernels, for a few
-    grid sizes; the step kernel's traffic is compared with the best."""
+    on plain grid-stride kernels for a few grid sizes and in the step
+    kernel's tile-marching order, and of a device copy; the step kernel's
+    rate is compared with them."""
     import torch
 
     from paper_1004_2503_amd import rt
@@ -440,6 +441,19 @@ def stream_ceiling(dev, n: int = 1 << 30, reps: int = 10):
             rows.append({"mix": name, "blocks": blocks, "ms": ms, "GBs": gbs})
             print(f"# {name}, {blocks} blocks: {ms:.3f} ms, {gbs:.1f} GB/s", file=sys.stderr,
                   flush=True)
+    # the same mix in the step kernel's tile-marching order (64 x 16 tiles,
+    # 128-plane chunks, one block per compute unit) on a cubic grid
+    side = round(n ** (1.0 / 3.0))
+    march = None
+    if side ** 3 == n and side % 128 == 0:
+        rc, ms = rt.rt_march_probe(arr[:7], arr[7:13], (side,) * 3, reps)
+        rt.check(rc, "rt_march_probe")
+        march = 52 * n / (ms * 1e-3) / 1e9
+        rows.append({"mix": "7 read + 6 write in the step's tile-marching order",
+                     "blocks": (side // 64) * (side // 16) * (side // 128), "ms": ms,
+                     "GBs": march})
+        print(f"# tile-marching order, {side}^3: {ms:.3f} ms, {march:.1f} GB/s",
+              file=sys.stderr, flush=True)
     # a device copy of 4 GiB (torch's copy_) for reference
     src, dst = arr[0], arr[7]
     dst.copy_(src)
@@ -451,8 +465,9 @@ def stream_ceiling(dev, n: int = 1 << 30, reps: int = 10):
     ms = (time.perf_counter() - t0) / reps * 1e3
     rows.append({"mix": "device copy (torch copy_)", "blocks": None, "ms": ms,
                  "GBs": 8 * n / (ms * 1e-3) / 1e9})
-    best = max(r["GBs"] for r in rows if r["mix"].startswith("7 read + 6"))
-    return {"stream_ceiling": rows, "best_step_mix_GBs": best, "n_floats_per_array": n,
+    best = max(r["GBs"] for r in rows if r["mix"].startswith("7 read + 6 write (the step"))
+    return {"stream_ceiling": rows, "best_step_mix_GBs": best, "tile_march_GBs": march,
+            "n_floats_per_array": n,
             "reps": reps}
 
 

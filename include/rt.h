@@ -502,6 +502,19 @@ int rt_mlp_grad_noalloc(int32_t grad_blocks, const float *theta, const float *X,
 int rt_stream_probe(const float *const *in, int32_t nin, float *const *out, int32_t nout,
                     int64_t n, int32_t blocks, int32_t reps, double *ms, void *hip_stream);
 
+/* The same 7-read / 6-write mix in the LF step kernel's access order: 64 x
+ * 16 tiles of 1024 threads, one per block and one block per compute unit
+ * (96 KiB of LDS each), march 128 planes in z with the next plane's loads
+ * in flight and one barrier per plane, over an nx x ny x nz grid (x
+ * fastest; nx a multiple of 64, ny of 16, nz of 128, else RT_E_ARG) of
+ * in[0..6] (read) and out[0..5] (written, non-temporal stores); no stencil,
+ * halo, sources or chemistry.  One warm-up launch, then reps launches timed
+ * with HIP events on hip_stream; *ms receives the average launch time, in
+ * which 52 bytes per cell move.  Arrays are caller-owned, nx ny nz floats
+ * each, and must not alias.  Waits for the stream. */
+int rt_march_probe(const float *const *in, float *const *out, int32_t nx, int32_t ny,
+                   int32_t nz, int32_t reps, double *ms, void *hip_stream);
+
 /* Static string naming a return code. */
 const char *rt_strerror(int code);
 

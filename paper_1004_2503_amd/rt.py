@@ -548,7 +548,7 @@ def equilibrium_xhi(params: rt_params, model: int, gamma0: float, n_star: float,
     return out
 
 
-EXPORTS += ["rt_gamma_plateau", "rt_stream_probe"]
+EXPORTS += ["rt_gamma_plateau", "rt_stream_probe", "rt_march_probe"]
 
 
 def rt_stream_probe(ins, outs, blocks: int, reps: int, stream: int | None = None):
@@ -565,6 +565,25 @@ def rt_stream_probe(ins, outs, blocks: int, reps: int, stream: int | None = None
     ms = ctypes.c_double()
     rc = L.rt_stream_probe(a, len(ins), b, len(outs), int(ins[0].numel()), int(blocks),
                            int(reps), ctypes.byref(ms), vp(stream or 0))
+    return rc, ms.value
+
+
+def rt_march_probe(ins, outs, shape, reps: int, stream: int | None = None):
+    """ins: 7, outs: 6 float32 device tensors of nz*ny*nx elements; shape =
+    (nz, ny, nx).  Returns (code, average ms per launch)."""
+    L = lib()
+    vp = ctypes.c_void_p
+    L.rt_march_probe.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.c_int32,
+                                 ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                 ctypes.POINTER(ctypes.c_double), vp]
+    L.rt_march_probe.restype = ctypes.c_int
+    nz, ny, nx = (int(v) for v in shape)
+    if len(ins) != 7 or len(outs) != 6 or any(t.numel() != nx * ny * nz for t in ins + outs):
+        return RT_E_ARG, 0.0
+    a = (vp * 7)(*[t.data_ptr() for t in ins])
+    b = (vp * 6)(*[t.data_ptr() for t in outs])
+    ms = ctypes.c_double()
+    rc = L.rt_march_probe(a, b, nx, ny, nz, int(reps), ctypes.byref(ms), vp(stream or 0))
     return rc, ms.value
 
 

@@ -126,6 +126,7 @@ constexpr int GRAD_WAVES = 4, GRAD_THREADS = 64 * GRAD_WAVES;
 // small gradients per wavefront: W1 (64 x 5), b1, b2, b3, W4 (2 x 64), b4
 constexpr int GS_W1 = 0, GS_B1 = 320, GS_B2 = 384, GS_B3 = 448, GS_W4 = 512, GS_B4 = 640,
               GS_N = 642, GS_PAD = 644;
+static_assert(GS_PAD >= GS_N && GS_PAD % 4 == 0, "small-gradient area");
 
 struct GradWaveLds {
     __bf16 Gs[64][32];     // dL/dZ of a layer (neurons x samples), bf16

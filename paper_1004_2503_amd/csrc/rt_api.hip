@@ -55,6 +55,7 @@ struct Ev {
 // Tiles of one form of the step and the point sources binned into them.
 struct TileSet {
     int ty = 0, nty = 0, nblocks = 0;
+    int zc = 0, nzc = 0;            // planes per z chunk, chunks
     int32_t *d_src_ptr = nullptr;   // per tile [start, end) into key/rate
     int32_t *d_src_key = nullptr;
     float *d_src_rate = nullptr;
@@ -65,14 +66,16 @@ struct rt_ctx {
     rt_fields f;
     hipStream_t stream = nullptr;
     int cur = 0;
-    int ntx = 0, nzc = 0, zc = 0;
+    int ntx = 0;
     uint32_t ncell = 0;
-    TileSet geo[2];   // 0: LF forms (TY_LF rows), 1: HLL and surrogate forms (TY rows)
+    // 0: LF forms on large grids (TY_LF rows), 1: LF forms on small grids
+    // (TY rows), 2: the HLL form (TY_HLL rows)
+    TileSet geo[3];
     // the current source set on the host; each tile set's lists are built
     // when a step first needs them
     std::vector<int32_t> src_ijk;
     std::vector<double> src_ndot;
-    bool geo_ready[2] = {true, true};   // the empty set at rt_init
+    bool geo_ready[3] = {true, true, true};   // the empty set at rt_init
     int64_t nsrc = 0;
     double ndot_total = 0.0;
     double *d_part = nullptr;
@@ -190,11 +193,11 @@ extern "C" const char *rt_strerror(int code)
 }
 
 // Planes per block along z: the longest chunk (at most the grid's depth),
-// halved while the grid has fewer than ZC_BLOCKS tiles of 64 x TY cells.
+// halved while the grid has fewer than ZC_BLOCKS tiles of 64 x ty cells.
 // Each block marches its chunk serially, so on small grids long chunks
 // leave most compute units idle; short chunks re-read more z-halo planes
 // (two per chunk), which the large grids avoid.
-static int z_chunk(int ntx, int ny, int nz)
+static int z_chunk(int ntx, int ny, int nz, int ty)
 {
     // the largest grids take 128-plane chunks as long as they still have
     // ZC_LONG_BLOCKS of them (32 per compute unit): fewer z-halo planes,
@@ -205,7 +208,7 @@ static int z_chunk(int ntx, int ny, int nz)
     if (nz >= ZC_LONG && layer * ((nz + ZC_LONG - 1) / ZC_LONG) >= ZC_LONG_BLOCKS)
         return ZC_LONG;
     int zc = std::min(ZC_DEFAULT, nz);
-    const int64_t cols = int64_t(ntx) * ((ny + TY - 1) / TY);
+    const int64_t cols = int64_t(ntx) * ((ny + ty - 1) / ty);
     while (zc / 2 >= ZC_MIN && cols * ((nz + zc - 1) / zc) < ZC_BLOCKS) zc /= 2;
     return zc;
 }
@@ -257,13 +260,14 @@ extern "C" int rt_init(const rt_params *params, const rt_fields *fields, void *h
     c->stream = static_cast<hipStream_t>(hip_stream);
     c->ncell = uint32_t(params->nx) * uint32_t(params->ny) * uint32_t(params->nz);
     c->ntx = (params->nx + TX - 1) / TX;
-    c->zc = z_chunk(c->ntx, params->ny, params->nz);
-    c->nzc = (params->nz + c->zc - 1) / c->zc;
-    for (int gi = 0; gi < 2; ++gi) {
+    for (int gi = 0; gi < 3; ++gi) {
         TileSet &g = c->geo[gi];
-        g.ty = gi == 0 ? TY_LF : TY;
+        g.ty = gi == 0 ? TY_LF : (gi == 1 ? TY : TY_HLL);
         g.nty = (params->ny + g.ty - 1) / g.ty;
-        const int64_t nb = int64_t(c->ntx) * g.nty * c->nzc;
+        // both LF tile sets chunk z as the small tiles need
+        g.zc = z_chunk(c->ntx, params->ny, params->nz, gi == 2 ? TY_HLL : TY);
+        g.nzc = (params->nz + g.zc - 1) / g.zc;
+        const int64_t nb = int64_t(c->ntx) * g.nty * g.nzc;
         if (nb > (int64_t(1) << 30)) {
             delete c;
             return RT_E_ARG;
@@ -278,7 +282,8 @@ extern "C" int rt_init(const rt_params *params, const rt_fields *fields, void *h
     c->gwords = int((mask_groups(c->nwords) + 63) / 64);
     // partial rows: a step writes one per block of whichever tile set it
     // runs on, then the deferred chemistry nb2 more after them
-    c->npart = std::max(std::max(c->geo[0].nblocks, c->geo[1].nblocks) + 2 * c->nb2,
+    c->npart = std::max(std::max(std::max(c->geo[0].nblocks, c->geo[1].nblocks),
+                                 c->geo[2].nblocks) + 2 * c->nb2,
                         std::max(state_sums_blocks(c->ncell),
                                  (2 * plateau_blocks(c->ncell) + NRED - 1) / NRED));
     if (defer) {
@@ -296,6 +301,8 @@ extern "C" int rt_init(const rt_params *params, const rt_fields *fields, void *h
             hipSuccess ||
         hipMalloc(&c->geo[1].d_src_ptr, size_t(c->geo[1].nblocks + 1) * sizeof(int32_t)) !=
             hipSuccess ||
+        hipMalloc(&c->geo[2].d_src_ptr, size_t(c->geo[2].nblocks + 1) * sizeof(int32_t)) !=
+            hipSuccess ||
         hipMalloc(&c->d_sink, NTHREADS_MAX * sizeof(float)) != hipSuccess ||
         hipMalloc(&c->d_hcount, RT_HIST_MAX_BINS * sizeof(unsigned long long)) != hipSuccess ||
         hipMalloc(&c->d_hsum, HSUM_DOUBLES * sizeof(double)) != hipSuccess ||
@@ -308,6 +315,8 @@ extern "C" int rt_init(const rt_params *params, const rt_fields *fields, void *h
     if (hipMemsetAsync(c->geo[0].d_src_ptr, 0, size_t(c->geo[0].nblocks + 1) * sizeof(int32_t),
                        c->stream) != hipSuccess ||
         hipMemsetAsync(c->geo[1].d_src_ptr, 0, size_t(c->geo[1].nblocks + 1) * sizeof(int32_t),
+                       c->stream) != hipSuccess ||
+        hipMemsetAsync(c->geo[2].d_src_ptr, 0, size_t(c->geo[2].nblocks + 1) * sizeof(int32_t),
                        c->stream) != hipSuccess ||
         hipMemsetAsync(c->d_acc, 0, ACC_SIZE * sizeof(double), c->stream) != hipSuccess) {
         free_ctx(c);
@@ -432,15 +441,15 @@ Lists bin_sources(const rt_ctx *c, const TileSet &g, int64_t n, const int32_t *i
     // two stable counting sorts (by cell within the tile, then by tile) give
     // the (tile, cell) order with equal cells kept in input order, so
     // duplicates are summed in input order
-    const int64_t nkeys = int64_t(c->zc) * nt;
+    const int64_t nkeys = int64_t(g.zc) * nt;
     std::vector<int32_t> tile_of(static_cast<size_t>(n)), key_of(static_cast<size_t>(n));
     std::vector<int64_t> kcount(static_cast<size_t>(nkeys) + 1, 0);
     std::vector<int64_t> tcount(static_cast<size_t>(g.nblocks) + 1, 0);
     for (int64_t s = 0; s < n; ++s) {
         const int32_t i = ijk[3 * s], j = ijk[3 * s + 1], k = ijk[3 * s + 2];
-        const int itx = i / TX, ity = j / g.ty, izc = k / c->zc;
+        const int itx = i / TX, ity = j / g.ty, izc = k / g.zc;
         const int tile = (izc * g.nty + ity) * c->ntx + itx;
-        const int key = (k - izc * c->zc) * nt + (j - ity * g.ty) * TX + (i - itx * TX);
+        const int key = (k - izc * g.zc) * nt + (j - ity * g.ty) * TX + (i - itx * TX);
         tile_of[size_t(s)] = tile;
         key_of[size_t(s)] = key;
         kcount[size_t(key) + 1] += 1;
@@ -481,11 +490,11 @@ Lists bin_sources(const rt_ctx *c, const TileSet &g, int64_t n, const int32_t *i
 
 // Which tile set the next step uses: the LF forms take the 64 x TY_LF
 // tiles when there are enough of them to fill the chip (four per compute
-// unit); small grids and HLL take the 64 x TY ones.
+// unit), the 64 x TY ones on small grids; HLL takes the 64 x TY_HLL ones.
 static int tile_set(const rt_ctx *c)
 {
-    const bool lf = c->p.flux == RT_FLUX_LF;
-    return (lf && c->geo[0].nblocks >= BIG_MIN_BLOCKS) ? 0 : 1;
+    if (c->p.flux == RT_FLUX_HLL) return 2;
+    return c->geo[0].nblocks >= BIG_MIN_BLOCKS ? 0 : 1;
 }
 
 // Build tile set g's lists from the host copy of the sources.  New lists are
@@ -554,7 +563,8 @@ int rtk::inject_host(rt_ctx *c, int64_t n, const int32_t *ijk, const double *ndo
         c->src_ndot.swap(old_ndot);
         return rc;
     }
-    c->geo_ready[1 - g] = false;
+    for (int o = 0; o < 3; ++o)
+        if (o != g) c->geo_ready[o] = false;
     c->nsrc = int64_t(c->src_ndot.size());
     c->ndot_total = total;
     return RT_OK;
@@ -624,8 +634,8 @@ static void fill_args(const rt_ctx *c, double dt, int nsub, StepArgs &a)
     a.plane = uint32_t(p.nx) * uint32_t(p.ny);
     a.ntx = c->ntx;
     a.nty = g.nty;
-    a.nzc = c->nzc;
-    a.zc = c->zc;
+    a.nzc = g.nzc;
+    a.zc = g.zc;
     a.nblocks = g.nblocks;
     for (int f = 0; f < 6; ++f) a.bc[f] = p.bc[f];
     a.chem = p.chem;

@@ -12,21 +12,29 @@ namespace rtk {
 // Tiles of the fused step kernel: one wavefront per x-row of 64 cells, the
 // block marching ZC planes along z.  On large grids the plain LF forms use
 // TY_LF rows per block (64 TY_LF threads, at most 128 VGPRs each: more rows
-// share each halo row); small grids (too few such tiles to fill the chip)
-// and the HLL and surrogate forms, which need more registers per thread,
-// use TY rows (64 TY threads).
+// share each halo row); on small grids (too few such tiles to fill the
+// chip) they use TY rows (64 TY threads).  The HLL form, which needs more
+// registers per thread, uses TY_HLL rows: 768 threads at up to 168 VGPRs,
+// three wavefronts per SIMD (two with 64 x 8 tiles at its 187 VGPRs).
 #ifndef RT_M1_TY
 #define RT_M1_TY 8
 #endif
 #ifndef RT_M1_TY_LF
 #define RT_M1_TY_LF 16
 #endif
+#ifndef RT_M1_TY_HLL
+#define RT_M1_TY_HLL 12
+#endif
 constexpr int TX = 64;
 constexpr int TY = RT_M1_TY;
 constexpr int NTHREADS = TX * TY;
 constexpr int TY_LF = RT_M1_TY_LF;
 constexpr int NTHREADS_LF = TX * TY_LF;
-constexpr int NTHREADS_MAX = NTHREADS > NTHREADS_LF ? NTHREADS : NTHREADS_LF;
+constexpr int TY_HLL = RT_M1_TY_HLL;
+constexpr int NTHREADS_HLL = TX * TY_HLL;
+constexpr int NTHREADS_MAX = NTHREADS_LF > (NTHREADS > NTHREADS_HLL ? NTHREADS : NTHREADS_HLL)
+                                 ? NTHREADS_LF
+                                 : (NTHREADS > NTHREADS_HLL ? NTHREADS : NTHREADS_HLL);
 constexpr int SRC_LDS = 256;   // sources staged in LDS per refill
 
 // Per-block partial sums written by the step kernel (all FP64).

@@ -108,21 +108,29 @@ __device__ __forceinline__ Cell4 load4(const StepArgs &A, uint32_t i, float sx, 
 
 // ------------------------------------------------------ fused step kernel
 // One block per CU.  On large grids the LF forms take 64 x 16 tiles (BIG):
-// 1024 threads at up to 128 VGPRs, four wavefronts per SIMD.  Otherwise, and
-// for the HLL form, 64 x 8 tiles: 512 threads at up to 256 VGPRs.
+// 1024 threads at up to 128 VGPRs, four wavefronts per SIMD; on small grids
+// 64 x 8 tiles: 512 threads at up to 256 VGPRs.  The HLL form takes 64 x 12
+// tiles: 768 threads at up to 168 VGPRs, three wavefronts per SIMD (measured
+// 14.63 against 15.59 ms per 1024^3 step on 64 x 8 tiles at 187 VGPRs, 2.02
+// against 2.33 ms at 512^3; the small LF form was 14% slower at 128^3 on
+// 64 x 12 tiles, which leave fewer blocks).
 #ifndef RT_M1_MINW
 #define RT_M1_MINW 2
 #endif
 #ifndef RT_M1_MINW_LF
 #define RT_M1_MINW_LF 4
 #endif
+#ifndef RT_M1_MINW_HLL
+#define RT_M1_MINW_HLL 3
+#endif
 
 template <bool HLL, bool BIG>
-__global__ __launch_bounds__(BIG ? NTHREADS_LF : NTHREADS, BIG ? RT_M1_MINW_LF : RT_M1_MINW)
+__global__ __launch_bounds__(BIG ? NTHREADS_LF : (HLL ? NTHREADS_HLL : NTHREADS),
+                             BIG ? RT_M1_MINW_LF : (HLL ? RT_M1_MINW_HLL : RT_M1_MINW))
 void m1_step_kernel(StepArgs A)
 {
     static_assert(!BIG || !HLL, "64 x 16 tiles: LF forms only");
-    constexpr int KTY = BIG ? TY_LF : TY;   // tile rows of this form
+    constexpr int KTY = BIG ? TY_LF : (HLL ? TY_HLL : TY);   // tile rows of this form
     constexpr int KNT = TX * KTY;           // its threads per block
     constexpr int SW = TX + 2;
     // Plane z's tile and halo, double-buffered by the parity of z: a plane
@@ -1343,7 +1351,7 @@ int state_sums_blocks(uint32_t ncell)
 
 hipError_t launch_step(const StepArgs &a, hipStream_t s)
 {
-    const dim3 g(a.nblocks), b(a.big ? NTHREADS_LF : NTHREADS);
+    const dim3 g(a.nblocks), b(a.big ? NTHREADS_LF : (a.hll ? NTHREADS_HLL : NTHREADS));
     if (a.hll)
         hipLaunchKernelGGL((m1_step_kernel<true, false>), g, b, 0, s, a);
     else if (a.big)

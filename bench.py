@@ -424,14 +424,37 @@ def sources_leg(G, w, nH_dev, n: int = 1_000_000, reps: int = 3):
 def stream_ceiling(dev, n: int = 1 << 30, reps: int = 10):
     """GB/s of the step's stream mix (7 float arrays of n read, 6 written)
     on plain grid-stride kernels for a few grid sizes and in the step
-    kernel's tile-marching order, and of a device copy; the step kernel's
-    rate is compared with them."""
+    kernel's tile-marching order, and of a device copy; the arrays are
+    placed as RTGrid places the step's fields (one allocation, 256-byte
+    stagger), and the tile-marching probe is repeated on separately
+    allocated arrays.  The step kernel's rate is compared with them."""
     import torch
 
     from paper_1004_2503_amd import rt
 
-    arr = [torch.zeros(n, dtype=torch.float32, device=dev) for _ in range(13)]
+    side = round(n ** (1.0 / 3.0))
+    cubic = side ** 3 == n and side % 128 == 0
+
+    def march_row(arr, label):
+        rc, ms = rt.rt_march_probe(arr[:7], arr[7:13], (side,) * 3, reps)
+        rt.check(rc, "rt_march_probe")
+        gbs = 52 * n / (ms * 1e-3) / 1e9
+        print(f"# tile-marching order, {side}^3, {label}: {ms:.3f} ms, {gbs:.1f} GB/s",
+              file=sys.stderr, flush=True)
+        return {"mix": f"7 read + 6 write in the step's tile-marching order, {label}",
+                "blocks": (side // 64) * (side // 16) * (side // 128), "ms": ms, "GBs": gbs}
+
     rows = []
+    march_separate = None
+    if cubic:
+        arr = [torch.zeros(n, dtype=torch.float32, device=dev) for _ in range(13)]
+        rows.append(march_row(arr, "13 separate allocations"))
+        march_separate = rows[-1]["GBs"]
+        del arr
+        torch.cuda.empty_cache()
+    stride = (n + 63) // 64 * 64 + rt.FIELD_STAGGER
+    slab = torch.zeros(stride * 12 + n, dtype=torch.float32, device=dev)
+    arr = [slab[k * stride:k * stride + n] for k in range(13)]
     for blocks in (4096, 16384, 65536):
         for name, nin, nout in (("7 read + 6 write (the step's mix)", 7, 6),
                                 ("7 read + 1 write", 7, 1)):
@@ -441,19 +464,10 @@ def stream_ceiling(dev, n: int = 1 << 30, reps: int = 10):
             rows.append({"mix": name, "blocks": blocks, "ms": ms, "GBs": gbs})
             print(f"# {name}, {blocks} blocks: {ms:.3f} ms, {gbs:.1f} GB/s", file=sys.stderr,
                   flush=True)
-    # the same mix in the step kernel's tile-marching order (64 x 16 tiles,
-    # 128-plane chunks, one block per compute unit) on a cubic grid
-    side = round(n ** (1.0 / 3.0))
     march = None
-    if side ** 3 == n and side % 128 == 0:
-        rc, ms = rt.rt_march_probe(arr[:7], arr[7:13], (side,) * 3, reps)
-        rt.check(rc, "rt_march_probe")
-        march = 52 * n / (ms * 1e-3) / 1e9
-        rows.append({"mix": "7 read + 6 write in the step's tile-marching order",
-                     "blocks": (side // 64) * (side // 16) * (side // 128), "ms": ms,
-                     "GBs": march})
-        print(f"# tile-marching order, {side}^3: {ms:.3f} ms, {march:.1f} GB/s",
-              file=sys.stderr, flush=True)
+    if cubic:
+        rows.append(march_row(arr, "one allocation, 256-byte stagger"))
+        march = rows[-1]["GBs"]
     # a device copy of 4 GiB (torch's copy_) for reference
     src, dst = arr[0], arr[7]
     dst.copy_(src)
@@ -467,8 +481,8 @@ def stream_ceiling(dev, n: int = 1 << 30, reps: int = 10):
                  "GBs": 8 * n / (ms * 1e-3) / 1e9})
     best = max(r["GBs"] for r in rows if r["mix"].startswith("7 read + 6 write (the step"))
     return {"stream_ceiling": rows, "best_step_mix_GBs": best, "tile_march_GBs": march,
-            "n_floats_per_array": n,
-            "reps": reps}
+            "tile_march_separate_GBs": march_separate, "n_floats_per_array": n,
+            "stagger_bytes": 4 * rt.FIELD_STAGGER, "reps": reps}
 
 
 def main():

@@ -85,7 +85,16 @@ typedef struct rt_ctx rt_ctx;
  * the initial state; every step reads buffer `cur` and writes buffer
  * 1 - cur (rt_current reports `cur`).  xHI and T are updated in place; nH is
  * read only.  All buffers hold nx*ny*nz floats, 256-byte alignment or
- * better recommended, and must not alias one another. */
+ * better recommended, and must not alias one another.
+ *
+ * Placement: a step streams all eleven buffers at the same cell index at
+ * once, so their relative offsets decide how the traffic spreads over the
+ * HBM channels.  Separate allocations of equal power-of-two-ish sizes tend
+ * to sit at large aligned distances from one another (on one MI355X the
+ * 1024^3 LF step took 12.2 ms on such fields); carving them from one
+ * allocation at a stride of the 256-byte-rounded field size plus 256 bytes,
+ * so that buffer k starts k * 256 bytes off that alignment, took 10.7 ms
+ * (the Python binding's RTGrid lays them out so). */
 typedef struct {
     float *N[2];
     float *Fx[2];

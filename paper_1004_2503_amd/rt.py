@@ -217,6 +217,10 @@ def make_params(shape, dx, bc=(BC_PERIODIC,) * 6, chem=CHEM_FULL, prec=PREC_FP32
                      float(sub_eps), float(xhi_fp64_thr), *cl)
 
 
+NFIELD_BUFFERS = 11      # N, Fx, Fy, Fz twice, xHI, T, nH
+FIELD_STAGGER = 64       # floats (256 bytes) between the fields' channel offsets
+
+
 class RTGrid:
     """Torch-owned device fields bound to one library context.
 
@@ -232,17 +236,30 @@ class RTGrid:
         self.shape = shape
         self.device = torch.device(device)
 
-        def dev(name, fill=0.0):
-            v = state.get(name)
-            if v is None:
-                return torch.full(shape, fill, dtype=torch.float32, device=self.device)
-            t = torch.as_tensor(v)
-            return t.to(device=self.device, dtype=torch.float32).reshape(shape).contiguous().clone()
+        # The eleven fields are views of one allocation, field k starting
+        # k * FIELD_STAGGER floats past a 256-byte-aligned stride, so that
+        # the streams of one cell index fall on different HBM channels.
+        ncell = shape[0] * shape[1] * shape[2]
+        stride = (ncell + 63) // 64 * 64 + FIELD_STAGGER
+        self._slab = torch.empty(stride * (NFIELD_BUFFERS - 1) + ncell, dtype=torch.float32,
+                                 device=self.device)
+        slots = iter(range(NFIELD_BUFFERS))
 
-        self.N = [dev("N"), torch.zeros(shape, dtype=torch.float32, device=self.device)]
-        self.Fx = [dev("Fx"), torch.zeros_like(self.N[1])]
-        self.Fy = [dev("Fy"), torch.zeros_like(self.N[1])]
-        self.Fz = [dev("Fz"), torch.zeros_like(self.N[1])]
+        def dev(name, fill=0.0):
+            k = next(slots)
+            t = self._slab[k * stride:k * stride + ncell].view(shape)
+            v = state.get(name) if name else None
+            if v is None:
+                t.fill_(fill)
+            else:
+                t.copy_(torch.as_tensor(v).to(device=self.device,
+                                              dtype=torch.float32).reshape(shape))
+            return t
+
+        self.N = [dev("N"), dev(None)]
+        self.Fx = [dev("Fx"), dev(None)]
+        self.Fy = [dev("Fy"), dev(None)]
+        self.Fz = [dev("Fz"), dev(None)]
         self.xHI = dev("xHI", 1.0)
         self.T = dev("T", 1e4)
         self.nH = dev("nH", 1e-3)

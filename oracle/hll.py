@@ -41,15 +41,19 @@ def _flux(U, d):
 
 
 def jacobian(N, w, d):
-    """(..., 4, 4) Jacobian dG_d/dU at U = (N, w)."""
-    U = np.concatenate([np.asarray(N, np.float64)[..., None],
-                        np.asarray(w, np.float64)], -1).astype(np.complex128)
-    h = 1e-30
+    """(..., 4, 4) Jacobian dG_d/dU at U = (N, w) (N > 0).  The complex step
+    is exact to rounding only while it is far below the state it perturbs:
+    it is taken relative to N (G is homogeneous of degree one in U, so the
+    Jacobian depends on the reduced flux alone), also for N near the empty
+    threshold of 1e-30."""
+    N = np.asarray(N, np.float64)
+    U = np.concatenate([N[..., None], np.asarray(w, np.float64)], -1).astype(np.complex128)
+    h = 1e-20 * N
     cols = []
     for k in range(4):
-        e = np.zeros(4, np.complex128)
-        e[k] = 1j * h
-        cols.append(_flux(U + e, d).imag / h)
+        e = np.zeros(U.shape, np.complex128)
+        e[..., k] = 1j * h
+        cols.append(_flux(U + e, d).imag / h[..., None])
     return np.stack(cols, -1)
 
 

@@ -94,6 +94,31 @@ def test_closed_form_of_the_extremes():
     assert np.allclose(lo, (B - r) / 2, atol=2e-8)
 
 
+def test_extremes_depend_on_the_reduced_flux_alone():
+    # G is homogeneous of degree one in (N, F), so its Jacobian, hence the
+    # signal speeds, depend on F/(cN) only: the same reduced fluxes at N
+    # from just above the empty threshold to 1e5 give the same extremes,
+    # against the closed form.  (A complex step of fixed size, comparable to
+    # N near 1e-30, broke this.)
+    rng = np.random.default_rng(5)
+    f = rng.uniform(1e-3, 1 - 1e-9, 300)
+    mu = rng.uniform(-1, 1, 300)
+    ref = extremes(f, mu)
+    S = np.sqrt(4 - 3 * f * f)
+    Sm1 = 3 * (1 - f * f) / (S + 1)
+    r = np.sqrt(8 * Sm1 * (Sm1 * (1 + mu * mu) + (1 - mu * mu)) / (3 * S * S))
+    B = mu * dchi(f)
+    assert np.allclose(ref[1], (B + r) / 2, atol=2e-8)
+    for N0 in (1.5e-30, 3e-29, 1e-12, 1e5):
+        F = np.zeros(f.shape + (3,))
+        F[..., 0] = f * mu
+        F[..., 1] = f * np.sqrt(np.clip(1 - mu * mu, 0, 1))
+        N = np.full(f.shape, N0)
+        lam = hll.eigen_extremes(N, *(C * N * F[..., k] for k in range(3)), C)
+        assert np.allclose(lam[:, 0], ref[0], atol=1e-9), N0
+        assert np.allclose(lam[:, 1], ref[1], atol=1e-9), N0
+
+
 def grid(orc, shape, flux, chem=None, bc=(0,) * 6):
     chem = orc.CHEM_OFF if chem is None else chem
     return orc.Grid(orc.make_params(shape, DX, bc=bc, chem=chem, flux=flux))

@@ -32,8 +32,10 @@ struct Press {
 // would leave the normal FP32 range.
 constexpr float N_TINY = 1e-30f;
 
+// P = D N, times ns (the HLL step keeps c^2 P, the physical flux of F,
+// so that no face multiplies by c^2 again; ns = 1 gives P itself)
 __device__ __forceinline__ Press closure(float N, float Fx, float Fy, float Fz,
-                                         float inv_c)
+                                         float inv_c, float ns = 1.0f)
 {
     Press P;
     if (!(N > N_TINY)) {
@@ -46,9 +48,10 @@ __device__ __forceinline__ Press closure(float N, float Fx, float Fy, float Fz,
     const float u2 = ux * ux + uy * uy + uz * uz;
     const float f2 = rmin(u2, 1.0f);
     const float chi = (3.0f + 4.0f * f2) * frcp(5.0f + 2.0f * fsqrt(4.0f - 3.0f * f2));
-    const float iso = 0.5f * (1.0f - chi) * N;
+    const float Ns = N * ns;
+    const float iso = 0.5f * (1.0f - chi) * Ns;
     // (3chi-1)/2 N n_i n_j with n = u/|u|; negligible below f^2 = 1e-30
-    const float w = (u2 > 1e-30f) ? 0.5f * (3.0f * chi - 1.0f) * N * frcp(u2) : 0.0f;
+    const float w = (u2 > 1e-30f) ? 0.5f * (3.0f * chi - 1.0f) * Ns * frcp(u2) : 0.0f;
     P.xx = iso + w * ux * ux;
     P.yy = iso + w * uy * uy;
     P.zz = iso + w * uz * uz;
@@ -97,13 +100,14 @@ __device__ __forceinline__ SpeedPrep m1_speed_prep(float N, float Fx, float Fy, 
     const float f2 = p.x2 + p.y2 + p.z2;
     if (!(f2 > 1e-20f)) return p;
     p.iso = false;
-    // 1 - f^2 = ((cN)^2 - |F|^2) / (cN)^2: the difference in FP64 (it cancels
-    // near free streaming), the quotient in FP32
+    // 1 - f^2 = ((cN)^2 - |F|^2) q^2 with q = 1/(cN): the difference (it
+    // cancels near free streaming) and the product (q^2 leaves the FP32
+    // range for N just above N_TINY) in FP64
     const double cn = double(N) * c_d;
-    const double cn2 = cn * cn;
     const double diff =
-        cn2 - (double(Fx) * double(Fx) + double(Fy) * double(Fy) + double(Fz) * double(Fz));
-    const float g2 = diff > 0.0 ? float(diff) * frcp(float(cn2)) : 0.0f;   // 1 - f^2
+        cn * cn - (double(Fx) * double(Fx) + double(Fy) * double(Fy) + double(Fz) * double(Fz));
+    const double qd = double(q);
+    const float g2 = diff > 0.0 ? float(diff * (qd * qd)) : 0.0f;
     const float fs = 1.0f - g2;
     const float S = fsqrt(1.0f + 3.0f * g2);
     const float Sp1 = S + 1.0f;
@@ -137,6 +141,77 @@ __device__ __forceinline__ void m1_axis(const SpeedPrep &p, float ud, float a2, 
     lp = 0.5f * (B + r);
 }
 
+// The HLL form needs both the pressure (times ns) and the speed inputs of
+// a cell: one pass shares 1/N, the reduced flux, 1/f^2 and sqrt(4 - 3 f^2)
+// (= sqrt(1 + 3 (1 - f^2)), the speeds' S) between them.
+__device__ __forceinline__ void closure_and_prep(float N, float Fx, float Fy, float Fz,
+                                                 float inv_c, double c_d, float ns, Press &P,
+                                                 SpeedPrep &sp)
+{
+    sp = SpeedPrep{};
+    sp.iso = true;
+    if (!(N > N_TINY)) {
+        P.xx = P.yy = P.zz = P.xy = P.xz = P.yz = 0.0f;
+        return;
+    }
+    const float q = inv_c * frcp(N);
+    sp.ux = Fx * q;
+    sp.uy = Fy * q;
+    sp.uz = Fz * q;
+    sp.x2 = sp.ux * sp.ux;
+    sp.y2 = sp.uy * sp.uy;
+    sp.z2 = sp.uz * sp.uz;
+    const float f2 = sp.x2 + sp.y2 + sp.z2;
+    const float Ns = N * ns;
+    float S = 2.0f;   // sqrt(4 - 3 f^2) at f^2 <= 1e-20
+    float inv_f2 = 0.0f;
+    if (f2 > 1e-20f) {
+        sp.iso = false;
+        const double cn = double(N) * c_d;
+        const double diff = cn * cn - (double(Fx) * double(Fx) + double(Fy) * double(Fy) +
+                                       double(Fz) * double(Fz));
+        // 1 - f^2 = diff q^2, the product in FP64 (q^2 = 1/(cN)^2 leaves the
+        // FP32 range for N just above N_TINY)
+        const double qd = double(q);
+        const float g2 = diff > 0.0 ? float(diff * (qd * qd)) : 0.0f;
+        const float fs = 1.0f - g2;
+        S = fsqrt(1.0f + 3.0f * g2);
+        const float Sp1 = S + 1.0f;
+        const float D = 5.0f + 2.0f * S;
+        const float D2 = D * D;
+        const float R = frcp(S * Sp1 * D2);
+        const float inv_S = R * Sp1 * D2;
+        const float inv_Sp1 = R * S * D2;
+        const float inv_D2 = R * S * Sp1;
+        sp.Sm1 = 3.0f * g2 * inv_Sp1;
+        sp.Q = (8.0f * D + 6.0f * (3.0f + 4.0f * fs) * inv_S) * inv_D2;
+        sp.pref = (8.0f / 3.0f) * sp.Sm1 * inv_S * inv_S;
+        inv_f2 = frcp(f2);
+        sp.inv_f2 = inv_f2;
+    }
+    // Levermore chi from f^2 = 1 - g2 (clamped to 1) and the same S
+    const float f2c = rmin(f2, 1.0f);
+    const float chi = (3.0f + 4.0f * f2c) * frcp(5.0f + 2.0f * S);
+    const float iso = 0.5f * (1.0f - chi) * Ns;
+    // (the anisotropic part is of order f^2 N: nothing at f^2 <= 1e-20)
+    const float w = sp.iso ? 0.0f : 0.5f * (3.0f * chi - 1.0f) * Ns * inv_f2;
+    P.xx = iso + w * sp.x2;
+    P.yy = iso + w * sp.y2;
+    P.zz = iso + w * sp.z2;
+    P.xy = w * sp.ux * sp.uy;
+    P.xz = w * sp.ux * sp.uz;
+    P.yz = w * sp.uy * sp.uz;
+}
+
+__device__ __forceinline__ Speeds m1_axes(const SpeedPrep &p)
+{
+    Speeds s;
+    m1_axis(p, p.ux, p.x2, p.y2 + p.z2, s.xm, s.xp);
+    m1_axis(p, p.uy, p.y2, p.x2 + p.z2, s.ym, s.yp);
+    m1_axis(p, p.uz, p.z2, p.x2 + p.y2, s.zm, s.zp);
+    return s;
+}
+
 __device__ __forceinline__ Speeds m1_speeds(float N, float Fx, float Fy, float Fz, float inv_c,
                                             double c_d)
 {
@@ -157,6 +232,9 @@ struct HllW {
 
 __device__ __forceinline__ HllW hll_weights(float lmL, float lpL, float lmR, float lpR, float c)
 {
+    // (the factor c keeps a+ - a- out of the denormal range where both
+    // speeds nearly vanish, across a free-streaming beam: its reciprocal
+    // stays finite)
     const float ap = c * rmax(0.0f, rmax(lpL, lpR));
     const float am = c * rmin(0.0f, rmin(lmL, lmR));
     const float den = ap - am;

@@ -233,19 +233,28 @@ void m1_step_kernel(StepArgs A)
     // prologue: plane z0-1 (boundary image if outside), plane z0, plane z0+1
     const Map1 mzm = map_coord(z0 - 1, A.nz, A.bc[4], A.bc[5]);
     Cell4 prv = load4(A, col + uint32_t(mzm.idx) * plane, mx.sign, my.sign, mzm.sign);
-    Press pprv = closure(prv.N, prv.Fx, prv.Fy, prv.Fz, A.inv_c);
+    // the HLL form carries c^2 P (the flux of F along each axis) and takes
+    // the pressure and the signal speeds of a cell in one pass
+    const float pscale = HLL ? 2.0f * A.half_c2 : 1.0f;
+    auto press_speeds = [&](const Cell4 &u, Press &P, Speeds &L) {
+        if constexpr (HLL) {
+            SpeedPrep sp;
+            closure_and_prep(u.N, u.Fx, u.Fy, u.Fz, A.inv_c, A.c_d, pscale, P, sp);
+            L = m1_axes(sp);
+        } else {
+            P = closure(u.N, u.Fx, u.Fy, u.Fz, A.inv_c);
+        }
+    };
+    Press pprv, pcur;
+    Speeds lprv{}, lcur{};
+    press_speeds(prv, pprv, lprv);
     Cell4 cur = load4(A, col + uint32_t(z0) * plane, mx.sign, my.sign, 1.0f);
-    Press pcur = closure(cur.N, cur.Fx, cur.Fy, cur.Fz, A.inv_c);
-    // HLL signal speeds travel with the z window like the pressure tensors
+    press_speeds(cur, pcur, lcur);
+    // HLL signal speeds travel with the z window like the pressure tensors.
     // The z face below plane z is the face above plane z-1: its HLL weights
     // are carried from one plane to the next.
-    Speeds lcur{};
     HllW wz_prev{};
-    if constexpr (HLL) {
-        const Speeds lprv = m1_speeds(prv.N, prv.Fx, prv.Fy, prv.Fz, A.inv_c, A.c_d);
-        lcur = m1_speeds(cur.N, cur.Fx, cur.Fy, cur.Fz, A.inv_c, A.c_d);
-        wz_prev = hll_weights(lprv.zm, lprv.zp, lcur.zm, lcur.zp, A.c);
-    }
+    if constexpr (HLL) wz_prev = hll_weights(lprv.zm, lprv.zp, lcur.zm, lcur.zp, A.c);
     // Prefetched planes live in two register sets that swap roles every
     // plane: the loop below is unrolled by two so that a value loaded for
     // the next plane is never copied, and its load stays in flight across
@@ -318,7 +327,12 @@ void m1_step_kernel(StepArgs A)
             }
         }
         if (has_halo) {
-            const Press ph = closure(hal.N, hal.Fx, hal.Fy, hal.Fz, A.inv_c);
+            Press ph;
+            SpeedPrep ph2;
+            if constexpr (HLL)
+                closure_and_prep(hal.N, hal.Fx, hal.Fy, hal.Fz, A.inv_c, A.c_d, pscale, ph, ph2);
+            else
+                ph = closure(hal.N, hal.Fx, hal.Fy, hal.Fz, A.inv_c);
             sN[bi][hsy][hsx] = hal.N;
             sFx[bi][hsy][hsx] = hal.Fx;
             sFy[bi][hsy][hsx] = hal.Fy;
@@ -331,7 +345,6 @@ void m1_step_kernel(StepArgs A)
             if constexpr (HLL) {
                 // a halo row is read for its y speeds only, a halo column for
                 // its x speeds (whole wavefronts take the same branch)
-                const SpeedPrep ph2 = m1_speed_prep(hal.N, hal.Fx, hal.Fy, hal.Fz, A.inv_c, A.c_d);
                 float lm, lp;
                 if (tid < 2 * TX) {
                     m1_axis(ph2, ph2.uy, ph2.y2, ph2.x2 + ph2.z2, lm, lp);
@@ -346,9 +359,9 @@ void m1_step_kernel(StepArgs A)
         }
         __syncthreads();
 
-        const Press pnxt = closure(nxt.N, nxt.Fx, nxt.Fy, nxt.Fz, A.inv_c);
+        Press pnxt;
         Speeds lnxt{};
-        if constexpr (HLL) lnxt = m1_speeds(nxt.N, nxt.Fx, nxt.Fy, nxt.Fz, A.inv_c, A.c_d);
+        press_speeds(nxt, pnxt, lnxt);
         const int sy = ly + 1, sx = lx + 1;
         // neighbours: x-1 (L), x+1 (R), y-1 (D), y+1 (U), z-1 (prv), z+1 (nxt)
         const float NL = sN[bi][sy][sx - 1], NR = sN[bi][sy][sx + 1];
@@ -382,8 +395,9 @@ void m1_step_kernel(StepArgs A)
         if constexpr (HLL) {
             // HLL face fluxes G = wl G(UL) + wr G(UR) + wd (UR - UL), the
             // weights from the signal speeds of the two cells of each face;
-            // physical fluxes along d: N -> F_d, F_k -> c^2 P_kd
-            const float c = A.c, C2 = 2.0f * A.half_c2;
+            // physical fluxes along d: N -> F_d, F_k -> c^2 P_kd (the
+            // pressures here already hold c^2 P)
+            const float c = A.c;
             const HllW wxm = hll_weights(lxmL, lxpL, lcur.xm, lcur.xp, c);
             const HllW wxp = hll_weights(lcur.xm, lcur.xp, lxmR, lxpR, c);
             const HllW wym = hll_weights(lymD, lypD, lcur.ym, lcur.yp, c);
@@ -398,24 +412,24 @@ void m1_step_kernel(StepArgs A)
                  (face(wyp, cur.Fy, FyU, cur.N, NU) - face(wym, FyD, cur.Fy, ND, cur.N)) +
                  (face(wzp, cur.Fz, nxt.Fz, cur.N, nxt.N) -
                   face(wzm, prv.Fz, cur.Fz, prv.N, cur.N));
-            dFx = (face(wxp, C2 * pcur.xx, C2 * PxxR, cur.Fx, FxR) -
-                   face(wxm, C2 * PxxL, C2 * pcur.xx, FxL, cur.Fx)) +
-                  (face(wyp, C2 * pcur.xy, C2 * PxyU, cur.Fx, FxU) -
-                   face(wym, C2 * PxyD, C2 * pcur.xy, FxD, cur.Fx)) +
-                  (face(wzp, C2 * pcur.xz, C2 * pnxt.xz, cur.Fx, nxt.Fx) -
-                   face(wzm, C2 * pprv.xz, C2 * pcur.xz, prv.Fx, cur.Fx));
-            dFy = (face(wxp, C2 * pcur.xy, C2 * PxyR, cur.Fy, FyR) -
-                   face(wxm, C2 * PxyL, C2 * pcur.xy, FyL, cur.Fy)) +
-                  (face(wyp, C2 * pcur.yy, C2 * PyyU, cur.Fy, FyU) -
-                   face(wym, C2 * PyyD, C2 * pcur.yy, FyD, cur.Fy)) +
-                  (face(wzp, C2 * pcur.yz, C2 * pnxt.yz, cur.Fy, nxt.Fy) -
-                   face(wzm, C2 * pprv.yz, C2 * pcur.yz, prv.Fy, cur.Fy));
-            dFz = (face(wxp, C2 * pcur.xz, C2 * PxzR, cur.Fz, FzR) -
-                   face(wxm, C2 * PxzL, C2 * pcur.xz, FzL, cur.Fz)) +
-                  (face(wyp, C2 * pcur.yz, C2 * PyzU, cur.Fz, FzU) -
-                   face(wym, C2 * PyzD, C2 * pcur.yz, FzD, cur.Fz)) +
-                  (face(wzp, C2 * pcur.zz, C2 * pnxt.zz, cur.Fz, nxt.Fz) -
-                   face(wzm, C2 * pprv.zz, C2 * pcur.zz, prv.Fz, cur.Fz));
+            dFx = (face(wxp, pcur.xx, PxxR, cur.Fx, FxR) -
+                   face(wxm, PxxL, pcur.xx, FxL, cur.Fx)) +
+                  (face(wyp, pcur.xy, PxyU, cur.Fx, FxU) -
+                   face(wym, PxyD, pcur.xy, FxD, cur.Fx)) +
+                  (face(wzp, pcur.xz, pnxt.xz, cur.Fx, nxt.Fx) -
+                   face(wzm, pprv.xz, pcur.xz, prv.Fx, cur.Fx));
+            dFy = (face(wxp, pcur.xy, PxyR, cur.Fy, FyR) -
+                   face(wxm, PxyL, pcur.xy, FyL, cur.Fy)) +
+                  (face(wyp, pcur.yy, PyyU, cur.Fy, FyU) -
+                   face(wym, PyyD, pcur.yy, FyD, cur.Fy)) +
+                  (face(wzp, pcur.yz, pnxt.yz, cur.Fy, nxt.Fy) -
+                   face(wzm, pprv.yz, pcur.yz, prv.Fy, cur.Fy));
+            dFz = (face(wxp, pcur.xz, PxzR, cur.Fz, FzR) -
+                   face(wxm, PxzL, pcur.xz, FzL, cur.Fz)) +
+                  (face(wyp, pcur.yz, PyzU, cur.Fz, FzU) -
+                   face(wym, PyzD, pcur.yz, FzD, cur.Fz)) +
+                  (face(wzp, pcur.zz, pnxt.zz, cur.Fz, nxt.Fz) -
+                   face(wzm, pprv.zz, pcur.zz, prv.Fz, cur.Fz));
         } else {
             // sum over d of the LF face-flux differences G_{d,+1/2} - G_{d,-1/2}:
             //   N   : 1/2 (F_d[+] - F_d[-]) - c/2 (N[+] + N[-] - 2N)

@@ -168,3 +168,55 @@ def test_surrogate_runs_with_hll():
             assert rhs == pytest.approx(lhs, rel=1e-5)
     for k in outs[0]:
         assert np.array_equal(outs[0][k], outs[1][k]), k
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_free_streaming_beams_with_vanishing_transverse_speeds(axis):
+    # A slab of cells at |F| = cN along one axis (FP32-rounded, so f is 1 to
+    # within rounding) with transverse flux components so small that the
+    # transverse signal speeds are denormal (~1e-40 in units of c), beside
+    # isotropic cells and nearly empty ones (N just above the empty
+    # threshold).  Regression: HLL weights formed in units of c took the
+    # reciprocal of a denormal a+ - a- there and turned the step to NaN.
+    # At f = 1 the flux Jacobian is defective, so the oracle's numerical
+    # eigenvalues are ill-conditioned there (errors of order sqrt(rounding));
+    # parity is checked on the cells whose stencil does not reach the slab,
+    # finiteness, the guards and the photon budget everywhere.
+    shape = (20, 24, 66)
+    rng = np.random.default_rng(40 + axis)
+    N = (1e-3 * rng.random(shape) ** 2 + 1e-8).astype(np.float32)
+    c = rt.C_LIGHT
+    F = np.zeros((3,) + shape, np.float32)
+    beam = np.zeros(shape, bool)
+    beam[:, 8:16, :] = True
+    F[axis][beam] = (np.float32(c) * N[beam]).astype(np.float32)
+    for t in range(3):
+        if t != axis:
+            F[t][beam] = (1e-40 * c * N[beam].astype(np.float64)
+                          * rng.choice([-1.0, 1.0], beam.sum())).astype(np.float32)
+    tiny = (rng.random(shape) < 0.05) & ~beam
+    N[tiny] = np.float32(1.5e-30)
+    F[axis][tiny] = (0.5 * c * N[tiny].astype(np.float64)).astype(np.float32)
+    st = dict(N=N, Fx=F[0], Fy=F[1], Fz=F[2],
+              xHI=np.full(shape, 0.5, np.float32), T=np.full(shape, 1e4, np.float32),
+              nH=np.full(shape, 1e-3, np.float32))
+    print(f"HLL vanishing transverse speeds, beams along axis {axis}", flush=True)
+    # transport alone (the chemistry would only add a stiff absorber here)
+    g, o, red, og = one_step_pair(st, shape, DX, DT, 1, (rt.BC_PERIODIC,) * 6, rt.CHEM_OFF,
+                                  flux=HLL)
+    assert red["n_nonfinite"] == 0
+    for k in ("N", "Fx", "Fy", "Fz", "xHI", "T"):
+        assert np.all(np.isfinite(g[k])), k
+    assert np.all(g["N"] >= 0.0)
+    fl = np.sqrt(g["Fx"].astype(np.float64) ** 2 + g["Fy"].astype(np.float64) ** 2
+                 + g["Fz"].astype(np.float64) ** 2)
+    assert np.all(fl <= c * g["N"].astype(np.float64) * (1 + 1e-6))
+    lhs = red["photons_initial"] + red["photons_emitted"] + red["photons_floor"]
+    rhs = red["photons_stored"] + red["photons_absorbed"] + red["photons_escaped"]
+    assert rhs == pytest.approx(lhs, rel=1e-5)
+    near = beam.copy()
+    for ax in range(3):
+        near |= np.roll(beam, 1, ax) | np.roll(beam, -1, ax)
+    far = ~near
+    gf = {k: np.where(far, g[k], o[k]) for k in o}
+    assert_parity(errors(gf, o), what=f"HLL beams axis {axis}, cells off the slab")

@@ -84,47 +84,6 @@ struct SpeedPrep {
     float ux, uy, uz, x2, y2, z2, inv_f2, pref, Sm1, Q;
 };
 
-__device__ __forceinline__ SpeedPrep m1_speed_prep(float N, float Fx, float Fy, float Fz,
-                                                   float inv_c, double c_d)
-{
-    SpeedPrep p{};
-    p.iso = true;
-    if (!(N > N_TINY)) return p;
-    const float q = inv_c * frcp(N);
-    p.ux = Fx * q;
-    p.uy = Fy * q;
-    p.uz = Fz * q;
-    p.x2 = p.ux * p.ux;
-    p.y2 = p.uy * p.uy;
-    p.z2 = p.uz * p.uz;
-    const float f2 = p.x2 + p.y2 + p.z2;
-    if (!(f2 > 1e-20f)) return p;
-    p.iso = false;
-    // 1 - f^2 = ((cN)^2 - |F|^2) q^2 with q = 1/(cN): the difference (it
-    // cancels near free streaming) and the product (q^2 leaves the FP32
-    // range for N just above N_TINY) in FP64
-    const double cn = double(N) * c_d;
-    const double diff =
-        cn * cn - (double(Fx) * double(Fx) + double(Fy) * double(Fy) + double(Fz) * double(Fz));
-    const double qd = double(q);
-    const float g2 = diff > 0.0 ? float(diff * (qd * qd)) : 0.0f;
-    const float fs = 1.0f - g2;
-    const float S = fsqrt(1.0f + 3.0f * g2);
-    const float Sp1 = S + 1.0f;
-    const float D = 5.0f + 2.0f * S;
-    const float D2 = D * D;
-    // one reciprocal for 1/S, 1/(S+1) and 1/D^2
-    const float R = frcp(S * Sp1 * D2);
-    const float inv_S = R * Sp1 * D2;
-    const float inv_Sp1 = R * S * D2;
-    const float inv_D2 = R * S * Sp1;
-    p.Sm1 = 3.0f * g2 * inv_Sp1;
-    p.Q = (8.0f * D + 6.0f * (3.0f + 4.0f * fs) * inv_S) * inv_D2;   // chi'/f
-    p.pref = (8.0f / 3.0f) * p.Sm1 * inv_S * inv_S;
-    p.inv_f2 = frcp(f2);
-    return p;
-}
-
 // The extreme eigenvalues along one axis: ud the reduced flux along it, a2
 // its square, o2 the sum of the other two squares.
 __device__ __forceinline__ void m1_axis(const SpeedPrep &p, float ud, float a2, float o2,
@@ -141,9 +100,11 @@ __device__ __forceinline__ void m1_axis(const SpeedPrep &p, float ud, float a2, 
     lp = 0.5f * (B + r);
 }
 
-// The HLL form needs both the pressure (times ns) and the speed inputs of
-// a cell: one pass shares 1/N, the reduced flux, 1/f^2 and sqrt(4 - 3 f^2)
-// (= sqrt(1 + 3 (1 - f^2)), the speeds' S) between them.
+// The HLL form needs both the pressure (times ns) and the parts of the
+// speed formula shared by the three axes: one pass shares 1/N, the reduced
+// flux, 1/f^2 and sqrt(4 - 3 f^2) (= sqrt(1 + 3 (1 - f^2)), the speeds' S)
+// between them.  S, 1/S, 1/(S+1) and 1/D^2 (D = 5 + 2S) come from one
+// reciprocal.
 __device__ __forceinline__ void closure_and_prep(float N, float Fx, float Fy, float Fz,
                                                  float inv_c, double c_d, float ns, Press &P,
                                                  SpeedPrep &sp)
@@ -205,17 +166,6 @@ __device__ __forceinline__ void closure_and_prep(float N, float Fx, float Fy, fl
 
 __device__ __forceinline__ Speeds m1_axes(const SpeedPrep &p)
 {
-    Speeds s;
-    m1_axis(p, p.ux, p.x2, p.y2 + p.z2, s.xm, s.xp);
-    m1_axis(p, p.uy, p.y2, p.x2 + p.z2, s.ym, s.yp);
-    m1_axis(p, p.uz, p.z2, p.x2 + p.y2, s.zm, s.zp);
-    return s;
-}
-
-__device__ __forceinline__ Speeds m1_speeds(float N, float Fx, float Fy, float Fz, float inv_c,
-                                            double c_d)
-{
-    const SpeedPrep p = m1_speed_prep(N, Fx, Fy, Fz, inv_c, c_d);
     Speeds s;
     m1_axis(p, p.ux, p.x2, p.y2 + p.z2, s.xm, s.xp);
     m1_axis(p, p.uy, p.y2, p.x2 + p.z2, s.ym, s.yp);

@@ -150,7 +150,8 @@ __device__ __forceinline__ void closure_and_prep(float N, float Fx, float Fy, fl
         inv_f2 = frcp(f2);
         sp.inv_f2 = inv_f2;
     }
-    // Levermore chi from f^2 = 1 - g2 (clamped to 1) and the same S
+    // Levermore chi with f^2 clamped to 1 and the speeds' S in place of
+    // sqrt(4 - 3 f^2)
     const float f2c = rmin(f2, 1.0f);
     const float chi = (3.0f + 4.0f * f2c) * frcp(5.0f + 2.0f * S);
     const float iso = 0.5f * (1.0f - chi) * Ns;
